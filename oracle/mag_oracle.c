@@ -1,0 +1,291 @@
+/*
+ * mag_oracle.c -- CPU reference for the weighting equation of metric magnitude.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the parity oracle: a plain, slow,
+ * obviously correct FP64 implementation of what the HIP library computes.
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * load it.  It shares no code, header, table or constant with the HIP path.
+ *
+ * Arithmetic is written so that every operation rounds as written: build
+ * with -ffp-contract=off and without -ffast-math.  OpenMP only distributes
+ * independent rows; it never reorders a sum.
+ *
+ * What it computes (paper, Section 2 "Weightings, magnitude, and diversity"):
+ *   d_jk = ||x_j - x_k||_2 over points x_j in R^m              (Section 2)
+ *   Z    = exp[-t d], componentwise, t in (0, inf)             (Section 2)
+ *   w    : Z w = 1  (eq. weighting); unique since Z is positive definite
+ *          for Euclidean d                                     (Section 2)
+ *   Mag  = 1^T w                                               (Section 2)
+ *   bound t_+ <= log(n-1) / min_{j != k} d_jk                  (Sections 1, 2)
+ * and, derived from eq. weighting by differentiating Z(t, X) w = 1:
+ *   dw        = -Z^{-1} (dZ) w
+ *   dL/dt     = lambda^T (D o Z) w,      lambda = Z^{-1} (gM 1 + gw)
+ *   dL/dx_j   = t sum_{k != j} (lambda_j w_k + lambda_k w_j) Z_jk (x_j - x_k) / d_jk
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Euclidean distance between rows j and k of the row-major n x m array X.
+ * Exact coordinate differences, summed over l in ascending order. */
+static double dist(const double *X, int m, int64_t j, int64_t k)
+{
+    double s = 0.0;
+    for (int l = 0; l < m; ++l) {
+        double e = X[j * m + l] - X[k * m + l];
+        s = s + e * e;
+    }
+    return sqrt(s);
+}
+
+/* Z_jk = exp(-t d_jk); Z_jj = exp(0) = 1. */
+static double zentry(const double *X, int m, double t, int64_t j, int64_t k)
+{
+    if (j == k)
+        return 1.0;
+    return exp(-(t * dist(X, m, j, k)));
+}
+
+double orc_dist(const double *X, int64_t n, int m, int64_t j, int64_t k)
+{
+    (void)n;
+    return dist(X, m, j, k);
+}
+
+/* Full n x n row-major distance matrix. */
+void orc_distance_matrix(const double *X, int64_t n, int m, double *D)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = 0; k < n; ++k)
+            D[j * n + k] = (j == k) ? 0.0 : dist(X, m, j, k);
+}
+
+/* Full n x n row-major similarity matrix Z = exp[-t d]. */
+void orc_zmatrix(const double *X, int64_t n, int m, double t, double *Z)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = 0; k < n; ++k)
+            Z[j * n + k] = zentry(X, m, t, j, k);
+}
+
+/* min_{j != k} d_jk by brute force over all pairs (bound on t_+). */
+double orc_dmin(const double *X, int64_t n, int m)
+{
+    double best = INFINITY;
+#pragma omp parallel for schedule(dynamic, 16) reduction(min : best)
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = j + 1; k < n; ++k) {
+            double d = dist(X, m, j, k);
+            if (d < best)
+                best = d;
+        }
+    return best;
+}
+
+/* Cholesky factorisation A = L L^T of a symmetric positive definite matrix,
+ * computed column by column (the gaxpy / Cholesky-Crout form):
+ *   L_jj = sqrt(A_jj - sum_{k<j} L_jk^2)
+ *   L_ij = (A_ij - sum_{k<j} L_ik L_jk) / L_jj,   i > j.
+ * A is n x n row-major; L overwrites the lower triangle (the strict upper
+ * triangle is left untouched and never read).  Returns 0, or j+1 when the
+ * j-th pivot is not positive (A not numerically positive definite). */
+int orc_cholesky(double *A, int64_t n)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        const double *Lj = A + j * n;
+        double s = A[j * n + j];
+        for (int64_t k = 0; k < j; ++k)
+            s = s - Lj[k] * Lj[k];
+        if (!(s > 0.0))
+            return (int)(j + 1);
+        double ljj = sqrt(s);
+        A[j * n + j] = ljj;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = j + 1; i < n; ++i) {
+            const double *Li = A + i * n;
+            double a = Li[j];
+            for (int64_t k = 0; k < j; ++k)
+                a = a - Li[k] * Lj[k];
+            A[i * n + j] = a / ljj;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Solve L L^T x = b with the lower factor from orc_cholesky.
+ * Forward substitution L y = b row by row, then back substitution
+ * L^T x = y column by column (row i of L scatters x_i into y_k, k < i). */
+void orc_chol_solve(const double *L, int64_t n, const double *b, double *x)
+{
+    double *y = (double *)malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        const double *Li = L + i * n;
+        double a = b[i];
+        for (int64_t k = 0; k < i; ++k)
+            a = a - Li[k] * y[k];
+        y[i] = a / Li[i];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        const double *Li = L + i * n;
+        double xi = y[i] / Li[i];
+        x[i] = xi;
+        for (int64_t k = 0; k < i; ++k)
+            y[k] = y[k] - Li[k] * xi;
+    }
+    free(y);
+}
+
+/* Error-free transformations (Knuth TwoSum; TwoProduct through fma). */
+static void two_sum(double a, double b, double *s, double *e)
+{
+    double x = a + b;
+    double z = x - a;
+    *e = (a - (x - z)) + (b - z);
+    *s = x;
+}
+
+static void two_prod(double a, double b, double *p, double *e)
+{
+    double x = a * b;
+    *e = fma(a, b, -x);
+    *p = x;
+}
+
+/* Residual r_j = 1 - sum_k Z_jk w_k with Z regenerated from X, accumulated
+ * by the compensated dot product Dot2 of Ogita, Rump and Oishi (2005): the
+ * result is as accurate as if computed in twice the working precision and
+ * then rounded.  rows == NULL means all n rows; otherwise r[i] is the
+ * residual of row rows[i]. */
+void orc_residual(const double *X, int64_t n, int m, double t, const double *w,
+                  const int64_t *rows, int64_t nrows, double *r)
+{
+    int64_t cnt = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < cnt; ++i) {
+        int64_t j = rows ? rows[i] : i;
+        double s = 1.0, c = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            double p, ep, q;
+            two_prod(zentry(X, m, t, j, k), -w[k], &p, &ep);
+            two_sum(s, p, &s, &q);
+            c = c + (q + ep);
+        }
+        r[i] = s + c;
+    }
+}
+
+/* Plain matrix-vector products with Z regenerated from X, ascending k. */
+void orc_zmatvec(const double *X, int64_t n, int m, double t, const double *v, double *y)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int64_t k = 0; k < n; ++k)
+            s = s + zentry(X, m, t, j, k) * v[k];
+        y[j] = s;
+    }
+}
+
+/* y = (D o Z) v with (D o Z)_jk = d_jk exp(-t d_jk) (= -dZ_jk/dt). */
+void orc_dzmatvec(const double *X, int64_t n, int m, double t, const double *v, double *y)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == j)
+                continue;
+            double d = dist(X, m, j, k);
+            s = s + d * exp(-(t * d)) * v[k];
+        }
+        y[j] = s;
+    }
+}
+
+/* dL/dx_j = t sum_{k != j} (lambda_j w_k + lambda_k w_j) Z_jk (x_j - x_k) / d_jk,
+ * written into the row-major n x m array dX. */
+void orc_grad_x(const double *X, int64_t n, int m, double t, const double *lam,
+                const double *w, double *dX)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int l = 0; l < m; ++l)
+            dX[j * m + l] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == j)
+                continue;
+            double d = dist(X, m, j, k);
+            double coef = t * (lam[j] * w[k] + lam[k] * w[j]) * exp(-(t * d)) / d;
+            for (int l = 0; l < m; ++l)
+                dX[j * m + l] = dX[j * m + l] + coef * (X[j * m + l] - X[k * m + l]);
+        }
+    }
+}
+
+/* Neumaier's compensated sum (for Mag = 1^T w). */
+double orc_sum(const double *v, int64_t n)
+{
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double x = v[i];
+        double u = s + x;
+        if (fabs(s) >= fabs(x))
+            c = c + ((s - u) + x);
+        else
+            c = c + ((x - u) + s);
+        s = u;
+    }
+    return s + c;
+}
+
+/* Weighting by a dense FP64 solve of Z w = 1 (eq. weighting):
+ *   1. Z from X (work, n x n row-major), 2. Z = L L^T in place,
+ *   3. w_plain = L^{-T} L^{-1} 1,
+ *   4. `refine` steps of w <- w + L^{-T} L^{-1} r with r = 1 - Z w from
+ *      orc_residual (Dot2), so that w carries no more than unit-roundoff
+ *      error for well-conditioned Z.
+ * On return `work` holds L (lower triangle).  w_plain may be NULL.
+ * Returns 0, or the 1-based index of the failing pivot. */
+int orc_weighting(const double *X, int64_t n, int m, double t, int refine,
+                  double *w_plain, double *w, double *work)
+{
+    orc_zmatrix(X, n, m, t, work);
+    int st = orc_cholesky(work, n);
+    if (st != ORC_OK)
+        return st;
+    double *ones = (double *)malloc((size_t)n * sizeof(double));
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *dw = (double *)malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        ones[i] = 1.0;
+    orc_chol_solve(work, n, ones, w);
+    if (w_plain)
+        memcpy(w_plain, w, (size_t)n * sizeof(double));
+    for (int it = 0; it < refine; ++it) {
+        orc_residual(X, n, m, t, w, NULL, 0, r);
+        orc_chol_solve(work, n, r, dw);
+        for (int64_t i = 0; i < n; ++i)
+            w[i] = w[i] + dw[i];
+    }
+    free(ones);
+    free(r);
+    free(dw);
+    return ORC_OK;
+}
