@@ -1,0 +1,159 @@
+/*
+ * mag.h -- C ABI of libmag: the weighting equation of metric magnitude on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Huntsman et al., "Scalably computing metric magnitude", Section 2):
+ * given points x_1..x_n in R^m and a scale t in (0, inf),
+ *     d_jk = ||x_j - x_k||_2,   Z = exp[-t d] (componentwise),
+ *     the weighting w solves Z w = 1              (eq. weighting),
+ *     the magnitude is Mag = 1^T w.
+ * Z is symmetric positive definite for distinct Euclidean points, so w is
+ * unique.  The cutoff t_+ is the least t with w >= 0 (Section 2, cutoff
+ * paragraph), bounded above by log(n-1) / min_{j != k} d_jk.
+ *
+ * Conventions for every entry point:
+ *   - Arrays named X, w, dX and the packed batch arrays are DEVICE pointers
+ *     on the context's device; scalars and arrays marked HOST are host
+ *     memory.  X is row-major n x m FP64 (point j at X[j*m .. j*m+m-1]).
+ *   - The caller owns every array passed in; the library never frees or
+ *     retains a caller pointer after a call returns.
+ *   - Work is enqueued on the context's stream (mag_set_stream); calls
+ *     block only to deliver host outputs and status.  A context is
+ *     single-stream and not thread-safe.
+ *   - Every function returns MAG_OK (0) or a negative error code; nothing
+ *     throws across the ABI.  mag_strerror names a code.
+ */
+#ifndef MAG_H
+#define MAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define MAG_OK        0
+#define MAG_EINVAL   (-1)  /* n < 1, m < 1, t <= 0 or non-finite, NULL required pointer */
+#define MAG_ENOTPD   (-2)  /* Z not positive definite: duplicate points (d_jk = 0, j != k),
+                              or breakdown of the FP64 Cholesky                          */
+#define MAG_ENOCONV  (-3)  /* refinement did not reach tol; w holds the best iterate      */
+#define MAG_ENOMEM   (-4)  /* workspace does not fit in device memory                     */
+#define MAG_EHIP     (-5)  /* HIP runtime or library error                                */
+#define MAG_EINTERNAL (-6) /* internal consistency failure                                */
+
+const char *mag_strerror(int code);
+
+/* ---- context ------------------------------------------------------------ */
+typedef struct mag_ctx mag_ctx;
+
+/* Create a context on HIP device `device`.  It owns all scratch memory
+ * (grown on demand, reused across calls, released by mag_destroy). */
+int mag_create(mag_ctx **ctx, int device);
+void mag_destroy(mag_ctx *ctx);
+/* Enqueue subsequent work on `hip_stream` (a hipStream_t; NULL = the
+ * context's own stream). */
+int mag_set_stream(mag_ctx *ctx, void *hip_stream);
+
+/* ---- options and diagnostics --------------------------------------------- */
+enum {
+    MAG_AUTO = 0,        /* MAG_FP32_IR                                                  */
+    MAG_FP64_DENSE = 1,  /* FP64 Z in HBM + rocSOLVER dpotrf/dpotrs (dense comparator)   */
+    MAG_FP32_IR = 2,     /* FP32 MFMA Cholesky + FP64 GMRES iterative refinement         */
+    MAG_HODLR = 3        /* HODLR preconditioner + FP64 GMRES (largest sizes)            */
+};
+
+typedef struct {
+    int32_t solver;        /* MAG_AUTO ...                                                */
+    int32_t max_outer;     /* refinement steps (residual evaluations), default 10         */
+    int32_t gmres_restart; /* Krylov dimension per refinement step, default 30            */
+    int32_t max_gmres;     /* total inner iterations over the whole solve, default 200    */
+    double tol;            /* target ||1 - Z w||_inf, default 1e-12                       */
+    double inner_tol;      /* relative reduction asked of each inner GMRES, default 1e-8  */
+    int32_t leaf;          /* HODLR leaf size, default 256                                */
+    int32_t max_rank;      /* HODLR off-diagonal rank, default 64                         */
+    int32_t oversample;    /* HODLR sampling oversampling, default 16                     */
+    int32_t profile;       /* 1: time phases with HIP events (adds a sync per phase)      */
+    uint64_t seed;         /* HODLR sampling seed                                          */
+} mag_opts;
+
+/* Fill *opts with the defaults above. */
+void mag_opts_default(mag_opts *opts);
+
+typedef struct {
+    int32_t status;        /* return code of the call                                     */
+    int32_t outer_iters;   /* residual evaluations                                        */
+    int32_t gmres_iters;   /* inner GMRES iterations                                      */
+    int32_t shifted;       /* 1 if the FP32 factor was taken of Z + shift*I after breakdown */
+    double shift;          /* the diagonal shift used (0 if none)                          */
+    double resid_inf;      /* ||1 - Z w||_inf as last evaluated on the device (FP64)       */
+    double magnitude;      /* 1^T w                                                        */
+    double min_w;          /* min_j w_j                                                    */
+    int64_t argmin_w;      /* argmin_j w_j                                                 */
+    double ms_tilegen;     /* phase times (profile = 1 only)                              */
+    double ms_factor;
+    double ms_refine;
+    double ms_total;
+    double ms_update;      /* summed device time of the trailing-update kernel launches   */
+    double flop_update;    /* algorithmic flops of those launches                         */
+    int32_t n_update;      /* number of trailing-update launches                          */
+    int32_t pad_;
+} mag_info;
+
+/* ---- the weighting (eq. weighting) ---------------------------------------- */
+
+/* Solve Z w = 1 for the n points X (device, n x m row-major FP64) at scale t;
+ * write w (device, n FP64).  opts may be NULL (defaults); info may be NULL.
+ * MAG_FP32_IR: w meets ||1 - Z w||_inf <= tol with Z evaluated in FP64, or
+ * MAG_ENOCONV is returned with the best iterate in w.  Duplicate points give
+ * MAG_ENOTPD.  n = 1 gives w = 1. */
+int mag_weighting(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                  double *w, const mag_opts *opts, mag_info *info);
+
+/* As mag_weighting, and return Mag = 1^T w in *M (HOST).  w may be NULL. */
+int mag_magnitude(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                  double *M, double *w, const mag_opts *opts, mag_info *info);
+
+/* min_{j != k} ||x_j - x_k|| by brute force over all pairs into *d_min (HOST);
+ * the bound on the cutoff is log(n-1)/d_min (Sections 1 and 2).  n >= 2. */
+int mag_dmin(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double *d_min);
+
+
+/* ---- kernel-level entry points --------------------------------------------
+ * The steps of the FP32_IR path exposed one by one, for parity tests and
+ * profiling.  npad = mag_padded_size(n) = n rounded up to a multiple of 256.
+ * The FP32 factor layout is column-major with leading dimension npad; rows
+ * and columns >= n hold an identity padding. */
+
+/* npad for n points (0 for n < 1). */
+int64_t mag_padded_size(int64_t n);
+
+/* y = Z v in FP64 with Z regenerated from X (matrix-free).  v, y: device, n. */
+int mag_zmatvec(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                const double *v, double *y);
+
+/* r = 1 - Z w in FP64 (device, n) and *rinf = ||r||_inf (HOST, may be NULL). */
+int mag_residual(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                 const double *w, double *r, double *rinf);
+
+/* FP32 Z (tile generator output) into A: device, npad x npad column-major;
+ * only the lower triangle and the 128 x 128 diagonal tiles are written. */
+int mag_tile32(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, float *A);
+
+/* FP32 Cholesky factor of Z + shift*I into L (device, npad x npad, lower
+ * triangle valid) and the inverses of its 128 x 128 diagonal blocks into dinv
+ * (device, npad/128 blocks of 128 x 128 column-major).  *breakdown (HOST, may
+ * be NULL) receives 0, or 1 + the index of the first non-positive pivot. */
+int mag_factor32(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                 double shift, float *L, float *dinv, int32_t *breakdown);
+
+/* z = (L L^T)^{-1} r with the factor from mag_factor32, FP64 arithmetic;
+ * r, z: device, n. */
+int mag_prec_apply(mag_ctx *ctx, const float *L, const float *dinv, int64_t n,
+                   const double *r, double *z);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAG_H */

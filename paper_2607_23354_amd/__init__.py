@@ -1,0 +1,215 @@
+"""libmag: the weighting equation of metric magnitude on an MI355X (gfx950).
+
+Python binding of the C ABI in ``include/mag.h``.  Tensors are PyTorch CUDA
+(HIP) tensors; PyTorch supplies device memory and the stream, and every step
+of the computation runs in the HIP library ``libmag.so``.
+
+Problem (Section 2 of the paper): for points x_1..x_n in R^m and t > 0,
+Z = exp[-t d] with d the Euclidean distance matrix; the weighting w solves
+Z w = 1 and the magnitude is 1^T w.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import MagError, MagInfo, MagOpts  # noqa: F401
+
+__all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "tile32",
+           "factor32", "prec_apply", "padded_size", "MagError", "SOLVERS"]
+
+SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
+           "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR}
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _points(X: torch.Tensor) -> torch.Tensor:
+    if X.dim() == 1:
+        X = X[:, None]
+    if X.dim() != 2 or X.dtype != torch.float64 or not X.is_cuda:
+        raise ValueError("X must be a 2-D float64 CUDA tensor (n, m)")
+    return X.contiguous()
+
+
+class Context:
+    """Owns a libmag context (device scratch memory) on one device."""
+
+    def __init__(self, device: int | None = None):
+        self.lib = _lib.load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.mag_create(ctypes.byref(h), self.device), "mag_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.mag_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _lib.check(self.lib.mag_set_stream(self.handle, ctypes.c_void_p(s)), "mag_set_stream")
+
+
+_default: dict[int, Context] = {}
+
+
+def _ctx(ctx: Context | None, X: torch.Tensor) -> Context:
+    if ctx is not None:
+        ctx._sync_stream()
+        return ctx
+    dev = X.device.index if X.device.index is not None else torch.cuda.current_device()
+    c = _default.get(dev)
+    if c is None:
+        c = _default[dev] = Context(dev)
+    c._sync_stream()
+    return c
+
+
+def make_opts(solver: str = "auto", tol: float = 1e-12, max_outer: int | None = None,
+              gmres_restart: int | None = None, max_gmres: int | None = None,
+              inner_tol: float | None = None, profile: bool = False, leaf: int | None = None,
+              max_rank: int | None = None, oversample: int | None = None,
+              seed: int | None = None) -> MagOpts:
+    o = MagOpts()
+    _lib.load().mag_opts_default(ctypes.byref(o))
+    o.solver = SOLVERS[solver]
+    o.tol = tol
+    if max_outer is not None:
+        o.max_outer = max_outer
+    if gmres_restart is not None:
+        o.gmres_restart = gmres_restart
+    if max_gmres is not None:
+        o.max_gmres = max_gmres
+    if inner_tol is not None:
+        o.inner_tol = inner_tol
+    if leaf is not None:
+        o.leaf = leaf
+    if max_rank is not None:
+        o.max_rank = max_rank
+    if oversample is not None:
+        o.oversample = oversample
+    if seed is not None:
+        o.seed = seed
+    o.profile = 1 if profile else 0
+    return o
+
+
+@dataclass
+class Result:
+    w: torch.Tensor
+    info: dict
+
+
+def weighting(X: torch.Tensor, t: float, *, ctx: Context | None = None, out: torch.Tensor | None = None,
+              raise_on_noconv: bool = True, **opts) -> Result:
+    """Solve Z w = 1 (eq. weighting) on the device; returns w and the info
+    record (iterations, residual, magnitude, min w, phase times)."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    w = out if out is not None else torch.empty(n, dtype=torch.float64, device=X.device)
+    o = make_opts(**opts)
+    info = MagInfo()
+    rc = c.lib.mag_weighting(c.handle, _ptr(X), n, m, float(t), _ptr(w), ctypes.byref(o), ctypes.byref(info))
+    if rc != _lib.MAG_OK and not (rc == _lib.MAG_ENOCONV and not raise_on_noconv):
+        raise MagError(rc, "mag_weighting")
+    return Result(w, info.as_dict())
+
+
+def magnitude(X: torch.Tensor, t: float, *, ctx: Context | None = None, **opts) -> float:
+    """Mag = 1^T w (Section 2)."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    o = make_opts(**opts)
+    M = ctypes.c_double()
+    _lib.check(c.lib.mag_magnitude(c.handle, _ptr(X), n, m, float(t), ctypes.byref(M), None,
+                                   ctypes.byref(o), None), "mag_magnitude")
+    return M.value
+
+
+def dmin(X: torch.Tensor, *, ctx: Context | None = None) -> float:
+    """min_{j != k} ||x_j - x_k||, brute force on the device."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    d = ctypes.c_double()
+    _lib.check(c.lib.mag_dmin(c.handle, _ptr(X), n, m, ctypes.byref(d)), "mag_dmin")
+    return d.value
+
+
+def padded_size(n: int) -> int:
+    return int(_lib.load().mag_padded_size(n))
+
+
+def zmatvec(X: torch.Tensor, t: float, v: torch.Tensor, *, ctx: Context | None = None) -> torch.Tensor:
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    v = v.contiguous()
+    y = torch.empty(n, dtype=torch.float64, device=X.device)
+    _lib.check(c.lib.mag_zmatvec(c.handle, _ptr(X), n, m, float(t), _ptr(v), _ptr(y)), "mag_zmatvec")
+    return y
+
+
+def residual(X: torch.Tensor, t: float, w: torch.Tensor, *, ctx: Context | None = None):
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    w = w.contiguous()
+    r = torch.empty(n, dtype=torch.float64, device=X.device)
+    rinf = ctypes.c_double()
+    _lib.check(c.lib.mag_residual(c.handle, _ptr(X), n, m, float(t), _ptr(w), _ptr(r), ctypes.byref(rinf)),
+               "mag_residual")
+    return r, rinf.value
+
+
+def tile32(X: torch.Tensor, t: float, *, ctx: Context | None = None) -> torch.Tensor:
+    """FP32 Z as the tile generator writes it (npad x npad, column-major:
+    the returned tensor A satisfies A[j, i] = Z_ij)."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    npad = padded_size(n)
+    A = torch.zeros((npad, npad), dtype=torch.float32, device=X.device)
+    _lib.check(c.lib.mag_tile32(c.handle, _ptr(X), n, m, float(t), _ptr(A)), "mag_tile32")
+    return A
+
+
+def factor32(X: torch.Tensor, t: float, shift: float = 0.0, *, ctx: Context | None = None):
+    """FP32 Cholesky factor (column-major npad x npad buffer, lower triangle
+    valid) and the inverses of its 128-diagonal blocks."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    npad = padded_size(n)
+    L = torch.zeros((npad, npad), dtype=torch.float32, device=X.device)
+    dinv = torch.zeros((npad // 128, 128, 128), dtype=torch.float32, device=X.device)
+    bd = ctypes.c_int32()
+    _lib.check(c.lib.mag_factor32(c.handle, _ptr(X), n, m, float(t), float(shift), _ptr(L), _ptr(dinv),
+                                  ctypes.byref(bd)), "mag_factor32")
+    return L, dinv, int(bd.value)
+
+
+def prec_apply(L: torch.Tensor, dinv: torch.Tensor, n: int, r: torch.Tensor, *,
+               ctx: Context | None = None) -> torch.Tensor:
+    c = _ctx(ctx, r)
+    r = r.contiguous()
+    z = torch.empty(n, dtype=torch.float64, device=r.device)
+    _lib.check(c.lib.mag_prec_apply(c.handle, _ptr(L), _ptr(dinv), n, _ptr(r), _ptr(z)), "mag_prec_apply")
+    return z

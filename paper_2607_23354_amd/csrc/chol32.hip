@@ -1,0 +1,69 @@
+// chol32.hip -- blocked right-looking FP32 Cholesky of Z on MFMA.
+//
+// Z is symmetric positive definite for distinct Euclidean points (Sections 2
+// and 3.2), so Z = L L^T exists; this factor is computed in FP32 and used as
+// the preconditioner of the FP64 refinement.  For each panel of nb = 256
+// columns starting at k (two 128-column sub-panels s):
+//   1. potrf128   factor of the 128 x 128 diagonal block and its inverse
+//   2. trsm       rows below:  L21 = A21 * inv(L11)^T     (MFMA, in place)
+//   3. (s = 0)    update the second sub-panel's columns with the first
+//   4. syrk       trailing update  A22 -= L21 L21^T, K = 256, lower tiles only
+// The panel inverses of the diagonal 128-blocks are kept (dinv) for the
+// preconditioner's triangular solves.
+#include "internal.hpp"
+
+#include <vector>
+
+namespace mag {
+
+
+// Factor the padded npad x npad FP32 matrix A (column-major, ld = npad) in place.
+// update_events (optional) records an event pair around every trailing update.
+void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv, int *status,
+                   FactorTimer *timer)
+{
+    const int64_t T = kTile;
+    for (int64_t k = 0; k < npad; k += kPanel) {
+        for (int sub = 0; sub < kPanel / T; ++sub) {
+            const int64_t kk = k + sub * T;
+            float *Linv = dinv + (kk / T) * T * T;
+            launch_potrf128(s, A, npad, kk, Linv, status);
+            const int64_t below = npad - kk - T;
+            if (below > 0) {
+                float *A21 = A + kk * npad + kk + T;
+                launch_gemm_nt(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSet, false);
+            }
+            if (sub + 1 < kPanel / T && below > 0) {
+                // update the next sub-panel's columns (rows kk+T ..) with this sub-panel
+                float *C = A + (kk + T) * npad + kk + T;
+                const float *P = A + kk * npad + kk + T;
+                launch_gemm_nt(s, C, npad, P, npad, P, npad, below, T, T, kGemmSub, false);
+            }
+        }
+        const int64_t trail = npad - k - kPanel;
+        if (trail > 0) {
+            float *C = A + (k + kPanel) * npad + k + kPanel;
+            const float *P = A + k * npad + k + kPanel;
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (timer) {
+                if (timer->used + 2 > timer->ev.size()) {
+                    for (int q = 0; q < 64; ++q) {
+                        hipEvent_t e;
+                        hipEventCreate(&e);
+                        timer->ev.push_back(e);
+                    }
+                }
+                e0 = timer->ev[timer->used++];
+                e1 = timer->ev[timer->used++];
+                // algorithmic flops of the trailing update restricted to the true n
+                const int64_t nt = n - (k + kPanel);
+                timer->flops.push_back(nt > 0 ? (double)kPanel * (double)nt * (double)(nt + 1) : 0.0);
+                hipEventRecord(e0, s);
+            }
+            launch_gemm_nt(s, C, npad, P, npad, P, npad, trail, trail, kPanel, kGemmSub, true);
+            if (timer) hipEventRecord(e1, s);
+        }
+    }
+}
+
+}  // namespace mag

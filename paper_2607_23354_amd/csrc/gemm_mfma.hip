@@ -1,0 +1,160 @@
+// gemm_mfma.hip -- FP32 MFMA kernel for the Cholesky's dense contractions.
+//
+//   C (M x N)  <-  C - P Q^T      (kGemmSub: trailing SYRK/GEMM updates)
+//   C (M x N)  <-  P Q^T          (kGemmSet: panel TRSM against an explicit
+//                                   inverse of the diagonal block)
+//
+// All operands are column-major FP32: P(i, p) = P[p * ldp + i],
+// Q(j, p) = Q[p * ldq + j], C(i, j) = C[j * ldc + i].  Accumulation is FP32
+// on v_mfma_f32_32x32x2_f32.
+//
+// Workgroup tile 128 x 128, 4 waves in a 2 x 2 arrangement, each wave a
+// 64 x 64 sub-tile held as 2 x 2 MFMA 32 x 32 accumulators (64 registers).
+// The MFMA's A operand is taken from Q and its B operand from P, so an
+// accumulator lane maps to a row i of C: each accumulator register is a
+// 128-byte contiguous column segment for a half-wave, which makes both the
+// initial load of C and the final store coalesced.
+// K is staged through LDS in chunks of 16, double-buffered, one barrier per
+// stage.
+#include "internal.hpp"
+
+namespace mag {
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr int BT = 128;
+constexpr int KC = 16;
+constexpr int NT = 256;
+
+__device__ inline void tri_index(int64_t idx, int64_t &ti, int64_t &tj)
+{
+    int64_t r = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > idx) --r;
+    while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+    ti = r;
+    tj = idx - r * (r + 1) / 2;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(NT, 2)
+k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
+          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, int lower_only)
+{
+    __shared__ float Ps[2][KC][BT];
+    __shared__ float Qs[2][KC][BT];
+
+    int64_t ti, tj;
+    if (lower_only) {
+        tri_index(blockIdx.x, ti, tj);
+    } else {
+        ti = blockIdx.x % tilesM;
+        tj = blockIdx.x / tilesM;
+    }
+    const int64_t i0 = ti * BT, j0 = tj * BT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wi = (wave & 1) * 64;
+    const int wj = (wave >> 1) * 64;
+    const int l32 = lane & 31;
+    const int hi = lane >> 5;
+
+    v16f acc[2][2];
+    if (MODE == kGemmSub) {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) {
+                const int64_t i = i0 + wi + ib * 32 + l32;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                    acc[jb][ib][r] = C[j * ldc + i];
+                }
+            }
+    } else {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[jb][ib][r] = 0.0f;
+    }
+
+    // global -> register staging: thread loads float4 at (row 4*(tid%32), p = tid/32 (+8))
+    const int lr = 4 * (threadIdx.x & 31);
+    const int lp = threadIdx.x >> 5;
+    float4 pa[2], qa[2];
+    auto gload = [&](int64_t kk) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            pa[s] = *reinterpret_cast<const float4 *>(P + (kk + lp + 8 * s) * ldp + i0 + lr);
+            qa[s] = *reinterpret_cast<const float4 *>(Q + (kk + lp + 8 * s) * ldq + j0 + lr);
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            float4 q = qa[s];
+            if (MODE == kGemmSub) {
+                q.x = -q.x; q.y = -q.y; q.z = -q.z; q.w = -q.w;
+            }
+            *reinterpret_cast<float4 *>(&Ps[buf][lp + 8 * s][lr]) = pa[s];
+            *reinterpret_cast<float4 *>(&Qs[buf][lp + 8 * s][lr]) = q;
+        }
+    };
+
+    const int nst = (int)(K / KC);
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) gload((int64_t)(st + 1) * KC);
+#pragma unroll
+        for (int kp = 0; kp < KC / 2; ++kp) {
+            const int p = 2 * kp + hi;
+            const float q0 = Qs[buf][p][wj + l32];
+            const float q1 = Qs[buf][p][wj + 32 + l32];
+            const float p0 = Ps[buf][p][wi + l32];
+            const float p1 = Ps[buf][p][wi + 32 + l32];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q0, p0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q0, p1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q1, p0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q1, p1, acc[1][1], 0, 0, 0);
+        }
+        if (st + 1 < nst) swrite(buf ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+            const int64_t i = i0 + wi + ib * 32 + l32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                C[j * ldc + i] = acc[jb][ib][r];
+            }
+        }
+}
+
+}  // namespace
+
+void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
+                    const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode,
+                    bool lower_only)
+{
+    const int64_t tm = M / BT, tn = N / BT;
+    if (tm <= 0 || tn <= 0 || K <= 0) return;
+    int64_t blocks = lower_only ? tm * (tm + 1) / 2 : tm * tn;
+    if (mode == kGemmSub)
+        hipLaunchKernelGGL(k_gemm_nt<kGemmSub>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
+                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_gemm_nt<kGemmSet>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
+                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0);
+}
+
+}  // namespace mag

@@ -1,0 +1,131 @@
+// internal.hpp -- shared declarations of libmag's HIP translation units.
+//
+// Storage conventions used by every kernel:
+//   * X        caller's points, row-major n x m FP64 (device).
+//   * factor   FP32, column-major, leading dimension npad = n rounded up to
+//              a multiple of 256.  Element (i, j) at A[j * npad + i].  Only
+//              the lower triangle (plus the full 128 x 128 diagonal tiles)
+//              is ever written or read.  Rows/columns >= n are an identity
+//              padding, so every kernel works on whole tiles.
+//   * vectors  FP64, length npad, zero in the padding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "mag.h"
+
+namespace mag {
+
+constexpr int kPad = 256;      // npad multiple (panel width of the factor)
+constexpr int kTile = 128;     // MFMA tile edge and diagonal-block size
+constexpr int kPanel = 256;    // panel width nb of the blocked Cholesky
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// ---- device buffer that grows on demand ------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// Status words written by kernels (device memory, zeroed per call).
+enum StatusWord : int {
+    kStBreakdown = 0,    // FP32 Cholesky met a non-positive pivot (index+1)
+    kStSpinTimeout = 1,  // a bounded spin-wait gave up (should never happen)
+    kStNonFinite = 2,    // non-finite coordinate seen
+    kStCount = 8
+};
+
+}  // namespace mag
+
+struct mag_ctx {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    mag::DevBuf factor;    // FP32 npad^2 factor, or FP64 n^2 dense Z
+    mag::DevBuf dinv;      // FP32 inverses of the 128-diagonal blocks
+    mag::DevBuf vecs;      // FP64 vectors (Krylov basis and work vectors)
+    mag::DevBuf partial;   // FP64 partial sums of split reductions
+    mag::DevBuf ints;      // int32 counters / flags / status
+    double *host_scalars = nullptr;  // pinned host staging (64 doubles)
+    void *blas = nullptr;            // rocblas_handle (lazy, FP64 comparator)
+    int64_t cu_count = 256;
+};
+
+namespace mag {
+
+// Grow `b` to at least `bytes` (frees the old block; contents are lost).
+int ensure(mag_ctx *ctx, DevBuf &b, size_t bytes);
+
+// Event pairs around the trailing-update launches of a factorisation, with
+// the algorithmic flops of each launch.
+struct FactorTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<double> flops;
+    size_t used = 0;
+};
+void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv, int *status,
+                   FactorTimer *timer);
+size_t dmin_partial_doubles(int64_t n);
+size_t blas1_partial_doubles(int kmax);
+
+// ---- launchers (all enqueue on ctx->stream) --------------------------------
+// tilegen.hip
+void launch_tilegen32(hipStream_t s, const double *X, int64_t n, int m, double t,
+                      float *A, int64_t npad, float shift);
+void launch_tilegen64(hipStream_t s, const double *X, int64_t n, int m, double t, double *A);
+// Writes min squared distance partials; returns number of partials in *np.
+void launch_dmin2(hipStream_t s, const double *X, int64_t n, int m, double *partial,
+                  int64_t *np, double *out_min2);
+void launch_check_finite(hipStream_t s, const double *X, int64_t count, int *status);
+
+// gemm_mfma.hip: C (M x N) = [C] - P * Q^T or C = P * Q^T, column-major operands.
+// P is M x K (P[p*ldp + i]), Q is N x K (Q[p*ldq + j]); M, N multiples of 128,
+// K multiple of 16.  lower_only skips tiles with tile_col > tile_row (C
+// assumed square-aligned, i.e. diagonal tiles at equal tile indices).
+enum GemmMode { kGemmSub = 0, kGemmSet = 1 };
+void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
+                    const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K,
+                    GemmMode mode, bool lower_only);
+
+// potrf.hip: factor the 128 x 128 diagonal block at (k0, k0) of A in place and
+// write its inverse to Linv (128 x 128 column-major).  Breakdown -> status.
+void launch_potrf128(hipStream_t s, float *A, int64_t ld, int64_t k0, float *Linv, int *status);
+
+// gemv64.hip: FP64 matrix-free products with Z regenerated from X.
+//   mode 0: y = Z v;  mode 1: y = b - Z v (b may be NULL meaning ones) and
+//   out_norm[0] = ||y||_inf (device scalar).
+void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t,
+                const double *v, double *y, const double *b, int mode,
+                double *partial, double *out_norm);
+size_t zmv_partial_doubles(int64_t n);
+
+// trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.
+void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
+                       const double *r, double *y_tmp, double *z, int *counters, int *status);
+size_t prec_counter_ints();
+
+// blas1.hip: deterministic FP64 vector kernels (length npad, two-pass).
+void launch_fill(hipStream_t s, double *x, int64_t len, double v);
+void launch_fill_ints(hipStream_t s, int *x, int64_t len, int v);
+void launch_copy(hipStream_t s, const double *x, double *y, int64_t len);
+// h[i] = V_i . u for i < k (V rows of stride ld), result in device h (k doubles).
+void launch_multidot(hipStream_t s, const double *V, int64_t ld, int k, const double *u,
+                     int64_t len, double *partial, double *h);
+// u -= sum_i h[i] V_i
+void launch_multi_axpy(hipStream_t s, const double *V, int64_t ld, int k, const double *h,
+                       double *u, int64_t len, double sign);
+// out = ||x||_2 (device scalar)
+void launch_nrm2(hipStream_t s, const double *x, int64_t len, double *partial, double *out);
+// y = x * (1/alpha[0]) with device alpha
+void launch_scale_inv(hipStream_t s, const double *x, double *y, int64_t len, const double *alpha);
+// y += x
+void launch_axpy1(hipStream_t s, const double *x, double *y, int64_t len);
+// sum (Neumaier-free, pairwise blocked), min, argmin of x[0..n): out[0]=sum, out[1]=min, out[2]=argmin
+void launch_sum_min(hipStream_t s, const double *x, int64_t n, double *partial, double *out);
+
+}  // namespace mag

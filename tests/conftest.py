@@ -30,3 +30,24 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "gpu" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    # name the case on stderr before any GPU work, so a crash is attributable
+    if "gpu" in request.keywords:
+        sys.stderr.write(f"\n[gpu-case] {request.node.nodeid}\n")
+        sys.stderr.flush()
+    yield
+
+
+@pytest.fixture(scope="session")
+def mag():
+    import torch
+    import paper_2607_23354_amd as m
+    from paper_2607_23354_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    assert torch.cuda.is_available()
+    return m
