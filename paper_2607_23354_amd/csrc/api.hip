@@ -59,7 +59,8 @@ using namespace mag;
 namespace {
 
 constexpr int kIntStatus = 0;    // 8 ints of status
-constexpr int kIntCounters = 8;  // preconditioner counters
+constexpr int kIntCounters = 64;  // preconditioner counters (prec_counter_ints())
+constexpr int kIntsTotal = 2048;
 
 struct Timer {
     bool on = false;
@@ -119,7 +120,7 @@ int check_points(mag_ctx *ctx, const double *X, int64_t n, int m)
 
 int ensure_common(mag_ctx *ctx, int64_t n, int restart)
 {
-    CHK(ensure(ctx, ctx->ints, sizeof(int) * 64));
+    CHK(ensure(ctx, ctx->ints, sizeof(int) * kIntsTotal));
     const int64_t npad = round_up(n, kPad);
     size_t part = std::max(zmv_partial_doubles(n), blas1_partial_doubles(restart + 2));
     part = std::max(part, dmin_partial_doubles(n) + 8);
@@ -443,7 +444,7 @@ int mag_create(mag_ctx **out, int device)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cu_count = cus;
-    if (ensure(c, c->ints, sizeof(int) * 64) != MAG_OK) {
+    if (ensure(c, c->ints, sizeof(int) * kIntsTotal) != MAG_OK) {
         mag_destroy(c);
         return MAG_ENOMEM;
     }
@@ -590,7 +591,7 @@ int mag_factor32(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, do
 {
     if (!c || !L || !dinv || !valid_args(X, n, m, t) || !(shift >= 0.0)) return MAG_EINVAL;
     HIPCHK(hipSetDevice(c->device));
-    CHK(ensure(c, c->ints, sizeof(int) * 64));
+    CHK(ensure(c, c->ints, sizeof(int) * kIntsTotal));
     const int64_t npad = round_up(n, kPad);
     int *status = (int *)c->ints.p;
     launch_fill_ints(c->stream, status, 8, 0);
@@ -607,7 +608,7 @@ int mag_prec_apply(mag_ctx *c, const float *L, const float *dinv, int64_t n, con
 {
     if (!c || !L || !dinv || !r || !z || n < 1) return MAG_EINVAL;
     HIPCHK(hipSetDevice(c->device));
-    CHK(ensure(c, c->ints, sizeof(int) * 64));
+    CHK(ensure(c, c->ints, sizeof(int) * kIntsTotal));
     const int64_t npad = round_up(n, kPad);
     CHK(ensure(c, c->vecs, sizeof(double) * ((size_t)npad * 3 + 256)));
     double *rb = (double *)c->vecs.p;

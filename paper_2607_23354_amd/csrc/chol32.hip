@@ -5,7 +5,8 @@
 // the preconditioner of the FP64 refinement.  For each panel of nb = 256
 // columns starting at k (two 128-column sub-panels s):
 //   1. potrf128   factor of the 128 x 128 diagonal block and its inverse
-//   2. trsm       rows below:  L21 = A21 * inv(L11)^T     (MFMA, in place)
+//   2. trsm       rows below:  L21 = A21 * inv(L11)^T     (MFMA, in place),
+//                 with L21^T written into the upper triangle
 //   3. (s = 0)    update the second sub-panel's columns with the first
 //   4. syrk       trailing update  A22 -= L21 L21^T, K = 256, lower tiles only
 // The panel inverses of the diagonal 128-blocks are kept (dinv) for the
@@ -31,7 +32,8 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
             const int64_t below = npad - kk - T;
             if (below > 0) {
                 float *A21 = A + kk * npad + kk + T;
-                launch_gemm_nt(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSet, false);
+                float *A12 = A + (kk + T) * npad + kk;  // upper triangle: L21^T
+                launch_gemm_nt(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSetT, false, A12);
             }
             if (sub + 1 < kPanel / T && below > 0) {
                 // update the next sub-panel's columns (rows kk+T ..) with this sub-panel

@@ -3,6 +3,9 @@
 //   C (M x N)  <-  C - P Q^T      (kGemmSub: trailing SYRK/GEMM updates)
 //   C (M x N)  <-  P Q^T          (kGemmSet: panel TRSM against an explicit
 //                                   inverse of the diagonal block)
+//   kGemmSetT: as kGemmSet and also C^T into CT (CT(j, i) = CT[i * ldc + j]),
+//   staged through LDS so both stores are coalesced; the factorisation uses
+//   it to keep L^T in the upper triangle for the backward substitution.
 //
 // All operands are column-major FP32: P(i, p) = P[p * ldp + i],
 // Q(j, p) = Q[p * ldq + j], C(i, j) = C[j * ldc + i].  Accumulation is FP32
@@ -36,13 +39,18 @@ __device__ inline void tri_index(int64_t idx, int64_t &ti, int64_t &tj)
     tj = idx - r * (r + 1) / 2;
 }
 
+constexpr int TLD = BT + 1;
+constexpr int LDS_FLOATS = (2 * 2 * KC * BT > BT * (64 + 1)) ? 2 * 2 * KC * BT : BT * (64 + 1);
+
 template <int MODE>
 __global__ void __launch_bounds__(NT, 2)
 k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
-          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, int lower_only)
+          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, int lower_only,
+          float *__restrict__ CT)
 {
-    __shared__ float Ps[2][KC][BT];
-    __shared__ float Qs[2][KC][BT];
+    __shared__ float lds[LDS_FLOATS];
+    float (*Ps)[KC][BT] = reinterpret_cast<float (*)[KC][BT]>(lds);
+    float (*Qs)[KC][BT] = reinterpret_cast<float (*)[KC][BT]>(lds + 2 * KC * BT);
 
     int64_t ti, tj;
     if (lower_only) {
@@ -138,23 +146,51 @@ k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64
                 C[j * ldc + i] = acc[jb][ib][r];
             }
         }
+    if (MODE == kGemmSetT) {
+        // transposed copy, 64 columns of the tile at a time through LDS (T[jl][i])
+        float *T = lds;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            __syncthreads();
+            if ((wave >> 1) == half) {
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib) {
+                        const int il = wi + ib * 32 + l32;
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int jl = jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                            T[jl * (BT + 1) + il] = acc[jb][ib][r];
+                        }
+                    }
+            }
+            __syncthreads();
+            const int jl = threadIdx.x & 63;
+            for (int il = threadIdx.x >> 6; il < BT; il += NT / 64)
+                CT[(i0 + il) * ldc + j0 + half * 64 + jl] = T[jl * (BT + 1) + il];
+        }
+    }
 }
 
 }  // namespace
 
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode,
-                    bool lower_only)
+                    bool lower_only, float *CT)
 {
     const int64_t tm = M / BT, tn = N / BT;
     if (tm <= 0 || tn <= 0 || K <= 0) return;
     int64_t blocks = lower_only ? tm * (tm + 1) / 2 : tm * tn;
     if (mode == kGemmSub)
         hipLaunchKernelGGL(k_gemm_nt<kGemmSub>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
-                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0);
-    else
+                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0, CT);
+    else if (mode == kGemmSet)
         hipLaunchKernelGGL(k_gemm_nt<kGemmSet>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
-                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0);
+                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0, CT);
+    else
+        hipLaunchKernelGGL(k_gemm_nt<kGemmSetT>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
+                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0, CT);
 }
 
 }  // namespace mag

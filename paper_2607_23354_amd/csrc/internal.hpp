@@ -3,9 +3,11 @@
 // Storage conventions used by every kernel:
 //   * X        caller's points, row-major n x m FP64 (device).
 //   * factor   FP32, column-major, leading dimension npad = n rounded up to
-//              a multiple of 256.  Element (i, j) at A[j * npad + i].  Only
-//              the lower triangle (plus the full 128 x 128 diagonal tiles)
-//              is ever written or read.  Rows/columns >= n are an identity
+//              a multiple of 256.  Element (i, j) at A[j * npad + i].  The
+//              factor L is built in the lower triangle; as each panel is
+//              finished its transpose is written into the upper triangle, so
+//              the backward substitution streams L^T with the same access
+//              pattern as the forward one.  Rows/columns >= n are an identity
 //              padding, so every kernel works on whole tiles.
 //   * vectors  FP64, length npad, zero in the padding.
 #pragma once
@@ -87,10 +89,11 @@ void launch_check_finite(hipStream_t s, const double *X, int64_t count, int *sta
 // P is M x K (P[p*ldp + i]), Q is N x K (Q[p*ldq + j]); M, N multiples of 128,
 // K multiple of 16.  lower_only skips tiles with tile_col > tile_row (C
 // assumed square-aligned, i.e. diagonal tiles at equal tile indices).
-enum GemmMode { kGemmSub = 0, kGemmSet = 1 };
+// kGemmSetT also writes C^T to CT (CT(j, i) at CT[i * ldc + j]).
+enum GemmMode { kGemmSub = 0, kGemmSet = 1, kGemmSetT = 2 };
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K,
-                    GemmMode mode, bool lower_only);
+                    GemmMode mode, bool lower_only, float *CT = nullptr);
 
 // potrf.hip: factor the 128 x 128 diagonal block at (k0, k0) of A in place and
 // write its inverse to Linv (128 x 128 column-major).  Breakdown -> status.

@@ -133,10 +133,10 @@ k_potrf128(float *__restrict__ A, int64_t ld, int64_t k0, float *__restrict__ Li
         __syncthreads();
     }
 
-    // write L back (lower triangle including the diagonal)
+    // write L back (lower triangle including the diagonal) and L^T above it
     for (int e = tid; e < NB * NB; e += 256) {
         const int r = e & (NB - 1), c = e >> 7;
-        if (r >= c) Ablk[(int64_t)c * ld + r] = S[c * LDS_LD + r];
+        Ablk[(int64_t)c * ld + r] = (r >= c) ? S[c * LDS_LD + r] : S[r * LDS_LD + c];
     }
 
     // inverse, diagonal 32 x 32 blocks: wave w inverts block w; lane%32 = column

@@ -89,6 +89,8 @@ def test_factor32(mag, n, m, t):
     Lc = L.cpu().numpy().T  # Lc[i, j] = L_ij
     npad = Lc.shape[0]
     Lf = np.tril(Lc).astype(np.float64)
+    # the upper triangle holds L^T (written by the factorisation for the backward solve)
+    assert np.array_equal(np.triu(Lc, 1), np.tril(Lc, -1).T)
     Z = np.eye(npad)
     Z[:n, :n] = oracle.zmatrix(X, t)
     E = Lf @ Lf.T - Z
