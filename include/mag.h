@@ -118,6 +118,76 @@ int mag_magnitude(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
  * the bound on the cutoff is log(n-1)/d_min (Sections 1 and 2).  n >= 2. */
 int mag_dmin(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double *d_min);
 
+/* ---- the cutoff t_+ (Section 2, cutoff paragraph and footnote) -------------
+ * t_+ is the least t from which w >= 0 (read as inf{t : w(s) >= 0 for all
+ * s >= t}).  Search: d_min by brute force gives the bound
+ * t_b = log(n-1)/d_min, where w >= 0; a log grid of `grid` points on
+ * [t_b*lo_factor, t_b] is scanned downward to the first t with min w < 0
+ * (extended downward by lo_factor up to max_extend times); the bracketing
+ * cell is then refined in log t by bisection, safeguarded Newton steps using
+ * d(min w)/dt = (Z^{-1} (D o Z) w)_{argmin} when newton != 0, until
+ * (t_hi - t_lo)/t_hi <= rtol, or until 0 <= min w < eps (eps = 0 means
+ * n * 2^-53).  The returned t_plus is the upper end, where min w >= 0.
+ * t_lo/t_hi > 0 give a starting bracket (resume); it is verified first. */
+typedef struct {
+    int32_t grid;          /* grid points, default 32                                     */
+    int32_t max_extend;    /* downward grid extensions, default 2                          */
+    int32_t newton;        /* 1: safeguarded Newton inside bisection, default 1            */
+    int32_t pad_;
+    double lo_factor;      /* grid spans [t_b*lo_factor, t_b], default 1e-3                */
+    double rtol;           /* relative bracket width, default 1e-6                         */
+    double eps;            /* early halt when 0 <= min w < eps; 0 = n * 2^-53              */
+    double t_lo, t_hi;     /* optional starting bracket (0 = none)                          */
+} mag_tplus_opts;
+
+typedef struct {
+    double t_plus;         /* = *t_plus                                                     */
+    double t_bound;        /* log(n-1)/d_min                                                */
+    double d_min;
+    double min_w;          /* min w at t_plus                                               */
+    double t_bracket_lo, t_bracket_hi;
+    int32_t solves;        /* weighting solves (factorisations)                             */
+    int32_t newton_steps;
+    int32_t no_sign_change;/* 1: w >= 0 on the whole (extended) grid; t_plus = 0            */
+    int32_t status;
+} mag_tplus_info;
+
+void mag_tplus_opts_default(mag_tplus_opts *opts);
+
+/* Cutoff search for the points X (device, n x m).  *t_plus (HOST) receives
+ * t_+ (0 when no sign change is found: collinear sets and n <= 2 have w > 0
+ * for every t).  w (device, n, may be NULL) receives w(t_plus).  topts and
+ * sopts (solver options of each weighting solve) may be NULL. */
+int mag_tplus(mag_ctx *ctx, const double *X, int64_t n, int32_t m, const mag_tplus_opts *topts,
+              const mag_opts *sopts, double *t_plus, double *w, mag_tplus_info *info);
+
+/* dw/dt = Z^{-1} (D o Z) w at scale t, where (D o Z)_jk = d_jk exp(-t d_jk)
+ * (from differentiating eq. weighting in t).  w (device, n, may be NULL)
+ * receives the weighting, dwdt (device, n) its derivative.  m <= 16. */
+int mag_dwdt(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, double *w,
+             double *dwdt, const mag_opts *opts);
+
+/* ---- adjoint of (w, Mag) with respect to (X, t) ----------------------------
+ * Differentiating Z(t, X) w = 1: with lambda = Z^{-1}(gM 1 + gw),
+ *   dL/dt   = lambda^T (D o Z) w,
+ *   dL/dx_j = t sum_{k != j} (lambda_j w_k + lambda_k w_j) Z_jk (x_j - x_k)/d_jk.
+ * mag_weighting_fwd solves like mag_weighting and keeps the FP32 factor in a
+ * handle (npad^2 * 4 bytes of device memory, owned by the handle until
+ * mag_factor_free); mag_weighting_vjp reuses it for lambda (one refinement
+ * solve; none when gw == NULL, since then lambda = gM w). */
+typedef struct mag_factor mag_factor;
+
+int mag_weighting_fwd(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, double *w,
+                      mag_factor **keep, const mag_opts *opts, mag_info *info);
+
+/* gM: dL/dMag; gw: dL/dw (device, n, may be NULL); dX: device n x m row-major
+ * output (may be NULL); dt: HOST output (may be NULL).  X, n, m, t must be
+ * those of the forward call (EINVAL otherwise).  m <= 16. */
+int mag_weighting_vjp(mag_ctx *ctx, mag_factor *f, const double *X, int64_t n, int32_t m,
+                      double t, const double *w, double gM, const double *gw, double *dX,
+                      double *dt, const mag_opts *opts);
+
+void mag_factor_free(mag_factor *f);
 
 /* ---- kernel-level entry points --------------------------------------------
  * The steps of the FP32_IR path exposed one by one, for parity tests and
@@ -151,6 +221,10 @@ int mag_factor32(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
  * r, z: device, n. */
 int mag_prec_apply(mag_ctx *ctx, const float *L, const float *dinv, int64_t n,
                    const double *r, double *z);
+
+/* y = (D o Z) v in FP64, matrix-free (device, n); m <= 16. */
+int mag_dzmatvec(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                 const double *v, double *y);
 
 #ifdef __cplusplus
 }

@@ -80,6 +80,8 @@ def lib():
         L.orc_zmatvec.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D]
         L.orc_dzmatvec.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D]
         L.orc_grad_x.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D, _D]
+        L.orc_grad_x_rows.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D, _I64,
+                                      ctypes.c_int64, _D]
         L.orc_sum.restype = ctypes.c_double
         L.orc_sum.argtypes = [_D, ctypes.c_int64]
         L.orc_weighting.restype = ctypes.c_int
@@ -318,6 +320,19 @@ def grad(X, t: float, gM: float = 1.0, gw=None, sol: Weighting | None = None):
     dX = np.empty((n, m))
     lib().orc_grad_x(_p(X), n, m, float(t), _p(np.ascontiguousarray(lam)), _p(sol.w), _p(dX))
     return dt, dX, sol
+
+
+def grad_x_rows(X, t: float, lam, w, rows) -> np.ndarray:
+    """Rows of dL/dX = t sum_{k != j} (lambda_j w_k + lambda_k w_j) Z_jk (x_j - x_k)/d_jk
+    for given lambda and w (one output row at a time)."""
+    X = _pts(X)
+    n, m = X.shape
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.empty((len(rows), m))
+    lib().orc_grad_x_rows(_p(X), n, m, float(t), _p(np.ascontiguousarray(lam, dtype=np.float64)),
+                          _p(np.ascontiguousarray(w, dtype=np.float64)), rows.ctypes.data_as(_I64),
+                          len(rows), _p(out))
+    return out
 
 
 def dw_dt(sol: Weighting) -> np.ndarray:

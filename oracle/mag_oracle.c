@@ -239,6 +239,27 @@ void orc_grad_x(const double *X, int64_t n, int m, double t, const double *lam,
     }
 }
 
+/* The same gradient for selected rows only: dX_rows[i*m + l] = dL/dx_{rows[i], l}.
+ * Lets full-size results be checked one output row at a time. */
+void orc_grad_x_rows(const double *X, int64_t n, int m, double t, const double *lam,
+                     const double *w, const int64_t *rows, int64_t nrows, double *dX_rows)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nrows; ++i) {
+        const int64_t j = rows[i];
+        for (int l = 0; l < m; ++l)
+            dX_rows[i * m + l] = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == j)
+                continue;
+            double d = dist(X, m, j, k);
+            double coef = t * (lam[j] * w[k] + lam[k] * w[j]) * exp(-(t * d)) / d;
+            for (int l = 0; l < m; ++l)
+                dX_rows[i * m + l] = dX_rows[i * m + l] + coef * (X[j * m + l] - X[k * m + l]);
+        }
+    }
+}
+
 /* Neumaier's compensated sum (for Mag = 1^T w). */
 double orc_sum(const double *v, int64_t n)
 {

@@ -16,10 +16,11 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import MagError, MagInfo, MagOpts  # noqa: F401
+from ._lib import MagError, MagInfo, MagOpts, MagTplusInfo, MagTplusOpts  # noqa: F401
 
 __all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "tile32",
-           "factor32", "prec_apply", "padded_size", "MagError", "SOLVERS"]
+           "factor32", "prec_apply", "padded_size", "tplus", "dwdt", "dzmatvec",
+           "MagnitudeFn", "weighting_and_magnitude", "MagError", "SOLVERS"]
 
 SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
            "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR}
@@ -213,3 +214,123 @@ def prec_apply(L: torch.Tensor, dinv: torch.Tensor, n: int, r: torch.Tensor, *,
     z = torch.empty(n, dtype=torch.float64, device=r.device)
     _lib.check(c.lib.mag_prec_apply(c.handle, _ptr(L), _ptr(dinv), n, _ptr(r), _ptr(z)), "mag_prec_apply")
     return z
+
+
+def dzmatvec(X: torch.Tensor, t: float, v: torch.Tensor, *, ctx: Context | None = None) -> torch.Tensor:
+    """(D o Z) v with (D o Z)_jk = d_jk exp(-t d_jk), matrix-free FP64."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    v = v.contiguous()
+    y = torch.empty(n, dtype=torch.float64, device=X.device)
+    _lib.check(c.lib.mag_dzmatvec(c.handle, _ptr(X), n, m, float(t), _ptr(v), _ptr(y)), "mag_dzmatvec")
+    return y
+
+
+def dwdt(X: torch.Tensor, t: float, *, ctx: Context | None = None, **opts):
+    """(w, dw/dt) at scale t, dw/dt = Z^{-1} (D o Z) w."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    o = make_opts(**opts)
+    w = torch.empty(n, dtype=torch.float64, device=X.device)
+    d = torch.empty(n, dtype=torch.float64, device=X.device)
+    _lib.check(c.lib.mag_dwdt(c.handle, _ptr(X), n, m, float(t), _ptr(w), _ptr(d), ctypes.byref(o)), "mag_dwdt")
+    return w, d
+
+
+@dataclass
+class TplusResult:
+    t_plus: float
+    w: torch.Tensor | None
+    info: dict
+
+
+def tplus(X: torch.Tensor, *, ctx: Context | None = None, grid: int = 32, lo_factor: float = 1e-3,
+          rtol: float = 1e-6, newton: bool = True, max_extend: int = 2, eps: float = 0.0,
+          t_lo: float = 0.0, t_hi: float = 0.0, want_w: bool = True, **opts) -> TplusResult:
+    """Cutoff t_+ (least t from which w >= 0) by a downward log-grid scan from
+    log(n-1)/d_min and safeguarded Newton/bisection in log t."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    to = MagTplusOpts()
+    c.lib.mag_tplus_opts_default(ctypes.byref(to))
+    to.grid, to.lo_factor, to.rtol, to.newton = grid, lo_factor, rtol, 1 if newton else 0
+    to.max_extend, to.eps, to.t_lo, to.t_hi = max_extend, eps, t_lo, t_hi
+    o = make_opts(**opts)
+    w = torch.empty(n, dtype=torch.float64, device=X.device) if want_w else None
+    tp = ctypes.c_double()
+    info = MagTplusInfo()
+    _lib.check(c.lib.mag_tplus(c.handle, _ptr(X), n, m, ctypes.byref(to), ctypes.byref(o), ctypes.byref(tp),
+                               _ptr(w), ctypes.byref(info)), "mag_tplus")
+    return TplusResult(tp.value, w if (want_w and not info.no_sign_change) else None, info.as_dict())
+
+
+class _FactorHandle:
+    """Owns a mag_factor (the FP32 factor kept by the forward pass)."""
+
+    def __init__(self, lib, handle):
+        self.lib, self.handle = lib, handle
+
+    def __del__(self):
+        if self.handle:
+            self.lib.mag_factor_free(self.handle)
+            self.handle = None
+
+
+class MagnitudeFn(torch.autograd.Function):
+    """(w, Mag) = MagnitudeFn.apply(X, t) with a hand-written adjoint.
+
+    Forward: mag_weighting_fwd (FP32 MFMA factor + FP64 refinement), keeping
+    the factor.  Backward: mag_weighting_vjp, which reuses the factor for
+    lambda = Z^{-1}(gM 1 + gw) and makes one matrix-free FP64 pass for
+    dL/dt = lambda^T (D o Z) w and dL/dX."""
+
+    @staticmethod
+    def forward(fctx, X, t):
+        X = _points(X)
+        n, m = X.shape
+        c = _ctx(None, X)
+        tval = float(t)
+        o = make_opts()
+        info = MagInfo()
+        w = torch.empty(n, dtype=torch.float64, device=X.device)
+        h = ctypes.c_void_p()
+        _lib.check(c.lib.mag_weighting_fwd(c.handle, _ptr(X), n, m, tval, _ptr(w), ctypes.byref(h),
+                                           ctypes.byref(o), ctypes.byref(info)), "mag_weighting_fwd")
+        fctx.factor = _FactorHandle(c.lib, h)
+        fctx.tval = tval
+        fctx.t_is_tensor = isinstance(t, torch.Tensor)
+        fctx.set_materialize_grads(False)
+        fctx.save_for_backward(X, w)
+        M = torch.tensor(info.magnitude, dtype=torch.float64, device=X.device)
+        return w, M
+
+    @staticmethod
+    def backward(fctx, gw, gM):
+        X, w = fctx.saved_tensors
+        n, m = X.shape
+        c = _ctx(None, X)
+        gMv = float(gM) if gM is not None else 0.0
+        gwp = None
+        if gw is not None:
+            gw = gw.contiguous().to(torch.float64)
+            gwp = _ptr(gw)
+        need_x = fctx.needs_input_grad[0]
+        need_t = fctx.needs_input_grad[1]
+        dX = torch.empty((n, m), dtype=torch.float64, device=X.device) if need_x else None
+        dt = ctypes.c_double()
+        o = make_opts()
+        _lib.check(c.lib.mag_weighting_vjp(c.handle, fctx.factor.handle, _ptr(X), n, m, fctx.tval, _ptr(w),
+                                           gMv, gwp, _ptr(dX), ctypes.byref(dt) if need_t else None,
+                                           ctypes.byref(o)), "mag_weighting_vjp")
+        gt = None
+        if need_t and fctx.t_is_tensor:
+            gt = torch.tensor(dt.value, dtype=torch.float64, device=X.device)
+        return dX, gt
+
+
+def weighting_and_magnitude(X: torch.Tensor, t):
+    """Differentiable (w, Mag) of eq. weighting (see MagnitudeFn)."""
+    return MagnitudeFn.apply(X, t)

@@ -67,6 +67,38 @@ class MagInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
 
 
+class MagTplusOpts(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_int32),
+        ("max_extend", ctypes.c_int32),
+        ("newton", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("lo_factor", ctypes.c_double),
+        ("rtol", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("t_lo", ctypes.c_double),
+        ("t_hi", ctypes.c_double),
+    ]
+
+
+class MagTplusInfo(ctypes.Structure):
+    _fields_ = [
+        ("t_plus", ctypes.c_double),
+        ("t_bound", ctypes.c_double),
+        ("d_min", ctypes.c_double),
+        ("min_w", ctypes.c_double),
+        ("t_bracket_lo", ctypes.c_double),
+        ("t_bracket_hi", ctypes.c_double),
+        ("solves", ctypes.c_int32),
+        ("newton_steps", ctypes.c_int32),
+        ("no_sign_change", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -90,6 +122,16 @@ SIGNATURES = {
     "mag_tile32": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp]),
     "mag_factor32": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _d, _vp, _vp, ctypes.POINTER(_i32)]),
     "mag_prec_apply": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "mag_dzmatvec": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp]),
+    "mag_tplus_opts_default": (None, [ctypes.POINTER(MagTplusOpts)]),
+    "mag_tplus": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(MagTplusOpts), ctypes.POINTER(MagOpts),
+                                 ctypes.POINTER(_d), _vp, ctypes.POINTER(MagTplusInfo)]),
+    "mag_dwdt": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp, ctypes.POINTER(MagOpts)]),
+    "mag_weighting_fwd": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, ctypes.POINTER(_vp),
+                                         ctypes.POINTER(MagOpts), ctypes.POINTER(MagInfo)]),
+    "mag_weighting_vjp": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _d, _vp, _d, _vp, _vp,
+                                         ctypes.POINTER(_d), ctypes.POINTER(MagOpts)]),
+    "mag_factor_free": (None, [_vp]),
 }
 
 _lib = None

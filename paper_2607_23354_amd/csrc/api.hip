@@ -135,72 +135,114 @@ struct Gmres {
     std::vector<double> cs, sn, g;
 };
 
-// FP32-factor + FP64 GMRES iterative refinement.  Returns status; w holds the
-// best iterate.
-int solve_fp32_ir(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double *w,
-                  const mag_opts &o, mag_info *info)
+// FP32 factor of Z (+ shift I) with its diagonal-block inverses.
+struct Factor32 {
+    float *A = nullptr;
+    float *dinv = nullptr;
+    int64_t npad = 0;
+    double shift = 0.0;
+    int shifted = 0;
+};
+
+// Work vectors carved from ctx->vecs (FP64, npad each) and device scalars.
+struct Vecs {
+    double *V, *x, *r, *z, *ytmp, *u, *best, *rhs, *dsc, *hdev;
+};
+
+int carve_vecs(mag_ctx *ctx, int64_t npad, int restart, Vecs &v)
+{
+    const int nvec = restart + 1 + 7;
+    CHK(ensure(ctx, ctx->vecs, sizeof(double) * ((size_t)nvec * npad + 512)));
+    double *p = (double *)ctx->vecs.p;
+    v.V = p;
+    p += (size_t)(restart + 1) * npad;
+    v.x = p; p += npad;
+    v.r = p; p += npad;
+    v.z = p; p += npad;
+    v.ytmp = p; p += npad;
+    v.u = p; p += npad;
+    v.best = p; p += npad;
+    v.rhs = p; p += npad;
+    v.dsc = p;        // 16 device scalars
+    v.hdev = p + 16;  // up to 2*(restart+1)+2 doubles
+    return MAG_OK;
+}
+
+int ensure_solver(mag_ctx *ctx, int64_t n, int m, int restart)
+{
+    CHK(ensure_common(ctx, n, restart));
+    size_t part = std::max(zmv_partial_doubles(n), pair_partial_doubles(n, m));
+    part = std::max(part, blas1_partial_doubles(restart + 2));
+    part = std::max(part, dmin_partial_doubles(n) + 8);
+    CHK(ensure(ctx, ctx->partial, sizeof(double) * (part + 64)));
+    return MAG_OK;
+}
+
+// Tile generation + blocked FP32 Cholesky, retried with a growing diagonal
+// shift when the FP32 factorisation meets a non-positive pivot.
+int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Factor32 &F,
+                FactorTimer *ft, Timer *tm)
 {
     hipStream_t s = ctx->stream;
-    const int64_t npad = round_up(n, kPad);
+    int *status = (int *)ctx->ints.p + kIntStatus;
+    double *hs = ctx->host_scalars;
+    F.shift = 0.0;
+    F.shifted = 0;
+    for (int attempt = 0;; ++attempt) {
+        launch_fill_ints(s, status, 8, 0);
+        launch_tilegen32(s, X, n, m, t, F.A, F.npad, (float)F.shift);
+        if (tm && attempt == 0) tm->mark(1);
+        if (ft) {
+            ft->used = 0;
+            ft->flops.clear();
+        }
+        chol32_factor(s, F.A, F.npad, n, F.dinv, status, ft);
+        HIPCHK(hipMemcpyAsync(hs, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (((const int *)hs)[kStBreakdown] == 0) break;
+        if (attempt >= 6) return MAG_ENOTPD;
+        F.shift = (F.shift == 0.0) ? 1e-6 * std::max<double>(1.0, std::sqrt((double)n)) : F.shift * 10.0;
+        F.shifted = 1;
+    }
+    return MAG_OK;
+}
+
+struct RefineStats {
+    int outer = 0, inner = 0;
+    double resid = INFINITY;
+};
+
+// Solve Z x = b (b: device npad vector, zero padded; NULL means the ones
+// vector of eq. weighting) by GMRES-based iterative refinement: FP64
+// residuals b - Z x with Z regenerated from X, corrections from GMRES on the
+// left-preconditioned system (L L^T)^{-1} Z d = (L L^T)^{-1} r.  The best
+// iterate goes to xout (device npad).  Stops when ||b - Z x||_inf <= tol *
+// max(1, ||b||_inf), on stagnation, or at the iteration limits.
+int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const Factor32 &F,
+                 const double *b, double bnorm, double *xout, const mag_opts &o, RefineStats &st)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t npad = F.npad;
     const int restart = std::max(1, o.gmres_restart);
-    CHK(ensure_common(ctx, n, restart));
-    CHK(ensure(ctx, ctx->factor, sizeof(float) * (size_t)npad * (size_t)npad));
-    CHK(ensure(ctx, ctx->dinv, sizeof(float) * (size_t)npad * kTile));
-    // vectors: V (restart+1), wv, r, z, ytmp, u, best, dev scalars
-    const int nvec = restart + 1 + 6;
-    CHK(ensure(ctx, ctx->vecs, sizeof(double) * ((size_t)nvec * npad + 256)));
-    float *A = (float *)ctx->factor.p;
-    float *dinv = (float *)ctx->dinv.p;
-    double *V = (double *)ctx->vecs.p;
-    double *wv = V + (size_t)(restart + 1) * npad;
-    double *r = wv + npad;
-    double *z = r + npad;
-    double *ytmp = z + npad;
-    double *u = ytmp + npad;
-    double *best = u + npad;
-    double *dsc = best + npad;  // device scalars: [0] norm, [1..] h, ...
-    double *hdev = dsc + 8;     // up to 2*(restart+1) + 2
+    Vecs v;
+    CHK(carve_vecs(ctx, npad, restart, v));
     double *partial = (double *)ctx->partial.p;
     int *ints = (int *)ctx->ints.p;
     int *status = ints + kIntStatus;
     int *counters = ints + kIntCounters;
     double *hs = ctx->host_scalars;
-
-    Timer tm;
-    tm.start(o.profile != 0, s);
-    FactorTimer ft;
-    tm.mark(0);
-
-    // ---- factor (with diagonal-shift retries on FP32 breakdown) ----
-    double shift = 0.0;
-    int shifted = 0;
-    for (int attempt = 0;; ++attempt) {
-        launch_fill_ints(s, status, 8, 0);
-        launch_tilegen32(s, X, n, m, t, A, npad, (float)shift);
-        if (attempt == 0) tm.mark(1);
-        ft.used = 0;
-        ft.flops.clear();
-        chol32_factor(s, A, npad, n, dinv, status, o.profile ? &ft : nullptr);
-        HIPCHK(hipMemcpyAsync(hs, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (((const int *)hs)[kStBreakdown] == 0) break;
-        if (attempt >= 6) return MAG_ENOTPD;
-        shift = (shift == 0.0) ? 1e-6 * std::max<double>(1.0, std::sqrt((double)n)) : shift * 10.0;
-        shifted = 1;
-    }
-    tm.mark(2);
-
-    // ---- refinement ----
-    const double tol = o.tol > 0 ? o.tol : 1e-12;
+    const double tol = (o.tol > 0 ? o.tol : 1e-12) * std::max(1.0, bnorm);
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-10;
-    int outer = 0, inner_total = 0;
-    double rnorm = INFINITY, best_norm = INFINITY;
-    int rc = MAG_ENOCONV;
+    const int max_gmres = o.max_gmres > 0 ? o.max_gmres : 200;
 
-    // w0 = M^{-1} 1
-    launch_fill(s, r, npad, 0.0);
-    launch_fill(s, r, n, 1.0);
-    launch_prec_apply(s, A, npad, dinv, r, ytmp, wv, counters, status);
+    const double *bb = b;
+    if (!bb) {
+        launch_fill(s, v.rhs, npad, 0.0);
+        launch_fill(s, v.rhs, n, 1.0);
+        bb = v.rhs;
+    }
+    // x0 = M^{-1} b
+    launch_prec_apply(s, F.A, npad, F.dinv, bb, v.ytmp, v.x, counters, status);
 
     Gmres G;
     G.restart = restart;
@@ -209,69 +251,66 @@ int solve_fp32_ir(mag_ctx *ctx, const double *X, int64_t n, int m, double t, dou
     G.sn.assign(restart, 0.0);
     G.g.assign(restart + 1, 0.0);
     std::vector<double> hbuf(2 * (restart + 2) + 2);
-
+    double rnorm = INFINITY, best_norm = INFINITY;
+    int rc = MAG_ENOCONV;
+    int outer = 0, inner_total = 0;
     for (outer = 0; outer < std::max(1, o.max_outer); ++outer) {
-        launch_zmv(s, X, n, m, t, wv, r, nullptr, 1, partial, dsc);
-        HIPCHK(hipMemcpyAsync(hs, dsc, sizeof(double), hipMemcpyDeviceToHost, s));
+        launch_zmv(s, X, n, m, t, v.x, v.r, bb, 1, partial, v.dsc);
+        HIPCHK(hipMemcpyAsync(hs, v.dsc, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hs + 8, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (((const int *)(hs + 8))[kStSpinTimeout]) return MAG_EINTERNAL;
         const double prev = rnorm;
         rnorm = hs[0];
-        if (!(rnorm < best_norm)) {
-            // no progress: stop with the best iterate
-            break;
-        }
+        if (!(rnorm < best_norm)) break;  // no progress: keep the best iterate
         best_norm = rnorm;
-        launch_copy(s, wv, best, npad);
+        launch_copy(s, v.x, v.best, npad);
         if (rnorm <= tol) {
             rc = MAG_OK;
             break;
         }
         if (outer > 0 && rnorm > 0.5 * prev) break;  // stagnation
-        if (inner_total >= o.max_gmres) break;
+        if (inner_total >= max_gmres) break;
         // GMRES(restart) on M^{-1} Z d = M^{-1} r, d0 = 0
-        double *V0 = V;
-        launch_prec_apply(s, A, npad, dinv, r, ytmp, z, counters, status);
-        launch_nrm2(s, z, npad, partial, dsc + 1);
-        HIPCHK(hipMemcpyAsync(hs + 1, dsc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        launch_prec_apply(s, F.A, npad, F.dinv, v.r, v.ytmp, v.z, counters, status);
+        launch_nrm2(s, v.z, npad, partial, v.dsc + 1);
+        HIPCHK(hipMemcpyAsync(hs + 1, v.dsc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         const double beta = hs[1];
         if (!(beta > 0.0) || !std::isfinite(beta)) break;
-        launch_scale_inv(s, z, V0, npad, dsc + 1);
+        launch_scale_inv(s, v.z, v.V, npad, v.dsc + 1);
         std::fill(G.H.begin(), G.H.end(), 0.0);
         std::fill(G.g.begin(), G.g.end(), 0.0);
         G.g[0] = beta;
         int kdone = 0;
-        for (int k = 0; k < restart && inner_total < o.max_gmres; ++k) {
-            double *Vk = V + (size_t)k * npad;
-            double *Vk1 = V + (size_t)(k + 1) * npad;
-            launch_zmv(s, X, n, m, t, Vk, u, nullptr, 0, partial, nullptr);
-            launch_prec_apply(s, A, npad, dinv, u, ytmp, Vk1, counters, status);
+        for (int k = 0; k < restart && inner_total < max_gmres; ++k) {
+            double *Vk = v.V + (size_t)k * npad;
+            double *Vk1 = v.V + (size_t)(k + 1) * npad;
+            launch_zmv(s, X, n, m, t, Vk, v.u, nullptr, 0, partial, nullptr);
+            launch_prec_apply(s, F.A, npad, F.dinv, v.u, v.ytmp, Vk1, counters, status);
             // classical Gram-Schmidt, twice
-            launch_multidot(s, V, npad, k + 1, Vk1, npad, partial, hdev);
-            launch_multi_axpy(s, V, npad, k + 1, hdev, Vk1, npad, -1.0);
-            launch_multidot(s, V, npad, k + 1, Vk1, npad, partial, hdev + (k + 1));
-            launch_multi_axpy(s, V, npad, k + 1, hdev + (k + 1), Vk1, npad, -1.0);
-            launch_nrm2(s, Vk1, npad, partial, hdev + 2 * (k + 1));
-            HIPCHK(hipMemcpyAsync(hbuf.data(), hdev, sizeof(double) * (2 * (k + 1) + 1),
+            launch_multidot(s, v.V, npad, k + 1, Vk1, npad, partial, v.hdev);
+            launch_multi_axpy(s, v.V, npad, k + 1, v.hdev, Vk1, npad, -1.0);
+            launch_multidot(s, v.V, npad, k + 1, Vk1, npad, partial, v.hdev + (k + 1));
+            launch_multi_axpy(s, v.V, npad, k + 1, v.hdev + (k + 1), Vk1, npad, -1.0);
+            launch_nrm2(s, Vk1, npad, partial, v.hdev + 2 * (k + 1));
+            HIPCHK(hipMemcpyAsync(hbuf.data(), v.hdev, sizeof(double) * (2 * (k + 1) + 1),
                                   hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             const double hk1 = hbuf[2 * (k + 1)];
             double *Hk = G.H.data() + (size_t)k * (restart + 1);
             for (int i = 0; i <= k; ++i) Hk[i] = hbuf[i] + hbuf[k + 1 + i];
             Hk[k + 1] = hk1;
-            if (hk1 > 0.0) launch_scale_inv(s, Vk1, Vk1, npad, hdev + 2 * (k + 1));
-            // apply previous rotations, then a new one
+            if (hk1 > 0.0) launch_scale_inv(s, Vk1, Vk1, npad, v.hdev + 2 * (k + 1));
             for (int i = 0; i < k; ++i) {
-                const double a = Hk[i], b = Hk[i + 1];
-                Hk[i] = G.cs[i] * a + G.sn[i] * b;
-                Hk[i + 1] = -G.sn[i] * a + G.cs[i] * b;
+                const double a = Hk[i], c = Hk[i + 1];
+                Hk[i] = G.cs[i] * a + G.sn[i] * c;
+                Hk[i + 1] = -G.sn[i] * a + G.cs[i] * c;
             }
-            const double a = Hk[k], b = Hk[k + 1];
-            const double rr = std::hypot(a, b);
+            const double a = Hk[k], c = Hk[k + 1];
+            const double rr = std::hypot(a, c);
             G.cs[k] = (rr > 0) ? a / rr : 1.0;
-            G.sn[k] = (rr > 0) ? b / rr : 0.0;
+            G.sn[k] = (rr > 0) ? c / rr : 0.0;
             Hk[k] = rr;
             Hk[k + 1] = 0.0;
             G.g[k + 1] = -G.sn[k] * G.g[k];
@@ -280,32 +319,95 @@ int solve_fp32_ir(mag_ctx *ctx, const double *X, int64_t n, int m, double t, dou
             kdone = k + 1;
             if (std::fabs(G.g[k + 1]) <= inner_tol * beta || !(hk1 > 0.0)) break;
         }
-        // y = H^{-1} g (upper triangular kdone x kdone)
         std::vector<double> y(kdone, 0.0);
         for (int i = kdone - 1; i >= 0; --i) {
             double acc = G.g[i];
             for (int j = i + 1; j < kdone; ++j) acc -= G.H[(size_t)j * (restart + 1) + i] * y[j];
             y[i] = acc / G.H[(size_t)i * (restart + 1) + i];
         }
-        HIPCHK(hipMemcpyAsync(hdev, y.data(), sizeof(double) * kdone, hipMemcpyHostToDevice, s));
-        launch_multi_axpy(s, V, npad, kdone, hdev, wv, npad, 1.0);
+        HIPCHK(hipMemcpyAsync(v.hdev, y.data(), sizeof(double) * kdone, hipMemcpyHostToDevice, s));
+        launch_multi_axpy(s, v.V, npad, kdone, v.hdev, v.x, npad, 1.0);
     }
-    tm.mark(3);
-    // return the best iterate
-    launch_copy(s, best, w, n);
-    launch_sum_min(s, best, n, partial, dsc + 2);
-    HIPCHK(hipMemcpyAsync(hs + 2, dsc + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (xout != v.best) launch_copy(s, v.best, xout, npad);
+    st.outer = outer + (rc == MAG_OK ? 1 : 0);
+    st.inner = inner_total;
+    st.resid = best_norm;
+    return rc;
+}
+
+// sum, min, argmin of w[0..n) -> host
+int summarize(mag_ctx *ctx, const double *w, int64_t n, double &sum, double &mn, int64_t &am)
+{
+    hipStream_t s = ctx->stream;
+    double *dsc = (double *)ctx->partial.p + blas1_partial_doubles(3);
+    launch_sum_min(s, w, n, (double *)ctx->partial.p, dsc);
+    HIPCHK(hipMemcpyAsync(ctx->host_scalars + 32, dsc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    sum = ctx->host_scalars[32];
+    mn = ctx->host_scalars[33];
+    am = (int64_t)ctx->host_scalars[34];
+    return MAG_OK;
+}
+
+Factor32 ctx_factor(mag_ctx *ctx, int64_t n)
+{
+    Factor32 F;
+    F.npad = round_up(n, kPad);
+    F.A = (float *)ctx->factor.p;
+    F.dinv = (float *)ctx->dinv.p;
+    return F;
+}
+
+int ensure_ctx_factor(mag_ctx *ctx, int64_t n)
+{
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure(ctx, ctx->factor, sizeof(float) * (size_t)npad * (size_t)npad));
+    CHK(ensure(ctx, ctx->dinv, sizeof(float) * (size_t)npad * kTile));
+    return MAG_OK;
+}
+
+// FP32-factor + FP64 GMRES iterative refinement for Z w = 1, into the
+// caller's w (n) -- optionally factorising into caller-provided buffers.
+int solve_fp32_ir(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double *w,
+                  const mag_opts &o, mag_info *info, Factor32 *keepF = nullptr)
+{
+    hipStream_t s = ctx->stream;
+    const int restart = std::max(1, o.gmres_restart);
+    CHK(ensure_solver(ctx, n, m, restart));
+    Factor32 F;
+    if (keepF) {
+        F = *keepF;
+    } else {
+        CHK(ensure_ctx_factor(ctx, n));
+        F = ctx_factor(ctx, n);
+    }
+    Timer tm;
+    tm.start(o.profile != 0, s);
+    FactorTimer ft;
+    tm.mark(0);
+    CHK(factor_fp32(ctx, X, n, m, t, F, o.profile ? &ft : nullptr, &tm));
+    if (keepF) *keepF = F;
+    tm.mark(2);
+    Vecs v;
+    CHK(carve_vecs(ctx, F.npad, restart, v));
+    RefineStats st;
+    int rc = refine_solve(ctx, X, n, m, t, F, nullptr, 1.0, v.best, o, st);
+    if (rc != MAG_OK && rc != MAG_ENOCONV) return rc;
+    tm.mark(3);
+    launch_copy(s, v.best, w, n);
+    double sum, mn;
+    int64_t am;
+    CHK(summarize(ctx, v.best, n, sum, mn, am));
     tm.mark(4);
     if (info) {
-        info->outer_iters = outer + (rc == MAG_OK ? 1 : 0);
-        info->gmres_iters = inner_total;
-        info->shifted = shifted;
-        info->shift = shift;
-        info->resid_inf = best_norm;
-        info->magnitude = hs[2];
-        info->min_w = hs[3];
-        info->argmin_w = (int64_t)hs[4];
+        info->outer_iters = st.outer;
+        info->gmres_iters = st.inner;
+        info->shifted = F.shifted;
+        info->shift = F.shift;
+        info->resid_inf = st.resid;
+        info->magnitude = sum;
+        info->min_w = mn;
+        info->argmin_w = am;
         if (o.profile) {
             info->ms_tilegen = tm.ms(0, 1);
             info->ms_factor = tm.ms(1, 2);
@@ -387,6 +489,88 @@ int solve_fp64_dense(mag_ctx *ctx, const double *X, int64_t n, int m, double t, 
     return MAG_OK;
 }
 
+
+// dw/dt = Z^{-1} (D o Z) w with the factor F of Z(t) (differentiating
+// eq. weighting in t).  w, out: device npad vectors.  Uses ctx->vecs.
+int dwdt_with_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const Factor32 &F,
+                     const double *w, double *out, const mag_opts &o, RefineStats &st)
+{
+    hipStream_t s = ctx->stream;
+    double *aux = (double *)ctx->aux.p;  // [0, npad): (D o Z) w
+    double *partial = (double *)ctx->partial.p;
+    launch_dzmv(s, X, n, m, t, w, aux, partial);
+    double *amax = aux + 4 * F.npad;  // scalar slot after the four aux vectors
+    launch_amax(s, aux, F.npad, partial, amax);
+    HIPCHK(hipMemcpyAsync(ctx->host_scalars + 40, amax, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return refine_solve(ctx, X, n, m, t, F, aux, ctx->host_scalars[40], out, o, st);
+}
+
+int ensure_aux(mag_ctx *ctx, int64_t npad)
+{
+    return ensure(ctx, ctx->aux, sizeof(double) * ((size_t)npad * 4 + 64));
+}
+
+}  // namespace
+
+struct mag_factor {
+    int device = 0;
+    int64_t n = 0;
+    int32_t m = 0;
+    double t = 0.0;
+    Factor32 F;
+};
+
+namespace {
+
+// One weighting solve at scale t for the cutoff search: w into dst (device,
+// npad), returns min w and argmin; optionally dw/dt at argmin.
+struct TEval {
+    double t = 0.0, minw = 0.0, dmin_dt = 0.0;
+    int64_t arg = -1;
+    bool has_deriv = false;
+};
+
+// d(min w)/dt at the point of the last solve, whose factor is still in ctx:
+// (dw/dt)_{argmin} with dw/dt = Z^{-1} (D o Z) w.
+int tplus_deriv(mag_ctx *ctx, const double *X, int64_t n, int m, const mag_opts &o,
+                const double *w, TEval &ev)
+{
+    Factor32 F = ctx_factor(ctx, n);
+    double *d = (double *)ctx->aux.p + 2 * F.npad;
+    RefineStats st2;
+    int rc2 = dwdt_with_factor(ctx, X, n, m, ev.t, F, w, d, o, st2);
+    if (rc2 == MAG_OK || rc2 == MAG_ENOCONV) {
+        HIPCHK(hipMemcpyAsync(ctx->host_scalars + 41, d + ev.arg, sizeof(double),
+                              hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ev.dmin_dt = ctx->host_scalars[41];
+        ev.has_deriv = std::isfinite(ev.dmin_dt);
+    } else if (rc2 != MAG_OK) {
+        return rc2;
+    }
+    return MAG_OK;
+}
+
+int tplus_eval(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const mag_opts &o,
+               bool deriv, double *dst, TEval &ev, int &solves)
+{
+    const int restart = std::max(1, o.gmres_restart);
+    Factor32 F = ctx_factor(ctx, n);
+    CHK(factor_fp32(ctx, X, n, m, t, F, nullptr, nullptr));
+    RefineStats st;
+    int rc = refine_solve(ctx, X, n, m, t, F, nullptr, 1.0, dst, o, st);
+    if (rc != MAG_OK && rc != MAG_ENOCONV) return rc;
+    ++solves;
+    double sum;
+    CHK(summarize(ctx, dst, n, sum, ev.minw, ev.arg));
+    ev.t = t;
+    ev.has_deriv = false;
+    (void)restart;
+    if (deriv) return tplus_deriv(ctx, X, n, m, o, dst, ev);
+    return MAG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -457,7 +641,7 @@ void mag_destroy(mag_ctx *c)
     if (!c) return;
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints})
+    for (DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints, &c->aux})
         if (b->p) hipFree(b->p);
     if (c->blas) rocblas_destroy_handle((rocblas_handle)c->blas);
     if (c->host_scalars) hipHostFree(c->host_scalars);
@@ -623,6 +807,331 @@ int mag_prec_apply(mag_ctx *c, const float *L, const float *dinv, int64_t n, con
     HIPCHK(hipMemcpyAsync(c->host_scalars, ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (((const int *)c->host_scalars)[kStSpinTimeout]) return MAG_EINTERNAL;
+    return MAG_OK;
+}
+
+
+// ---- cutoff search ----------------------------------------------------------
+
+void mag_tplus_opts_default(mag_tplus_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->grid = 32;
+    o->max_extend = 2;
+    o->newton = 1;
+    o->lo_factor = 1e-3;
+    o->rtol = 1e-6;
+    o->eps = 0.0;
+}
+
+int mag_tplus(mag_ctx *c, const double *X, int64_t n, int32_t m, const mag_tplus_opts *topts,
+              const mag_opts *sopts, double *t_plus, double *w_out, mag_tplus_info *info)
+{
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (!c || !X || !t_plus || n < 1 || m < 1) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    mag_tplus_opts to;
+    if (topts) to = *topts;
+    else mag_tplus_opts_default(&to);
+    mag_opts o;
+    if (sopts) o = *sopts;
+    else mag_opts_default(&o);
+    if (to.grid < 2 || !(to.lo_factor > 0.0 && to.lo_factor < 1.0) || !(to.rtol > 0.0)) return MAG_EINVAL;
+    const int restart = std::max(1, o.gmres_restart);
+    CHK(ensure_solver(c, n, m, restart));
+    int rc = check_points(c, X, n, m);
+    if (rc != MAG_OK) return rc;
+    *t_plus = 0.0;
+    if (n <= 2) {
+        // one or two points: w > 0 for every t (w_j = 1/(1 + e^{-td}))
+        if (info) {
+            info->no_sign_change = 1;
+            info->min_w = n == 1 ? 1.0 : 0.5;
+            info->status = MAG_OK;
+        }
+        return MAG_OK;
+    }
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure_ctx_factor(c, n));
+    CHK(ensure_aux(c, npad));
+    double dmin = 0.0;
+    CHK(mag_dmin(c, X, n, m, &dmin));
+    const double tb = std::log((double)(n - 1)) / dmin;
+    const double eps = to.eps > 0.0 ? to.eps : (double)n * std::ldexp(1.0, -53);
+    double *w_hi = (double *)c->aux.p + 3 * npad;  // weighting at the current upper end
+    double *w_cur = (double *)c->aux.p + npad;
+    int solves = 0, newton_steps = 0;
+    TEval lo, hi, cur;
+    bool have_lo = false, have_hi = false;
+    const bool newton = to.newton != 0;
+
+    auto accept_hi = [&](const TEval &e) -> int {
+        hi = e;
+        have_hi = true;
+        launch_copy(c->stream, w_cur, w_hi, npad);
+        return MAG_OK;
+    };
+
+    // optional caller bracket (resume): verify the signs, else fall back to the grid
+    if (to.t_lo > 0.0 && to.t_hi > to.t_lo) {
+        CHK(tplus_eval(c, X, n, m, to.t_hi, o, newton, w_cur, cur, solves));
+        if (cur.minw >= 0.0) {
+            accept_hi(cur);
+            CHK(tplus_eval(c, X, n, m, to.t_lo, o, newton, w_cur, cur, solves));
+            if (cur.minw < 0.0) {
+                lo = cur;
+                have_lo = true;
+            }
+        }
+        if (!have_lo) have_hi = false;
+    }
+    if (!have_lo) {
+        // downward scan of a log grid from the bound (readings: largest sign change)
+        double top = tb;
+        for (int ext = 0; ext <= to.max_extend && !have_lo; ++ext) {
+            for (int i = to.grid - 1; i >= 0; --i) {
+                const double tt = top * std::pow(to.lo_factor, (double)(to.grid - 1 - i) / (to.grid - 1));
+                if (have_hi && tt >= hi.t) continue;
+                CHK(tplus_eval(c, X, n, m, tt, o, false, w_cur, cur, solves));
+                if (cur.minw < 0.0) {
+                    lo = cur;
+                    have_lo = true;
+                    break;
+                }
+                accept_hi(cur);
+                if (cur.minw < eps && cur.minw >= 0.0 && ext == 0 && i == to.grid - 1) {
+                    // w already at the halting threshold at the bound
+                }
+            }
+            top *= to.lo_factor;
+        }
+    }
+    if (!have_lo) {
+        if (info) {
+            info->no_sign_change = 1;
+            info->t_bound = tb;
+            info->d_min = dmin;
+            info->min_w = have_hi ? hi.minw : 0.0;
+            info->solves = solves;
+            info->status = MAG_OK;
+        }
+        return MAG_OK;
+    }
+    // refine the bracket [lo, hi]: safeguarded Newton in log t inside bisection.
+    // The last evaluated point is lo, whose factor is still in the context, so
+    // its derivative costs one refinement solve rather than a factorisation.
+    TEval last = lo;
+    if (newton) {
+        CHK(tplus_deriv(c, X, n, m, o, w_cur, last));
+        lo = last;
+    }
+    bool prev_newton = false;
+    double prev_step = INFINITY;
+    int guard = 0;
+    while ((hi.t - lo.t) / hi.t > to.rtol && guard++ < 200) {
+        const double slo = std::log(lo.t), shi = std::log(hi.t);
+        const double mid = 0.5 * (slo + shi);
+        double sc = mid;
+        bool use_newton = false;
+        if (newton && last.has_deriv && last.dmin_dt != 0.0) {
+            // g(s) = min w(e^s), g'(s) = t * d(min w)/dt
+            const double sl = std::log(last.t);
+            const double sn = sl - last.minw / (last.t * last.dmin_dt);
+            const double step = std::fabs(sn - sl);
+            if (sn > slo && sn < shi && (!prev_newton || step <= 0.5 * prev_step)) {
+                sc = sn;
+                use_newton = true;
+                prev_step = step;
+                // next to a bracket end: step just past the predicted root so
+                // that the bracket closes to rtol
+                const double close = 0.25 * to.rtol;
+                if (sc - slo < close) sc = std::min(slo + 0.75 * to.rtol, mid);
+                if (shi - sc < close) sc = std::max(shi - 0.75 * to.rtol, mid);
+            }
+        }
+        prev_newton = use_newton;
+        if (!use_newton) prev_step = INFINITY;
+        const double tc = std::exp(sc);
+        if (!(tc > lo.t && tc < hi.t)) break;
+        CHK(tplus_eval(c, X, n, m, tc, o, newton, w_cur, cur, solves));
+        if (use_newton) ++newton_steps;
+        last = cur;
+        if (cur.minw < 0.0) {
+            lo = cur;
+        } else {
+            accept_hi(cur);
+            if (cur.minw < eps) break;  // halting rule: 0 <= min w < eps
+        }
+    }
+    *t_plus = hi.t;
+    if (w_out) {
+        launch_copy(c->stream, w_hi, w_out, n);
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    if (info) {
+        info->t_plus = hi.t;
+        info->t_bound = tb;
+        info->d_min = dmin;
+        info->min_w = hi.minw;
+        info->t_bracket_lo = lo.t;
+        info->t_bracket_hi = hi.t;
+        info->solves = solves;
+        info->newton_steps = newton_steps;
+        info->no_sign_change = 0;
+        info->status = MAG_OK;
+    }
+    return MAG_OK;
+}
+
+int mag_dwdt(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, double *w, double *dwdt,
+             const mag_opts *opts)
+{
+    if (!c || !dwdt || !valid_args(X, n, m, t)) return MAG_EINVAL;
+    if (m > pair_max_dim()) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    mag_opts o;
+    if (opts) o = *opts;
+    else mag_opts_default(&o);
+    const int restart = std::max(1, o.gmres_restart);
+    CHK(ensure_solver(c, n, m, restart));
+    CHK(check_points(c, X, n, m));
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure_ctx_factor(c, n));
+    CHK(ensure_aux(c, npad));
+    Factor32 F = ctx_factor(c, n);
+    CHK(factor_fp32(c, X, n, m, t, F, nullptr, nullptr));
+    double *wv = (double *)c->aux.p + npad;
+    double *d = (double *)c->aux.p + 2 * npad;
+    RefineStats st;
+    int rc = refine_solve(c, X, n, m, t, F, nullptr, 1.0, wv, o, st);
+    if (rc != MAG_OK) return rc;
+    rc = dwdt_with_factor(c, X, n, m, t, F, wv, d, o, st);
+    if (rc != MAG_OK) return rc;
+    if (w) HIPCHK(hipMemcpyAsync(w, wv, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(dwdt, d, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MAG_OK;
+}
+
+// ---- adjoint ----------------------------------------------------------------
+
+int mag_weighting_fwd(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, double *w,
+                      mag_factor **keep, const mag_opts *opts, mag_info *info)
+{
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (!c || !w || !keep || !valid_args(X, n, m, t)) return MAG_EINVAL;
+    *keep = nullptr;
+    HIPCHK(hipSetDevice(c->device));
+    mag_opts o;
+    if (opts) o = *opts;
+    else mag_opts_default(&o);
+    CHK(ensure_solver(c, n, m, std::max(1, o.gmres_restart)));
+    CHK(check_points(c, X, n, m));
+    mag_factor *f = new mag_factor();
+    f->device = c->device;
+    f->n = n;
+    f->m = m;
+    f->t = t;
+    f->F.npad = round_up(n, kPad);
+    if (hipMalloc((void **)&f->F.A, sizeof(float) * (size_t)f->F.npad * f->F.npad) != hipSuccess ||
+        hipMalloc((void **)&f->F.dinv, sizeof(float) * (size_t)f->F.npad * kTile) != hipSuccess) {
+        (void)hipGetLastError();
+        mag_factor_free(f);
+        return MAG_ENOMEM;
+    }
+    int rc;
+    if (n == 1) {
+        launch_fill(c->stream, w, 1, 1.0);
+        HIPCHK(hipStreamSynchronize(c->stream));
+        // factor of [1] padded with identity: build it through the normal path
+        rc = factor_fp32(c, X, n, m, t, f->F, nullptr, nullptr);
+        if (info) {
+            info->magnitude = 1.0;
+            info->min_w = 1.0;
+        }
+    } else {
+        rc = solve_fp32_ir(c, X, n, m, t, w, o, info, &f->F);
+    }
+    if (info) info->status = rc;
+    if (rc != MAG_OK) {
+        mag_factor_free(f);
+        return rc;
+    }
+    *keep = f;
+    return MAG_OK;
+}
+
+int mag_weighting_vjp(mag_ctx *c, mag_factor *f, const double *X, int64_t n, int32_t m, double t,
+                      const double *w, double gM, const double *gw, double *dX, double *dt,
+                      const mag_opts *opts)
+{
+    if (!c || !f || !w || !valid_args(X, n, m, t)) return MAG_EINVAL;
+    if (f->n != n || f->m != m || f->t != t || f->device != c->device) return MAG_EINVAL;
+    if (m > pair_max_dim()) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    mag_opts o;
+    if (opts) o = *opts;
+    else mag_opts_default(&o);
+    hipStream_t s = c->stream;
+    const int64_t npad = f->F.npad;
+    CHK(ensure_solver(c, n, m, std::max(1, o.gmres_restart)));
+    CHK(ensure_aux(c, npad));
+    double *aux = (double *)c->aux.p;
+    double *u = aux;              // (D o Z) w
+    double *lam = aux + npad;     // lambda
+    double *wv = aux + 2 * npad;  // w padded
+    double *rhs = aux + 3 * npad;
+    double *partial = (double *)c->partial.p;
+    launch_scale(s, w, 1.0, wv, n, npad);
+    if (gw) {
+        // lambda = Z^{-1} (gM 1 + gw), with the kept factor
+        launch_affine_ones(s, gw, gM, rhs, n, npad);
+        double *amax = (double *)c->partial.p + blas1_partial_doubles(3) + 8;
+        launch_amax(s, rhs, npad, partial, amax);
+        HIPCHK(hipMemcpyAsync(c->host_scalars + 42, amax, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        RefineStats st;
+        int rc = refine_solve(c, X, n, m, t, f->F, rhs, c->host_scalars[42], lam, o, st);
+        if (rc != MAG_OK) return rc;
+    } else {
+        launch_scale(s, wv, gM, lam, n, npad);  // lambda = gM w
+    }
+    if (dt) {
+        launch_dzmv(s, X, n, m, t, wv, u, partial);
+        double *h = (double *)c->partial.p + blas1_partial_doubles(3) + 16;
+        launch_multidot(s, u, npad, 1, lam, npad, partial, h);
+        HIPCHK(hipMemcpyAsync(c->host_scalars + 43, h, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (dX) launch_gradx(s, X, n, m, t, wv, lam, dX, partial);
+    HIPCHK(hipStreamSynchronize(s));
+    if (dt) *dt = c->host_scalars[43];
+    return MAG_OK;
+}
+
+void mag_factor_free(mag_factor *f)
+{
+    if (!f) return;
+    hipSetDevice(f->device);
+    if (f->F.A) hipFree(f->F.A);
+    if (f->F.dinv) hipFree(f->F.dinv);
+    delete f;
+}
+
+int mag_dzmatvec(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, const double *v,
+                 double *y)
+{
+    if (!c || !v || !y || !valid_args(X, n, m, t)) return MAG_EINVAL;
+    if (m > pair_max_dim()) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    CHK(ensure_solver(c, n, m, 1));
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure_aux(c, npad));
+    double *aux = (double *)c->aux.p;
+    launch_scale(c->stream, v, 1.0, aux + npad, n, npad);
+    launch_dzmv(c->stream, X, n, m, t, aux + npad, aux, (double *)c->partial.p);
+    HIPCHK(hipMemcpyAsync(y, aux, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return MAG_OK;
 }
 

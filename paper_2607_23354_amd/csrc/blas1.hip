@@ -171,6 +171,49 @@ __global__ void k_summin_final(const double *partial, double *out)
     out[2] = am;
 }
 
+__global__ void __launch_bounds__(RB) k_amax_partial(const double *x, int64_t len, double *partial)
+{
+    __shared__ double red[RB];
+    const int64_t chunk = (len + RG - 1) / RG;
+    const int64_t lo = blockIdx.x * chunk, hi = min(len, lo + chunk);
+    double s = 0.0;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) s = fmax(s, fabs(x[e]));
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = RB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(RB) k_amax_final(const double *partial, double *out)
+{
+    __shared__ double red[RB];
+    red[threadIdx.x] = (threadIdx.x < RG) ? partial[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = RB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// y[j] = a + (x ? x[j] : 0) for j < n, 0 for n <= j < len
+__global__ void k_affine_ones(const double *x, double a, double *y, int64_t n, int64_t len)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (i < n) ? a + (x ? x[i] : 0.0) : 0.0;
+}
+
+__global__ void k_scale(const double *x, double a, double *y, int64_t n, int64_t len)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (i < n) ? a * x[i] : 0.0;
+}
+
 inline unsigned grid_for(int64_t len)
 {
     int64_t b = (len + 255) / 256;
@@ -221,6 +264,20 @@ void launch_sum_min(hipStream_t s, const double *x, int64_t n, double *partial, 
 {
     hipLaunchKernelGGL(k_summin_partial, dim3(RG), dim3(RB), 0, s, x, n, partial);
     hipLaunchKernelGGL(k_summin_final, dim3(1), dim3(64), 0, s, partial, out);
+}
+
+void launch_amax(hipStream_t s, const double *x, int64_t len, double *partial, double *out)
+{
+    hipLaunchKernelGGL(k_amax_partial, dim3(RG), dim3(RB), 0, s, x, len, partial);
+    hipLaunchKernelGGL(k_amax_final, dim3(1), dim3(RB), 0, s, partial, out);
+}
+void launch_affine_ones(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len)
+{
+    hipLaunchKernelGGL(k_affine_ones, dim3(grid_for(len)), dim3(256), 0, s, x, a, y, n, len);
+}
+void launch_scale(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len)
+{
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(len)), dim3(256), 0, s, x, a, y, n, len);
 }
 
 size_t blas1_partial_doubles(int kmax) { return (size_t)RG * (size_t)(kmax > 3 ? kmax : 3); }

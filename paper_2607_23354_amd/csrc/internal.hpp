@@ -53,6 +53,7 @@ struct mag_ctx {
     mag::DevBuf vecs;      // FP64 vectors (Krylov basis and work vectors)
     mag::DevBuf partial;   // FP64 partial sums of split reductions
     mag::DevBuf ints;      // int32 counters / flags / status
+    mag::DevBuf aux;       // FP64 vectors of the cutoff search and the adjoint
     double *host_scalars = nullptr;  // pinned host staging (64 doubles)
     void *blas = nullptr;            // rocblas_handle (lazy, FP64 comparator)
     int64_t cu_count = 256;
@@ -74,6 +75,16 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
                    FactorTimer *timer);
 size_t dmin_partial_doubles(int64_t n);
 size_t blas1_partial_doubles(int kmax);
+
+// pairwise.hip: derivative passes (matrix-free FP64)
+int pair_max_dim();
+size_t pair_partial_doubles(int64_t n, int m);
+// y (npad) = (D o Z) v, i.e. -dZ/dt v
+void launch_dzmv(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
+                 double *y, double *partial);
+// dX (n x m) = t sum_{k != j} (lam_j w_k + lam_k w_j) Z_jk (x_j - x_k) / d_jk
+void launch_gradx(hipStream_t s, const double *X, int64_t n, int m, double t, const double *w,
+                  const double *lam, double *dX, double *partial);
 
 // ---- launchers (all enqueue on ctx->stream) --------------------------------
 // tilegen.hip
@@ -128,7 +139,14 @@ void launch_nrm2(hipStream_t s, const double *x, int64_t len, double *partial, d
 void launch_scale_inv(hipStream_t s, const double *x, double *y, int64_t len, const double *alpha);
 // y += x
 void launch_axpy1(hipStream_t s, const double *x, double *y, int64_t len);
-// sum (Neumaier-free, pairwise blocked), min, argmin of x[0..n): out[0]=sum, out[1]=min, out[2]=argmin
+// sum (block sums combined with Neumaier compensation), min, argmin of x[0..n):
+// out[0]=sum, out[1]=min, out[2]=argmin
 void launch_sum_min(hipStream_t s, const double *x, int64_t n, double *partial, double *out);
+// out = max |x_i|
+void launch_amax(hipStream_t s, const double *x, int64_t len, double *partial, double *out);
+// y = a*1 + x on [0, n) (x may be NULL), zero on [n, len)
+void launch_affine_ones(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len);
+// y = a*x on [0, n), zero on [n, len)
+void launch_scale(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len);
 
 }  // namespace mag

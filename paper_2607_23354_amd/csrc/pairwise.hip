@@ -1,0 +1,184 @@
+// pairwise.hip -- matrix-free FP64 passes over all pairs (j, k) for the
+// derivatives of the weighting.  Differentiating Z(t, X) w = 1 (Section 2,
+// eq. weighting) with Z_jk = exp(-t d_jk):
+//   dZ_jk/dt     = -d_jk Z_jk                        -> (D o Z) v  (kDZ)
+//   dZ_jk/dx_j   = -t Z_jk (x_j - x_k) / d_jk        -> gradient   (kGradX)
+// so, with lambda = Z^{-1}(gM 1 + gw):
+//   dL/dt   = lambda^T (D o Z) w
+//   dL/dx_j = t sum_{k != j} (lambda_j w_k + lambda_k w_j) Z_jk (x_j - x_k) / d_jk.
+// Entries are formed exactly as the tile generator forms Z (exact
+// differences, uncontracted squared sum, sqrt, exp(-(t d))).  Same grid as
+// the Z v product: row blocks x column splits, split partials reduced in a
+// fixed order.
+#include "internal.hpp"
+
+#include <cmath>
+
+namespace mag {
+namespace {
+
+constexpr int RT = 256;
+constexpr int CH = 256;
+constexpr int MMAX = 16;  // largest dimension handled by the gradient pass
+
+__device__ inline double sq_acc(double s, double e)
+{
+#pragma clang fp contract(off)
+    double p = e * e;
+    return s + p;
+}
+
+enum { kDZ = 0, kGradX = 1 };
+
+// M > 0: compile-time dimension; M == 0: runtime m <= MMAX.
+template <int MODE, int M>
+__global__ void __launch_bounds__(RT)
+k_pair_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
+               const double *__restrict__ v, const double *__restrict__ lam,
+               double *__restrict__ partial, int64_t cps, int64_t npad)
+{
+    constexpr int MM = (M > 0) ? M : MMAX;
+    __shared__ double Xc[MM * CH];
+    __shared__ double vc[CH];
+    __shared__ double lc[CH];
+    const int m = (M > 0) ? M : m_rt;
+    const int64_t j = (int64_t)blockIdx.x * RT + threadIdx.x;
+    const int64_t c_lo = (int64_t)blockIdx.y * cps;
+    const int64_t c_hi = min(n, c_lo + cps);
+    const bool live = j < n;
+    double xr[MM];
+    double acc[MODE == kGradX ? MM : 1];
+#pragma unroll
+    for (int l = 0; l < MM; ++l) xr[l] = (live && l < m) ? X[j * m + l] : 0.0;
+#pragma unroll
+    for (int l = 0; l < (MODE == kGradX ? MM : 1); ++l) acc[l] = 0.0;
+    const double vj = live ? v[j] : 0.0;
+    const double lj = (MODE == kGradX && live) ? lam[j] : 0.0;
+
+    for (int64_t k0 = c_lo; k0 < c_hi; k0 += CH) {
+        const int cnt = (int)min((int64_t)CH, c_hi - k0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt * m; e += RT) {
+            const int p = e / m, l = e % m;
+            Xc[l * CH + p] = X[(k0 + p) * m + l];
+        }
+        if (threadIdx.x < cnt) {
+            vc[threadIdx.x] = v[k0 + threadIdx.x];
+            if (MODE == kGradX) lc[threadIdx.x] = lam[k0 + threadIdx.x];
+        }
+        __syncthreads();
+        if (!live) continue;
+        for (int c = 0; c < cnt; ++c) {
+            if (k0 + c == j) continue;
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < MM; ++l)
+                if (l < m) s = sq_acc(s, xr[l] - Xc[l * CH + c]);
+            const double d = sqrt(s);
+            const double z = exp(-(t * d));
+            if (MODE == kDZ) {
+                acc[0] = fma(d * z, vc[c], acc[0]);
+            } else {
+                const double coef = t * (lj * vc[c] + lc[c] * vj) * z / d;
+#pragma unroll
+                for (int l = 0; l < MM; ++l)
+                    if (l < m) acc[l] = fma(coef, xr[l] - Xc[l * CH + c], acc[l]);
+            }
+        }
+    }
+    if (j < npad) {
+        if (MODE == kDZ) {
+            partial[(int64_t)blockIdx.y * npad + j] = live ? acc[0] : 0.0;
+        } else {
+#pragma unroll
+            for (int l = 0; l < MM; ++l)
+                if (l < m) partial[((int64_t)blockIdx.y * npad + j) * m + l] = live ? acc[l] : 0.0;
+        }
+    }
+}
+
+// out[e] = sum_s partial[s * stride + e] for e < count (fixed order)
+__global__ void k_split_reduce(const double *__restrict__ partial, int64_t stride, int splits,
+                               int64_t count, double *__restrict__ out)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int q = 0; q < splits; ++q) s += partial[(int64_t)q * stride + e];
+        out[e] = s;
+    }
+}
+
+struct Plan {
+    int64_t rowblocks, splits, cps, npad;
+};
+
+Plan plan_for(int64_t n)
+{
+    Plan p;
+    p.npad = round_up(n, kPad);
+    p.rowblocks = (n + RT - 1) / RT;
+    int64_t s = (2048 + p.rowblocks - 1) / p.rowblocks;
+    int64_t maxs = (n + CH - 1) / CH;
+    if (s > maxs) s = maxs;
+    if (s > 64) s = 64;
+    if (s < 1) s = 1;
+    p.cps = round_up((n + s - 1) / s, CH);
+    p.splits = (n + p.cps - 1) / p.cps;
+    return p;
+}
+
+template <int MODE>
+void launch_mode(hipStream_t s, const Plan &p, dim3 grid, const double *X, int64_t n, int m,
+                 double t, const double *v, const double *lam, double *partial)
+{
+#define MAG_PAIR_CASE(MV)                                                                        \
+    hipLaunchKernelGGL((k_pair_partial<MODE, MV>), grid, dim3(RT), 0, s, X, n, m, t, v, lam,     \
+                       partial, p.cps, p.npad)
+    switch (m) {
+    case 1: MAG_PAIR_CASE(1); break;
+    case 2: MAG_PAIR_CASE(2); break;
+    case 3: MAG_PAIR_CASE(3); break;
+    case 4: MAG_PAIR_CASE(4); break;
+    case 8: MAG_PAIR_CASE(8); break;
+    default: MAG_PAIR_CASE(0); break;
+    }
+#undef MAG_PAIR_CASE
+}
+
+}  // namespace
+
+int pair_max_dim() { return MMAX; }
+
+size_t pair_partial_doubles(int64_t n, int m)
+{
+    Plan p = plan_for(n);
+    return (size_t)(p.splits * p.npad * (m > 1 ? m : 1));
+}
+
+// y (npad) = (D o Z) v
+void launch_dzmv(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
+                 double *y, double *partial)
+{
+    Plan p = plan_for(n);
+    dim3 grid((unsigned)p.rowblocks, (unsigned)p.splits);
+    launch_mode<kDZ>(s, p, grid, X, n, m, t, v, nullptr, partial);
+    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)((p.npad + 255) / 256)), dim3(256), 0, s,
+                       partial, p.npad, (int)p.splits, p.npad, y);
+}
+
+// dX (n x m, row-major) = t sum_{k != j} (lam_j w_k + lam_k w_j) Z_jk (x_j - x_k) / d_jk
+void launch_gradx(hipStream_t s, const double *X, int64_t n, int m, double t, const double *w,
+                  const double *lam, double *dX, double *partial)
+{
+    Plan p = plan_for(n);
+    dim3 grid((unsigned)p.rowblocks, (unsigned)p.splits);
+    launch_mode<kGradX>(s, p, grid, X, n, m, t, w, lam, partial);
+    const int64_t cnt = n * (int64_t)m;
+    int64_t blocks = (cnt + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_split_reduce, dim3((unsigned)blocks), dim3(256), 0, s, partial,
+                       p.npad * m, (int)p.splits, cnt, dX);
+}
+
+}  // namespace mag

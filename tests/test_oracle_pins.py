@@ -374,3 +374,12 @@ def test_gaussian_cutoff_law_loose():
         vals = [oracle.tplus(W.gaussian(c["n"], c["m"], seed=s), rtol=1e-3).t_plus for s in c["seeds"]]
         law = spec["gamma_plus"] * c["m"] ** (-2 / 3) * c["n"] ** 0.25
         assert abs(np.mean(vals) - law) / law < c["rel_tol"], (vals, law)
+
+
+def test_grad_x_rows_matches_full():
+    X = W.gaussian(70, 3, seed=19)
+    t = 0.6
+    dt, dX, s = oracle.grad(X, t)
+    rows = np.array([0, 33, 69])
+    got = oracle.grad_x_rows(X, t, s.w, s.w, rows)
+    assert np.array_equal(got, dX[rows])
