@@ -29,6 +29,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int BT = 128;
 constexpr int KC = 16;
 constexpr int NT = 256;
+constexpr int kXcds = 8;
 
 __device__ inline void tri_index(int64_t idx, int64_t &ti, int64_t &tj)
 {
@@ -54,7 +55,19 @@ k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64
 
     int64_t ti, tj;
     if (lower_only) {
-        tri_index(blockIdx.x, ti, tj);
+        // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by
+        // id, so id % 8 picks the XCD and consecutive ids of one XCD walk the
+        // 64 tiles of one 8 x 8 super-tile of the lower triangle; the 16
+        // operand panels of a super-tile (2 MB at K = 256) stay in that
+        // XCD's L2 while its tiles run.
+        const int64_t b = blockIdx.x;
+        const int64_t xcd = b % kXcds, slot = b / kXcds;
+        const int64_t sidx = (slot / 64) * kXcds + xcd, within = slot % 64;
+        int64_t si, sj;
+        tri_index(sidx, si, sj);
+        ti = si * 8 + within / 8;
+        tj = sj * 8 + within % 8;
+        if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
     } else {
         ti = blockIdx.x % tilesM;
         tj = blockIdx.x / tilesM;
@@ -181,7 +194,13 @@ void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_
 {
     const int64_t tm = M / BT, tn = N / BT;
     if (tm <= 0 || tn <= 0 || K <= 0) return;
-    int64_t blocks = lower_only ? tm * (tm + 1) / 2 : tm * tn;
+    int64_t blocks = tm * tn;
+    if (lower_only) {
+        // super-tiles of 8 x 8 tiles, in groups of kXcds (one per XCD)
+        const int64_t st = (tm + 7) / 8;
+        const int64_t nsup = st * (st + 1) / 2;
+        blocks = ((nsup + kXcds - 1) / kXcds) * kXcds * 64;
+    }
     if (mode == kGemmSub)
         hipLaunchKernelGGL(k_gemm_nt<kGemmSub>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
                            ldp, Q, ldq, tm, K, lower_only ? 1 : 0, CT);

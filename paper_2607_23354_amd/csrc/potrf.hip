@@ -45,9 +45,25 @@ k_potrf128(float *__restrict__ A, int64_t ld, int64_t k0, float *__restrict__ Li
     const int wave = tid >> 6;
     float *Ablk = A + k0 * ld + k0;
 
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int r = e & (NB - 1), c = e >> 7;
-        S[c * LDS_LD + r] = Ablk[(int64_t)c * ld + r];
+    // 16 float4 loads per thread, all in flight before the first LDS store
+    {
+        float4 buf[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e4 = tid + 256 * i;
+            const int c = e4 >> 5, r4 = (e4 & 31) * 4;
+            buf[i] = *reinterpret_cast<const float4 *>(Ablk + (int64_t)c * ld + r4);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e4 = tid + 256 * i;
+            const int c = e4 >> 5, r4 = (e4 & 31) * 4;
+            float *dst = S + c * LDS_LD + r4;
+            dst[0] = buf[i].x;
+            dst[1] = buf[i].y;
+            dst[2] = buf[i].z;
+            dst[3] = buf[i].w;
+        }
     }
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -134,9 +150,16 @@ k_potrf128(float *__restrict__ A, int64_t ld, int64_t k0, float *__restrict__ Li
     }
 
     // write L back (lower triangle including the diagonal) and L^T above it
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int r = e & (NB - 1), c = e >> 7;
-        Ablk[(int64_t)c * ld + r] = (r >= c) ? S[c * LDS_LD + r] : S[r * LDS_LD + c];
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        const int e4 = tid + 256 * i;
+        const int c = e4 >> 5, r4 = (e4 & 31) * 4;
+        float4 v;
+        v.x = (r4 + 0 >= c) ? S[c * LDS_LD + r4 + 0] : S[(r4 + 0) * LDS_LD + c];
+        v.y = (r4 + 1 >= c) ? S[c * LDS_LD + r4 + 1] : S[(r4 + 1) * LDS_LD + c];
+        v.z = (r4 + 2 >= c) ? S[c * LDS_LD + r4 + 2] : S[(r4 + 2) * LDS_LD + c];
+        v.w = (r4 + 3 >= c) ? S[c * LDS_LD + r4 + 3] : S[(r4 + 3) * LDS_LD + c];
+        *reinterpret_cast<float4 *>(Ablk + (int64_t)c * ld + r4) = v;
     }
 
     // inverse, diagonal 32 x 32 blocks: wave w inverts block w; lane%32 = column
