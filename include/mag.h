@@ -189,6 +189,32 @@ int mag_weighting_vjp(mag_ctx *ctx, mag_factor *f, const double *X, int64_t n, i
 
 void mag_factor_free(mag_factor *f);
 
+/* ---- batches of problems of uneven n --------------------------------------
+ * B problems (clouds and scales) solved together: every phase of the solve is
+ * one launch over all problems (device work lists map blocks to problems),
+ * the factorisation's launch sequence is captured once in a hipGraph and
+ * replayed, and the refinement iterates all unconverged problems in
+ * lockstep.  X packs the clouds row-wise (device); offs (HOST, B+1) gives the
+ * row ranges, cloud b = rows [offs[b], offs[b+1]); rows may be shared
+ * (several scales of one cloud).  Every item gives the same result as the
+ * single call up to rounding order. */
+
+/* w (device, packed like X, rows offs[b]-offs[0] ...) receives each weighting,
+ * M (HOST, B, may be NULL) each magnitude, info (HOST, B, may be NULL) each
+ * record.  t: HOST, B scales.  Returns MAG_ENOCONV if any item did not meet
+ * tol (its info says which). */
+int mag_weighting_batch(mag_ctx *ctx, int32_t B, const double *X, const int64_t *offs, int32_t m,
+                        const double *t, double *w, double *M, const mag_opts *opts,
+                        mag_info *info);
+
+/* Cutoff search of mag_tplus for every cloud, the clouds' grid scans and
+ * bracket refinements stepped together.  t_plus (HOST, B) receives each
+ * cutoff (0 when no sign change); w (device, packed, may be NULL) the
+ * weighting at each cutoff; info (HOST, B, may be NULL). */
+int mag_tplus_batch(mag_ctx *ctx, int32_t B, const double *X, const int64_t *offs, int32_t m,
+                    const mag_tplus_opts *topts, const mag_opts *sopts, double *t_plus, double *w,
+                    mag_tplus_info *info);
+
 /* ---- kernel-level entry points --------------------------------------------
  * The steps of the FP32_IR path exposed one by one, for parity tests and
  * profiling.  npad = mag_padded_size(n) = n rounded up to a multiple of 256.

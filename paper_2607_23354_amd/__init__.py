@@ -20,7 +20,8 @@ from ._lib import MagError, MagInfo, MagOpts, MagTplusInfo, MagTplusOpts  # noqa
 
 __all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "tile32",
            "factor32", "prec_apply", "padded_size", "tplus", "dwdt", "dzmatvec",
-           "MagnitudeFn", "weighting_and_magnitude", "MagError", "SOLVERS"]
+           "MagnitudeFn", "weighting_and_magnitude", "weighting_batch", "tplus_batch",
+           "MagError", "SOLVERS"]
 
 SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
            "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR}
@@ -334,3 +335,51 @@ class MagnitudeFn(torch.autograd.Function):
 def weighting_and_magnitude(X: torch.Tensor, t):
     """Differentiable (w, Mag) of eq. weighting (see MagnitudeFn)."""
     return MagnitudeFn.apply(X, t)
+
+
+def _pack(X: torch.Tensor, offs):
+    X = _points(X)
+    offs = [int(o) for o in offs]
+    arr = (ctypes.c_int64 * len(offs))(*offs)
+    return X, offs, arr
+
+
+def weighting_batch(X: torch.Tensor, offs, t, *, ctx: Context | None = None, raise_on_noconv: bool = True,
+                    **opts):
+    """Batched weightings: cloud b is rows [offs[b], offs[b+1]) of X, solved at
+    scale t[b].  Returns (w packed like X, magnitudes list, info list)."""
+    X, offs, arr = _pack(X, offs)
+    B = len(offs) - 1
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    tt = (ctypes.c_double * B)(*[float(v) for v in t])
+    Ms = (ctypes.c_double * B)()
+    infos = (MagInfo * B)()
+    w = torch.empty(offs[-1] - offs[0], dtype=torch.float64, device=X.device)
+    o = make_opts(**opts)
+    rc = c.lib.mag_weighting_batch(c.handle, B, _ptr(X), arr, m, tt, _ptr(w), Ms, ctypes.byref(o), infos)
+    if rc != _lib.MAG_OK and not (rc == _lib.MAG_ENOCONV and not raise_on_noconv):
+        raise MagError(rc, "mag_weighting_batch")
+    return w, list(Ms), [i.as_dict() for i in infos]
+
+
+def tplus_batch(X: torch.Tensor, offs, *, ctx: Context | None = None, grid: int = 32, lo_factor: float = 1e-3,
+                rtol: float = 1e-6, newton: bool = True, max_extend: int = 2, eps: float = 0.0,
+                want_w: bool = False, **opts):
+    """Batched cutoff search over the clouds rows [offs[b], offs[b+1]) of X.
+    Returns (t_plus list, w packed or None, info list)."""
+    X, offs, arr = _pack(X, offs)
+    B = len(offs) - 1
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    to = MagTplusOpts()
+    c.lib.mag_tplus_opts_default(ctypes.byref(to))
+    to.grid, to.lo_factor, to.rtol, to.newton = grid, lo_factor, rtol, 1 if newton else 0
+    to.max_extend, to.eps = max_extend, eps
+    o = make_opts(**opts)
+    tp = (ctypes.c_double * B)()
+    infos = (MagTplusInfo * B)()
+    w = torch.zeros(offs[-1] - offs[0], dtype=torch.float64, device=X.device) if want_w else None
+    _lib.check(c.lib.mag_tplus_batch(c.handle, B, _ptr(X), arr, m, ctypes.byref(to), ctypes.byref(o), tp,
+                                     _ptr(w), infos), "mag_tplus_batch")
+    return list(tp), w, [i.as_dict() for i in infos]

@@ -132,6 +132,12 @@ SIGNATURES = {
     "mag_weighting_vjp": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _d, _vp, _d, _vp, _vp,
                                          ctypes.POINTER(_d), ctypes.POINTER(MagOpts)]),
     "mag_factor_free": (None, [_vp]),
+    "mag_weighting_batch": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_d),
+                                           _vp, ctypes.POINTER(_d), ctypes.POINTER(MagOpts),
+                                           ctypes.POINTER(MagInfo)]),
+    "mag_tplus_batch": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i64), _i32, ctypes.POINTER(MagTplusOpts),
+                                       ctypes.POINTER(MagOpts), ctypes.POINTER(_d), _vp,
+                                       ctypes.POINTER(MagTplusInfo)]),
 }
 
 _lib = None

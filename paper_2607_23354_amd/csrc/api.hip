@@ -46,6 +46,41 @@ int ensure(mag_ctx *ctx, DevBuf &b, size_t bytes)
 
 using namespace mag;
 
+#define HIPCHK0(x)                                  \
+    do {                                            \
+        if ((x) != hipSuccess) return MAG_EHIP;     \
+    } while (0)
+#define CHK0(x)                                     \
+    do {                                            \
+        int rc_ = (x);                              \
+        if (rc_ != MAG_OK) return rc_;              \
+    } while (0)
+
+namespace mag {
+// Validate the coordinates: finite, and no duplicate points (Z would be
+// singular).  One host sync.
+int check_points(mag_ctx *ctx, const double *X, int64_t n, int m)
+{
+    int *status = (int *)ctx->ints.p;
+    CHK0(ensure(ctx, ctx->partial, sizeof(double) * std::max<size_t>(dmin_partial_doubles(n) + 8, 64)));
+    double *partial = (double *)ctx->partial.p;
+    launch_fill_ints(ctx->stream, status, 8, 0);
+    launch_check_finite(ctx->stream, X, n * (int64_t)m, status);
+    double *dmin2 = partial + dmin_partial_doubles(n);
+    if (n >= 2) launch_dmin2(ctx->stream, X, n, m, partial, nullptr, dmin2);
+    HIPCHK0(hipMemcpyAsync(ctx->host_scalars, status, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    if (n >= 2)
+        HIPCHK0(hipMemcpyAsync(ctx->host_scalars + 8, dmin2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK0(hipStreamSynchronize(ctx->stream));
+    const int *hs = (const int *)ctx->host_scalars;
+    if (hs[kStNonFinite]) return MAG_EINVAL;
+    if (n >= 2 && !(ctx->host_scalars[8] > 0.0)) return MAG_ENOTPD;
+    return MAG_OK;
+}
+
+}  // namespace mag
+
+
 #define HIPCHK(x)                                   \
     do {                                            \
         if ((x) != hipSuccess) return MAG_EHIP;     \
@@ -95,27 +130,6 @@ struct Timer {
 bool valid_args(const double *X, int64_t n, int32_t m, double t)
 {
     return X != nullptr && n >= 1 && m >= 1 && std::isfinite(t) && t > 0.0;
-}
-
-// Validate the coordinates: finite, and no duplicate points (Z would be
-// singular).  One host sync.
-int check_points(mag_ctx *ctx, const double *X, int64_t n, int m)
-{
-    int *status = (int *)ctx->ints.p;
-    CHK(ensure(ctx, ctx->partial, sizeof(double) * std::max<size_t>(dmin_partial_doubles(n) + 8, 64)));
-    double *partial = (double *)ctx->partial.p;
-    launch_fill_ints(ctx->stream, status, 8, 0);
-    launch_check_finite(ctx->stream, X, n * (int64_t)m, status);
-    double *dmin2 = partial + dmin_partial_doubles(n);
-    if (n >= 2) launch_dmin2(ctx->stream, X, n, m, partial, nullptr, dmin2);
-    HIPCHK(hipMemcpyAsync(ctx->host_scalars, status, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    if (n >= 2)
-        HIPCHK(hipMemcpyAsync(ctx->host_scalars + 8, dmin2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    const int *hs = (const int *)ctx->host_scalars;
-    if (hs[kStNonFinite]) return MAG_EINVAL;
-    if (n >= 2 && !(ctx->host_scalars[8] > 0.0)) return MAG_ENOTPD;
-    return MAG_OK;
 }
 
 int ensure_common(mag_ctx *ctx, int64_t n, int restart)
@@ -641,8 +655,11 @@ void mag_destroy(mag_ctx *c)
     if (!c) return;
     hipSetDevice(c->device);
     if (c->stream) hipStreamSynchronize(c->stream);
-    for (DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints, &c->aux})
+    for (DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints, &c->aux, &c->bfactor,
+                      &c->bdinv, &c->bvec, &c->bscal, &c->bpartial, &c->bints, &c->bdesc, &c->barena,
+                      &c->bstage})
         if (b->p) hipFree(b->p);
+    if (c->bhost) hipHostFree(c->bhost);
     if (c->blas) rocblas_destroy_handle((rocblas_handle)c->blas);
     if (c->host_scalars) hipHostFree(c->host_scalars);
     if (c->own_stream) hipStreamDestroy(c->own_stream);

@@ -44,34 +44,15 @@ constexpr int TLD = BT + 1;
 constexpr int LDS_FLOATS = (2 * 2 * KC * BT > BT * (64 + 1)) ? 2 * 2 * KC * BT : BT * (64 + 1);
 
 template <int MODE>
-__global__ void __launch_bounds__(NT, 2)
-k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
-          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, int lower_only,
-          float *__restrict__ CT)
+__device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ldc,
+                                               const float *__restrict__ P, int64_t ldp,
+                                               const float *__restrict__ Q, int64_t ldq,
+                                               int64_t ti, int64_t tj, int64_t K,
+                                               float *__restrict__ CT)
 {
     __shared__ float lds[LDS_FLOATS];
     float (*Ps)[KC][BT] = reinterpret_cast<float (*)[KC][BT]>(lds);
     float (*Qs)[KC][BT] = reinterpret_cast<float (*)[KC][BT]>(lds + 2 * KC * BT);
-
-    int64_t ti, tj;
-    if (lower_only) {
-        // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by
-        // id, so id % 8 picks the XCD and consecutive ids of one XCD walk the
-        // 64 tiles of one 8 x 8 super-tile of the lower triangle; the 16
-        // operand panels of a super-tile (2 MB at K = 256) stay in that
-        // XCD's L2 while its tiles run.
-        const int64_t b = blockIdx.x;
-        const int64_t xcd = b % kXcds, slot = b / kXcds;
-        const int64_t sidx = (slot / 64) * kXcds + xcd, within = slot % 64;
-        int64_t si, sj;
-        tri_index(sidx, si, sj);
-        ti = si * 8 + within / 8;
-        tj = sj * 8 + within % 8;
-        if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
-    } else {
-        ti = blockIdx.x % tilesM;
-        tj = blockIdx.x / tilesM;
-    }
     const int64_t i0 = ti * BT, j0 = tj * BT;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -186,7 +167,89 @@ k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64
     }
 }
 
+template <int MODE>
+__global__ void __launch_bounds__(NT, 2)
+k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
+          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, int lower_only,
+          float *__restrict__ CT)
+{
+    int64_t ti, tj;
+    if (lower_only) {
+        // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by
+        // id, so id % 8 picks the XCD and consecutive ids of one XCD walk the
+        // 64 tiles of one 8 x 8 super-tile of the lower triangle; the 16
+        // operand panels of a super-tile (2 MB at K = 256) stay in that
+        // XCD's L2 while its tiles run.
+        const int64_t b = blockIdx.x;
+        const int64_t xcd = b % kXcds, slot = b / kXcds;
+        const int64_t sidx = (slot / 64) * kXcds + xcd, within = slot % 64;
+        int64_t si, sj;
+        tri_index(sidx, si, sj);
+        ti = si * 8 + within / 8;
+        tj = sj * 8 + within % 8;
+        if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
+    } else {
+        ti = blockIdx.x % tilesM;
+        tj = blockIdx.x / tilesM;
+    }
+    gemm_tile_body<MODE>(C, ldc, P, ldp, Q, ldq, ti, tj, K, CT);
+}
+
+// Batched factorisation updates at panel offset kk of every active problem.
+//   KIND 0: panel TRSM (SetT) of the 128-column sub-panel at kk, in place
+//   KIND 1: update of the next sub-panel's 128 columns by the one at kk
+//   KIND 2: trailing SYRK (lower tiles) by the 256-column panel at kk
+template <int KIND>
+__global__ void __launch_bounds__(NT, 2)
+k_gemm_b(const BProb *__restrict__ Pr, BWork w, int64_t kk)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = Pr[w.plist[i]];
+    if (!q.active) return;
+    const int64_t u = blockIdx.x - w.pref[i];
+    const int64_t np = q.npad;
+    float *A = q.A;
+    if (KIND == 0) {
+        float *A21 = A + kk * np + kk + BT;
+        gemm_tile_body<kGemmSetT>(A21, np, A21, np, q.dinv + (kk / BT) * BT * BT, BT, u, 0, BT,
+                                  A + (kk + BT) * np + kk);
+    } else if (KIND == 1) {
+        const float *Pp = A + kk * np + kk + BT;
+        gemm_tile_body<kGemmSub>(A + (kk + BT) * np + kk + BT, np, Pp, np, Pp, np, u, 0, BT,
+                                 nullptr);
+    } else {
+        int64_t ti, tj;
+        tri_index(u, ti, tj);
+        const float *Pp = A + kk * np + kk + 2 * BT;
+        gemm_tile_body<kGemmSub>(A + (kk + 2 * BT) * np + kk + 2 * BT, np, Pp, np, Pp, np, ti, tj,
+                                 2 * BT, nullptr);
+    }
+}
+
 }  // namespace
+
+// work units per problem of the batched updates (see k_gemm_b)
+int64_t gemm_b_units(int kind, int64_t npad, int64_t kk)
+{
+    if (kind == 0 || kind == 1) {
+        const int64_t rows = npad - kk - BT;
+        return rows > 0 ? rows / BT : 0;
+    }
+    const int64_t rows = npad - kk - 2 * BT;
+    const int64_t T = rows > 0 ? rows / BT : 0;
+    return T * (T + 1) / 2;
+}
+
+void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int64_t kk)
+{
+    if (w.total <= 0) return;
+    if (kind == 0)
+        hipLaunchKernelGGL(k_gemm_b<0>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
+    else if (kind == 1)
+        hipLaunchKernelGGL(k_gemm_b<1>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
+    else
+        hipLaunchKernelGGL(k_gemm_b<2>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
+}
 
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode,

@@ -30,16 +30,16 @@ __device__ inline double sq_acc(double s, double e)
 }
 
 template <int M>
-__global__ void __launch_bounds__(RT)
-k_zmv_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
-              const double *__restrict__ v, double *__restrict__ partial, int64_t cps,
-              int64_t npad)
+__device__ __forceinline__ void zmv_partial_body(const double *__restrict__ X, int64_t n, int m_rt,
+                                                 double t, const double *__restrict__ v,
+                                                 double *__restrict__ partial, int64_t cps,
+                                                 int64_t npad, int64_t bx, int64_t by)
 {
     __shared__ double Xc[MMAX_LDS * CH];
     __shared__ double vc[CH];
     const int m = (M > 0) ? M : m_rt;
-    const int64_t j = (int64_t)blockIdx.x * RT + threadIdx.x;
-    const int64_t c_lo = (int64_t)blockIdx.y * cps;
+    const int64_t j = bx * RT + threadIdx.x;
+    const int64_t c_lo = by * cps;
     const int64_t c_hi = min(n, c_lo + cps);
     const bool live = j < n;
     double acc = 0.0;
@@ -86,18 +86,27 @@ k_zmv_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
             }
         }
     }
-    if (j < npad) partial[(int64_t)blockIdx.y * npad + j] = live ? acc : 0.0;
+    if (j < npad) partial[by * npad + j] = live ? acc : 0.0;
+}
+
+template <int M>
+__global__ void __launch_bounds__(RT)
+k_zmv_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
+              const double *__restrict__ v, double *__restrict__ partial, int64_t cps,
+              int64_t npad)
+{
+    zmv_partial_body<M>(X, n, m_rt, t, v, partial, cps, npad, blockIdx.x, blockIdx.y);
 }
 
 // mode 0: y = sum_s partial;  mode 1: y = b - sum_s partial (b == NULL: ones),
 // and per-block max |y| into blkmax.
-__global__ void __launch_bounds__(256)
-k_zmv_reduce(const double *__restrict__ partial, int64_t npad, int64_t n, int splits,
-             double *__restrict__ y, const double *__restrict__ b, int mode,
-             double *__restrict__ blkmax)
+__device__ __forceinline__ void zmv_reduce_body(const double *__restrict__ partial, int64_t npad,
+                                                int64_t n, int splits, double *__restrict__ y,
+                                                const double *__restrict__ b, int mode,
+                                                double *__restrict__ blkmax, int64_t bx)
 {
     __shared__ double red[256];
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = bx * 256 + threadIdx.x;
     double val = 0.0;
     if (j < npad) {
         double s = 0.0;
@@ -114,8 +123,16 @@ k_zmv_reduce(const double *__restrict__ partial, int64_t npad, int64_t n, int sp
             if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
             __syncthreads();
         }
-        if (threadIdx.x == 0) blkmax[blockIdx.x] = red[0];
+        if (threadIdx.x == 0) blkmax[bx] = red[0];
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_zmv_reduce(const double *__restrict__ partial, int64_t npad, int64_t n, int splits,
+             double *__restrict__ y, const double *__restrict__ b, int mode,
+             double *__restrict__ blkmax)
+{
+    zmv_reduce_body(partial, npad, n, splits, y, b, mode, blkmax, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_max_final(const double *blkmax, int64_t nb, double *out)
@@ -136,19 +153,67 @@ struct Plan {
     int64_t rowblocks, splits, cps, npad;
 };
 
-Plan plan_for(int64_t n)
+__host__ __device__ inline Plan plan_for(int64_t n)
 {
     Plan p;
-    p.npad = round_up(n, kPad);
+    p.npad = (n + kPad - 1) / kPad * kPad;
     p.rowblocks = (n + RT - 1) / RT;
     int64_t s = (2048 + p.rowblocks - 1) / p.rowblocks;
     int64_t maxs = (n + CH - 1) / CH;
     if (s > maxs) s = maxs;
     if (s > 64) s = 64;
     if (s < 1) s = 1;
-    p.cps = round_up((n + s - 1) / s, CH);
+    p.cps = ((n + s - 1) / s + CH - 1) / CH * CH;
     p.splits = (n + p.cps - 1) / p.cps;
     return p;
+}
+
+// Batched Z v: work units of problem p = rowblocks * splits (row block major).
+template <int M>
+__global__ void __launch_bounds__(RT)
+k_zmv_partial_b(const BProb *__restrict__ P, BWork w, int v_slot)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    const Plan pl = plan_for(q.n);
+    const int64_t u = blockIdx.x - w.pref[i];
+    zmv_partial_body<M>(q.X, q.n, q.m, q.t, q.vec + (int64_t)v_slot * q.npad, q.partial, pl.cps,
+                        q.npad, u / pl.splits, u % pl.splits);
+}
+
+// Batched reduce (units = npad/256 per problem); mode 1 writes b - Z v with b
+// from b_slot (b_slot < 0: ones) and per-block maxima after the split partials.
+__global__ void __launch_bounds__(256)
+k_zmv_reduce_b(const BProb *__restrict__ P, BWork w, int y_slot, int b_slot, int mode)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    const Plan pl = plan_for(q.n);
+    const int64_t u = blockIdx.x - w.pref[i];
+    zmv_reduce_body(q.partial, q.npad, q.n, (int)pl.splits, q.vec + (int64_t)y_slot * q.npad,
+                    b_slot >= 0 ? q.vec + (int64_t)b_slot * q.npad : nullptr, mode,
+                    q.partial + pl.splits * q.npad, u);
+}
+
+// Batched max of the block maxima into a scalar slot of each problem.
+__global__ void __launch_bounds__(256) k_max_final_b(const BProb *__restrict__ P, BWork w, int64_t out_off)
+{
+    __shared__ double red[256];
+    const BProb &q = P[w.plist[blockIdx.x]];
+    const Plan pl = plan_for(q.n);
+    const double *blkmax = q.partial + pl.splits * q.npad;
+    const int64_t nb = q.npad / 256;
+    double v = 0.0;
+    for (int64_t e = threadIdx.x; e < nb; e += 256) v = fmax(v, blkmax[e]);
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) q.scal[out_off] = red[0];
 }
 
 }  // namespace
@@ -157,6 +222,33 @@ size_t zmv_partial_doubles(int64_t n)
 {
     Plan p = plan_for(n);
     return (size_t)(p.splits * p.npad + p.npad / 256 + 8);
+}
+
+int64_t zmv_b_units(int64_t n)
+{
+    Plan p = plan_for(n);
+    return p.rowblocks * p.splits;
+}
+
+// Batched y_slot = Z v_slot (mode 0) or y_slot = b - Z v_slot with its max norm
+// into vec[norm_off] (mode 1).  wz: units zmv_b_units(n); wr: units npad/256.
+void launch_zmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const BWork &wr,
+                  int v_slot, int y_slot, int b_slot, int mode, int64_t norm_off)
+{
+    if (wz.na <= 0) return;
+    const dim3 g((unsigned)wz.total);
+    switch (m) {
+    case 1: hipLaunchKernelGGL(k_zmv_partial_b<1>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 2: hipLaunchKernelGGL(k_zmv_partial_b<2>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 3: hipLaunchKernelGGL(k_zmv_partial_b<3>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 4: hipLaunchKernelGGL(k_zmv_partial_b<4>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 8: hipLaunchKernelGGL(k_zmv_partial_b<8>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    default: hipLaunchKernelGGL(k_zmv_partial_b<0>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    }
+    hipLaunchKernelGGL(k_zmv_reduce_b, dim3((unsigned)wr.total), dim3(256), 0, s, P, wr, y_slot,
+                       b_slot, mode);
+    if (mode == 1)
+        hipLaunchKernelGGL(k_max_final_b, dim3(wz.na), dim3(256), 0, s, P, wz, norm_off);
 }
 
 void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,

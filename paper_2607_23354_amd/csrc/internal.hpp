@@ -42,6 +42,80 @@ enum StatusWord : int {
     kStCount = 8
 };
 
+// ---- batched problems --------------------------------------------------------
+// One descriptor per problem of a batch (device array).  A batched launch takes
+// a work list: items i = 0..na-1, problem plist[i], work units
+// [pref[i], pref[i+1]) of the flat block index; bfind() maps a block to its item.
+struct BProb {
+    const double *X;
+    int64_t n, npad;
+    double t;
+    double shift;     // diagonal shift of the FP32 factor (0 unless it broke down)
+    float *A;         // FP32 factor, npad x npad column-major
+    float *dinv;      // inverses of the 128-diagonal blocks
+    double *vec;      // this problem's FP64 vectors: slot j at vec + j * npad
+    double *scal;     // this problem's device scalars
+    double *partial;  // this problem's split-reduction buffer
+    int *ints;        // status [0, 64) and preconditioner counters [64, ...)
+    int32_t m;
+    int32_t active;   // 0: skip (finished)
+};
+
+struct BWork {
+    const int *plist;
+    const int64_t *pref;
+    int na;
+    int64_t total;
+};
+
+__device__ inline int bfind(const int64_t *pref, int na, int64_t u)
+{
+    int lo = 0, hi = na - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- batched launchers (batch.hip drives them) ---------------------------------
+int64_t tilegen32_blocks(int64_t npad);
+void launch_tilegen32_b(hipStream_t s, const BProb *P, const BWork &w);
+void launch_potrf128_b(hipStream_t s, const BProb *P, const BWork &w, int64_t k0);
+int64_t gemm_b_units(int kind, int64_t npad, int64_t kk);
+void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int64_t kk);
+int64_t prec_b_units(int64_t npad);
+void launch_prec_apply_b(hipStream_t s, const BProb *P, const BWork &w, int rhs_slot, int tmp_slot,
+                         int x_slot);
+int64_t zmv_b_units(int64_t n);
+void launch_zmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const BWork &wr, int v_slot,
+                  int y_slot, int b_slot, int mode, int64_t norm_off);
+int64_t dz_b_units(int64_t n);
+void launch_dzmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const BWork &wr, int v_slot,
+                   int y_slot);
+void launch_fill_b(hipStream_t s, const BProb *P, const int *plist, int na, int64_t maxpad, int slot,
+                   double v, bool upto_n);
+void launch_copy_b(hipStream_t s, const BProb *P, const int *plist, int na, int64_t maxpad, int src, int dst);
+void launch_scale_inv_b(hipStream_t s, const BProb *P, const int *plist, int na, int64_t maxpad, int src,
+                        int dst, int64_t scal_off);
+void launch_multidot_b(hipStream_t s, const BProb *P, const int *plist, int na, int v0, int k, int u_slot,
+                       int64_t out_off);
+void launch_multi_axpy_b(hipStream_t s, const BProb *P, const int *plist, int na, int64_t maxpad, int v0,
+                         int k, int64_t h_off, int u_slot, double sign);
+void launch_multi_axpy_hb(hipStream_t s, const BProb *P, const int *plist, int na, int64_t maxpad, int v0,
+                          int k, const double *hb, int u_slot, double sign);
+void launch_nrm2_b(hipStream_t s, const BProb *P, const int *plist, int na, int slot, int64_t out_off);
+void launch_summin_b(hipStream_t s, const BProb *P, const int *plist, int na, int slot, int64_t out_off);
+void launch_amax_b(hipStream_t s, const BProb *P, const int *plist, int na, int slot, int64_t out_off);
+void launch_gather_scal_b(hipStream_t s, const BProb *P, const int *plist, int na, int64_t off, int cnt,
+                          double *out);
+void launch_pick_b(hipStream_t s, const BProb *P, const int *plist, int na, int slot, int64_t idx_off,
+                   int64_t dst);
+void launch_zero_status_b(hipStream_t s, const BProb *P, const int *plist, int na);
+void launch_unpack_b(hipStream_t s, const BProb *P, const int *plist, int na, const int64_t *offs, int slot,
+                     double *out, int64_t maxn);
+
 }  // namespace mag
 
 struct mag_ctx {
@@ -54,6 +128,10 @@ struct mag_ctx {
     mag::DevBuf partial;   // FP64 partial sums of split reductions
     mag::DevBuf ints;      // int32 counters / flags / status
     mag::DevBuf aux;       // FP64 vectors of the cutoff search and the adjoint
+    // batched solves
+    mag::DevBuf bfactor, bdinv, bvec, bscal, bpartial, bints, bdesc, barena, bstage;
+    void *bhost = nullptr;   // pinned host staging for work lists and descriptors
+    size_t bhost_bytes = 0;
     double *host_scalars = nullptr;  // pinned host staging (64 doubles)
     void *blas = nullptr;            // rocblas_handle (lazy, FP64 comparator)
     int64_t cu_count = 256;
@@ -63,6 +141,8 @@ namespace mag {
 
 // Grow `b` to at least `bytes` (frees the old block; contents are lost).
 int ensure(mag_ctx *ctx, DevBuf &b, size_t bytes);
+// Coordinates finite and pairwise distinct (else MAG_EINVAL / MAG_ENOTPD); one host sync.
+int check_points(mag_ctx *ctx, const double *X, int64_t n, int m);
 
 // Event pairs around the trailing-update launches of a factorisation, with
 // the algorithmic flops of each launch.

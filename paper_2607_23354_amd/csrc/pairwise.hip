@@ -32,18 +32,19 @@ enum { kDZ = 0, kGradX = 1 };
 
 // M > 0: compile-time dimension; M == 0: runtime m <= MMAX.
 template <int MODE, int M>
-__global__ void __launch_bounds__(RT)
-k_pair_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
-               const double *__restrict__ v, const double *__restrict__ lam,
-               double *__restrict__ partial, int64_t cps, int64_t npad)
+__device__ __forceinline__ void pair_partial_body(const double *__restrict__ X, int64_t n, int m_rt,
+                                                  double t, const double *__restrict__ v,
+                                                  const double *__restrict__ lam,
+                                                  double *__restrict__ partial, int64_t cps,
+                                                  int64_t npad, int64_t bx, int64_t by)
 {
     constexpr int MM = (M > 0) ? M : MMAX;
     __shared__ double Xc[MM * CH];
     __shared__ double vc[CH];
     __shared__ double lc[CH];
     const int m = (M > 0) ? M : m_rt;
-    const int64_t j = (int64_t)blockIdx.x * RT + threadIdx.x;
-    const int64_t c_lo = (int64_t)blockIdx.y * cps;
+    const int64_t j = bx * RT + threadIdx.x;
+    const int64_t c_lo = by * cps;
     const int64_t c_hi = min(n, c_lo + cps);
     const bool live = j < n;
     double xr[MM];
@@ -88,13 +89,22 @@ k_pair_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
     }
     if (j < npad) {
         if (MODE == kDZ) {
-            partial[(int64_t)blockIdx.y * npad + j] = live ? acc[0] : 0.0;
+            partial[by * npad + j] = live ? acc[0] : 0.0;
         } else {
 #pragma unroll
             for (int l = 0; l < MM; ++l)
-                if (l < m) partial[((int64_t)blockIdx.y * npad + j) * m + l] = live ? acc[l] : 0.0;
+                if (l < m) partial[(by * npad + j) * m + l] = live ? acc[l] : 0.0;
         }
     }
+}
+
+template <int MODE, int M>
+__global__ void __launch_bounds__(RT)
+k_pair_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
+               const double *__restrict__ v, const double *__restrict__ lam,
+               double *__restrict__ partial, int64_t cps, int64_t npad)
+{
+    pair_partial_body<MODE, M>(X, n, m_rt, t, v, lam, partial, cps, npad, blockIdx.x, blockIdx.y);
 }
 
 // out[e] = sum_s partial[s * stride + e] for e < count (fixed order)
@@ -113,19 +123,46 @@ struct Plan {
     int64_t rowblocks, splits, cps, npad;
 };
 
-Plan plan_for(int64_t n)
+__host__ __device__ inline Plan plan_for(int64_t n)
 {
     Plan p;
-    p.npad = round_up(n, kPad);
+    p.npad = (n + kPad - 1) / kPad * kPad;
     p.rowblocks = (n + RT - 1) / RT;
     int64_t s = (2048 + p.rowblocks - 1) / p.rowblocks;
     int64_t maxs = (n + CH - 1) / CH;
     if (s > maxs) s = maxs;
     if (s > 64) s = 64;
     if (s < 1) s = 1;
-    p.cps = round_up((n + s - 1) / s, CH);
+    p.cps = ((n + s - 1) / s + CH - 1) / CH * CH;
     p.splits = (n + p.cps - 1) / p.cps;
     return p;
+}
+
+// Batched (D o Z) v: units rowblocks * splits per problem, then a reduce over
+// the splits (units npad/256 per problem).
+template <int M>
+__global__ void __launch_bounds__(RT) k_dz_partial_b(const BProb *__restrict__ P, BWork w, int v_slot)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    const Plan pl = plan_for(q.n);
+    const int64_t u = blockIdx.x - w.pref[i];
+    pair_partial_body<kDZ, M>(q.X, q.n, q.m, q.t, q.vec + (int64_t)v_slot * q.npad, nullptr,
+                              q.partial, pl.cps, q.npad, u / pl.splits, u % pl.splits);
+}
+
+__global__ void __launch_bounds__(256) k_dz_reduce_b(const BProb *__restrict__ P, BWork w, int y_slot)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    const Plan pl = plan_for(q.n);
+    const int64_t j = (blockIdx.x - w.pref[i]) * 256 + threadIdx.x;
+    if (j >= q.npad) return;
+    double s = 0.0;
+    for (int k = 0; k < pl.splits; ++k) s += q.partial[k * q.npad + j];
+    q.vec[(int64_t)y_slot * q.npad + j] = s;
 }
 
 template <int MODE>
@@ -149,6 +186,28 @@ void launch_mode(hipStream_t s, const Plan &p, dim3 grid, const double *X, int64
 }  // namespace
 
 int pair_max_dim() { return MMAX; }
+
+int64_t dz_b_units(int64_t n)
+{
+    Plan p = plan_for(n);
+    return p.rowblocks * p.splits;
+}
+
+void launch_dzmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const BWork &wr,
+                   int v_slot, int y_slot)
+{
+    if (wz.na <= 0) return;
+    const dim3 g((unsigned)wz.total);
+    switch (m) {
+    case 1: hipLaunchKernelGGL(k_dz_partial_b<1>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 2: hipLaunchKernelGGL(k_dz_partial_b<2>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 3: hipLaunchKernelGGL(k_dz_partial_b<3>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 4: hipLaunchKernelGGL(k_dz_partial_b<4>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    case 8: hipLaunchKernelGGL(k_dz_partial_b<8>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    default: hipLaunchKernelGGL(k_dz_partial_b<0>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    }
+    hipLaunchKernelGGL(k_dz_reduce_b, dim3((unsigned)wr.total), dim3(256), 0, s, P, wr, y_slot);
+}
 
 size_t pair_partial_doubles(int64_t n, int m)
 {

@@ -31,9 +31,8 @@ __device__ inline float bcast(float v, int src_lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
 }
 
-__global__ void __launch_bounds__(256)
-k_potrf128(float *__restrict__ A, int64_t ld, int64_t k0, float *__restrict__ Linv,
-           int *__restrict__ status)
+__device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld, int64_t k0,
+                                              float *__restrict__ Linv, int *__restrict__ status)
 {
     __shared__ float S[NB * LDS_LD];    // L, column-major, S[c*LDS_LD + r]
     __shared__ float V[NB * LDS_LD];    // L^{-1}
@@ -210,7 +209,28 @@ k_potrf128(float *__restrict__ A, int64_t ld, int64_t k0, float *__restrict__ Li
     if (tid == 0 && bad != 0) atomicCAS(&status[kStBreakdown], 0, bad);
 }
 
+__global__ void __launch_bounds__(256)
+k_potrf128(float *__restrict__ A, int64_t ld, int64_t k0, float *__restrict__ Linv,
+           int *__restrict__ status)
+{
+    potrf128_body(A, ld, k0, Linv, status);
+}
+
+// Batched: one workgroup per problem whose padded size exceeds k0.
+__global__ void __launch_bounds__(256)
+k_potrf128_b(const BProb *__restrict__ P, BWork w, int64_t k0)
+{
+    const BProb &q = P[w.plist[blockIdx.x]];
+    if (!q.active || k0 >= q.npad) return;
+    potrf128_body(q.A, q.npad, k0, q.dinv + (k0 / NB) * NB * NB, q.ints);
+}
+
 }  // namespace
+
+void launch_potrf128_b(hipStream_t s, const BProb *P, const BWork &w, int64_t k0)
+{
+    if (w.na > 0) hipLaunchKernelGGL(k_potrf128_b, dim3(w.na), dim3(256), 0, s, P, w, k0);
+}
 
 void launch_potrf128(hipStream_t s, float *A, int64_t ld, int64_t k0, float *Linv, int *status)
 {

@@ -77,14 +77,14 @@ __device__ inline void block_sqdist(double (&s)[kPerThread], const double *X, in
     }
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_tilegen32(const double *__restrict__ X, int64_t n, int m, double t, float *__restrict__ A,
-            int64_t npad, float shift)
+__device__ __forceinline__ void tilegen32_body(const double *__restrict__ X, int64_t n, int m,
+                                               double t, float *__restrict__ A, int64_t npad,
+                                               float shift, int64_t blk)
 {
     __shared__ double Sr[kLC * kRows];
     __shared__ double Sc[kLC * kCols];
     int64_t I, Jc;
-    lower_block(blockIdx.x, I, Jc);
+    lower_block(blk, I, Jc);
     const int64_t row0 = I * kRows, col0 = Jc * kCols;
     double s[kPerThread];
     block_sqdist(s, X, n, m, row0, col0, Sr, Sc);
@@ -104,6 +104,23 @@ k_tilegen32(const double *__restrict__ X, int64_t n, int m, double t, float *__r
             v = expf(-(tf * sqrtf((float)s[c])));
         A[k * npad + j] = v;
     }
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_tilegen32(const double *__restrict__ X, int64_t n, int m, double t, float *__restrict__ A,
+            int64_t npad, float shift)
+{
+    tilegen32_body(X, n, m, t, A, npad, shift, blockIdx.x);
+}
+
+// Batched: one launch for every active problem of a batch.
+__global__ void __launch_bounds__(kThreads)
+k_tilegen32_b(const BProb *__restrict__ P, BWork w)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    tilegen32_body(q.X, q.n, q.m, q.t, q.A, q.npad, (float)q.shift, blockIdx.x - w.pref[i]);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -225,5 +242,13 @@ void launch_check_finite(hipStream_t s, const double *X, int64_t count, int *sta
 }
 
 size_t dmin_partial_doubles(int64_t n) { return (size_t)lower_blocks(n); }
+
+int64_t tilegen32_blocks(int64_t npad) { return lower_blocks(npad); }
+
+void launch_tilegen32_b(hipStream_t s, const BProb *P, const BWork &w)
+{
+    if (w.total > 0)
+        hipLaunchKernelGGL(k_tilegen32_b, dim3((unsigned)w.total), dim3(kThreads), 0, s, P, w);
+}
 
 }  // namespace mag

@@ -71,10 +71,10 @@ __device__ inline void publish(int *base, int value)
 // triangle, where the factorisation stored L^T.  Both read a 128-row band of
 // 512-byte column segments per step, the same HBM access pattern.
 template <bool BWD>
-__global__ void __launch_bounds__(256)
-k_trsv(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv,
-       const double *__restrict__ rhs, double *__restrict__ x, int *counters, int nblk,
-       int *status)
+__device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t ld,
+                                          const float *__restrict__ dinv,
+                                          const double *__restrict__ rhs, double *__restrict__ x,
+                                          int *counters, int nblk, int *status)
 {
     __shared__ float Dl[BS * (BS + 1)];  // Dinv_b, row-major with padded stride
     __shared__ double xs[2][BS];
@@ -140,9 +140,49 @@ k_trsv(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv,
     publish(counters + (BWD ? kBwdReady : kFwdReady), nsteps + 1);
 }
 
+template <bool BWD>
+__global__ void __launch_bounds__(256)
+k_trsv(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv,
+       const double *__restrict__ rhs, double *__restrict__ x, int *counters, int nblk,
+       int *status)
+{
+    trsv_body<BWD>(L, ld, dinv, rhs, x, counters, nblk, status);
+}
+
+// Batched: workgroups of problem p take tickets from p's own counters, so the
+// forward-progress argument holds per problem; problems never wait on each other.
+template <bool BWD>
+__global__ void __launch_bounds__(256)
+k_trsv_b(const BProb *__restrict__ P, BWork w, int rhs_slot, int x_slot)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    trsv_body<BWD>(q.A, q.npad, q.dinv, q.vec + (int64_t)rhs_slot * q.npad,
+                   q.vec + (int64_t)x_slot * q.npad, q.ints + 64, (int)(q.npad / BS), q.ints);
+}
+
+__global__ void k_zero_counters_b(const BProb *__restrict__ P, BWork w)
+{
+    const BProb &q = P[w.plist[blockIdx.x]];
+    for (int e = threadIdx.x; e < kCounterInts; e += blockDim.x) q.ints[64 + e] = 0;
+}
+
 }  // namespace
 
 size_t prec_counter_ints() { return kCounterInts; }
+
+int64_t prec_b_units(int64_t npad) { return npad / BS; }
+
+// x_slot = (L L^T)^{-1} rhs_slot for every problem of the work list (units = npad/128 each)
+void launch_prec_apply_b(hipStream_t s, const BProb *P, const BWork &w, int rhs_slot, int tmp_slot,
+                         int x_slot)
+{
+    if (w.na <= 0) return;
+    hipLaunchKernelGGL(k_zero_counters_b, dim3(w.na), dim3(256), 0, s, P, w);
+    hipLaunchKernelGGL(k_trsv_b<false>, dim3((unsigned)w.total), dim3(256), 0, s, P, w, rhs_slot, tmp_slot);
+    hipLaunchKernelGGL(k_trsv_b<true>, dim3((unsigned)w.total), dim3(256), 0, s, P, w, tmp_slot, x_slot);
+}
 
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
                        const double *r, double *y_tmp, double *z, int *counters, int *status)

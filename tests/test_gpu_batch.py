@@ -1,0 +1,85 @@
+"""Batched solves (mag_weighting_batch, mag_tplus_batch): every item against the
+single-call result and the CPU oracle, on clouds of uneven n."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def test_weighting_batch_uneven(mag):
+    clouds = [W.gaussian_mixture(n, 3, seed=s) for s, n in enumerate([300, 1000, 777, 256, 1, 2, 1500])]
+    X, offs = W.pack_clouds(clouds)
+    ts = [30.0, 12.0, 45.0, 5.0, 2.0, 1.0, 25.0]
+    w, Ms, infos = mag.weighting_batch(dev(X), offs, ts)
+    w = w.cpu().numpy()
+    for b, (Xb, t) in enumerate(zip(clouds, ts)):
+        wb = w[offs[b]:offs[b + 1]]
+        assert infos[b]["status"] == 0
+        assert np.abs(oracle.residual(Xb, t, wb)).max() <= 1e-12, b
+        ref = oracle.weighting(Xb, t)
+        assert abs(Ms[b] - ref.M) / abs(ref.M) <= 1e-10
+        single = mag.weighting(dev(Xb), t)
+        ws = single.w.cpu().numpy()
+        assert np.abs(wb - ws).max() <= 1e-12 * max(1.0, np.abs(ws).max())
+        assert infos[b]["argmin_w"] == int(np.argmin(wb))
+
+
+def test_weighting_batch_t_sweep_shared_rows(mag):
+    # several scales of one cloud: items may share rows of X
+    Xc = W.gaussian(900, 3, seed=2)
+    ts = [0.5, 1.0, 2.0, 4.0, 8.0]
+    X = np.concatenate([Xc] * len(ts))
+    offs = np.arange(len(ts) + 1) * 900
+    w, Ms, infos = mag.weighting_batch(dev(X), offs, ts)
+    w = w.cpu().numpy()
+    for b, t in enumerate(ts):
+        ref = oracle.weighting(Xc, t)
+        assert abs(Ms[b] - ref.M) / abs(ref.M) <= 1e-10
+        assert np.abs(oracle.residual(Xc, t, w[900 * b:900 * (b + 1)])).max() <= 1e-12
+
+
+def test_weighting_batch_repeat_deterministic(mag):
+    clouds = [W.gaussian(n, 3, seed=n) for n in (400, 640)]
+    X, offs = W.pack_clouds(clouds)
+    a = mag.weighting_batch(dev(X), offs, [3.0, 3.0])[0].cpu().numpy()
+    b = mag.weighting_batch(dev(X), offs, [3.0, 3.0])[0].cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_tplus_batch_vs_single_and_oracle(mag):
+    clouds = W.mixture_clouds(B=6, m=3, seed=11, n_lo=300, n_hi=900)
+    clouds.append(W.centre_kgon(8, m=3))
+    X, offs = W.pack_clouds(clouds)
+    tps, w, infos = mag.tplus_batch(dev(X), offs, want_w=True)
+    w = w.cpu().numpy()
+    for b, Xb in enumerate(clouds):
+        single = mag.tplus(dev(Xb))
+        assert infos[b]["no_sign_change"] == 0
+        assert abs(tps[b] - single.t_plus) / single.t_plus <= 2.5e-6
+        wb = w[offs[b]:offs[b + 1]]
+        assert wb.min() >= 0
+        assert np.abs(oracle.residual(Xb, tps[b], wb)).max() <= 1e-12
+        if b < 3:
+            ref = oracle.tplus(Xb)
+            assert abs(tps[b] - ref.t_plus) / ref.t_plus <= 2.5e-6
+        print(b, len(Xb), tps[b], infos[b]["solves"], infos[b]["newton_steps"])
+
+
+def test_tplus_batch_no_sign_change_items(mag):
+    rng = np.random.default_rng(4)
+    s_pos = np.linspace(0.0, 1.0, 200) + rng.random(200) * (0.1 / 200)
+    line = np.ascontiguousarray(s_pos[:, None] * np.array([0.6, 0.8, 0.0])[None, :])
+    clouds = [line, np.zeros((1, 3)), W.gaussian_mixture(400, 3, seed=5)]
+    X, offs = W.pack_clouds(clouds)
+    tps, _, infos = mag.tplus_batch(dev(X), offs, max_extend=0)
+    assert infos[0]["no_sign_change"] == 1 and tps[0] == 0.0
+    assert infos[1]["no_sign_change"] == 1 and tps[1] == 0.0
+    assert infos[2]["no_sign_change"] == 0 and tps[2] > 0
