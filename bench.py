@@ -24,6 +24,29 @@ sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
+SYRK_SOURCE = os.path.join(ROOT, "paper_2607_23354_amd", "csrc", "gemm_mfma.hip")
+SYRK_TRAFFIC = os.path.join(ROOT, "profiles", "k_syrk_lower_gaussian_n32768_m3_traffic.txt")
+
+
+def counter_traffic(n):
+    """HBM bytes per launch of the trailing-update kernel, from the committed
+    FETCH_SIZE + WRITE_SIZE counter summary, or None when there is none for
+    this size or the kernel source changed after the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        with open(SYRK_TRAFFIC) as f:
+            for line in f:
+                if ":" in line and not line.startswith((" ", "#", "|")):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        with open(SYRK_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("source_sha256") != sha or int(kv.get("n", -1)) != n:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -39,6 +62,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--check-rows", type=int, default=512)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB before the solves, so a "
+                         "hardware-counter run can scale FETCH_SIZE / WRITE_SIZE by a kernel "
+                         "of known traffic")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -64,6 +91,15 @@ def main():
     Xd = torch.from_numpy(X).to(dev)
     w = torch.empty(n, dtype=torch.float64, device=dev)
     ctx = mag.Context(0)
+
+    if args.copy_calib_mib > 0:
+        nel = args.copy_calib_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(profile=True, solver="fp32_ir"):
         return mag.weighting(Xd, t, ctx=ctx, out=w, solver=solver, profile=profile)
@@ -162,12 +198,12 @@ def main():
                    "seed": args.seed, "solver": "fp32_ir", "parallelism": "single-gpu"},
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_gemm_nt<kGemmSub> (trailing SYRK update, FP32 MFMA 32x32x2)",
+            "kernel": "k_syrk_lower (trailing update A22 -= L21 L21^T, K = 256, FP32 MFMA 32x32x2)",
             "achieved": achieved,
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": (achieved / FP32_MFMA_PEAK_TFLOPS) if achieved else None,
-            "traffic": None,
+            "traffic": counter_traffic(n),
             "launches": n_upd,
             "avg_launch_ms": ms_upd / n_upd if n_upd else None,
         },

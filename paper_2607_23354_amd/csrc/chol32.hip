@@ -33,13 +33,13 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
             if (below > 0) {
                 float *A21 = A + kk * npad + kk + T;
                 float *A12 = A + (kk + T) * npad + kk;  // upper triangle: L21^T
-                launch_gemm_nt(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSetT, false, A12);
+                launch_gemm_nt(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSetT, A12);
             }
             if (sub + 1 < kPanel / T && below > 0) {
                 // update the next sub-panel's columns (rows kk+T ..) with this sub-panel
                 float *C = A + (kk + T) * npad + kk + T;
                 const float *P = A + kk * npad + kk + T;
-                launch_gemm_nt(s, C, npad, P, npad, P, npad, below, T, T, kGemmSub, false);
+                launch_gemm_nt(s, C, npad, P, npad, P, npad, below, T, T, kGemmSub);
             }
         }
         const int64_t trail = npad - k - kPanel;
@@ -62,7 +62,7 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
                 timer->flops.push_back(nt > 0 ? (double)kPanel * (double)nt * (double)(nt + 1) : 0.0);
                 hipEventRecord(e0, s);
             }
-            launch_gemm_nt(s, C, npad, P, npad, P, npad, trail, trail, kPanel, kGemmSub, true);
+            launch_syrk_lower(s, C, npad, P, npad, trail, kPanel);
             if (timer) hipEventRecord(e1, s);
         }
     }

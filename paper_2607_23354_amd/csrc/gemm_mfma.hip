@@ -170,29 +170,32 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
 template <int MODE>
 __global__ void __launch_bounds__(NT, 2)
 k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
-          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, int lower_only,
+          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K,
           float *__restrict__ CT)
 {
-    int64_t ti, tj;
-    if (lower_only) {
-        // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by
-        // id, so id % 8 picks the XCD and consecutive ids of one XCD walk the
-        // 64 tiles of one 8 x 8 super-tile of the lower triangle; the 16
-        // operand panels of a super-tile (2 MB at K = 256) stay in that
-        // XCD's L2 while its tiles run.
-        const int64_t b = blockIdx.x;
-        const int64_t xcd = b % kXcds, slot = b / kXcds;
-        const int64_t sidx = (slot / 64) * kXcds + xcd, within = slot % 64;
-        int64_t si, sj;
-        tri_index(sidx, si, sj);
-        ti = si * 8 + within / 8;
-        tj = sj * 8 + within % 8;
-        if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
-    } else {
-        ti = blockIdx.x % tilesM;
-        tj = blockIdx.x / tilesM;
-    }
+    const int64_t ti = blockIdx.x % tilesM;
+    const int64_t tj = blockIdx.x / tilesM;
     gemm_tile_body<MODE>(C, ldc, P, ldp, Q, ldq, ti, tj, K, CT);
+}
+
+// Trailing symmetric update C -= P P^T on the lower tiles of C only.
+// XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by id, so
+// id % 8 picks the XCD and consecutive ids of one XCD walk the 64 tiles of
+// one 8 x 8 super-tile of the lower triangle; the 16 operand panels of a
+// super-tile (2 MB at K = 256) stay in that XCD's L2 while its tiles run.
+__global__ void __launch_bounds__(NT, 2)
+k_syrk_lower(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
+             int64_t tilesM, int64_t K)
+{
+    const int64_t b = blockIdx.x;
+    const int64_t xcd = b % kXcds, slot = b / kXcds;
+    const int64_t sidx = (slot / 64) * kXcds + xcd, within = slot % 64;
+    int64_t si, sj;
+    tri_index(sidx, si, sj);
+    const int64_t ti = si * 8 + within / 8;
+    const int64_t tj = sj * 8 + within % 8;
+    if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
+    gemm_tile_body<kGemmSub>(C, ldc, P, ldp, P, ldp, ti, tj, K, nullptr);
 }
 
 // Batched factorisation updates at panel offset kk of every active problem.
@@ -253,26 +256,29 @@ void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int6
 
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode,
-                    bool lower_only, float *CT)
+                    float *CT)
 {
     const int64_t tm = M / BT, tn = N / BT;
     if (tm <= 0 || tn <= 0 || K <= 0) return;
-    int64_t blocks = tm * tn;
-    if (lower_only) {
-        // super-tiles of 8 x 8 tiles, in groups of kXcds (one per XCD)
-        const int64_t st = (tm + 7) / 8;
-        const int64_t nsup = st * (st + 1) / 2;
-        blocks = ((nsup + kXcds - 1) / kXcds) * kXcds * 64;
-    }
+    const dim3 g((unsigned)(tm * tn));
     if (mode == kGemmSub)
-        hipLaunchKernelGGL(k_gemm_nt<kGemmSub>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
-                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0, CT);
+        hipLaunchKernelGGL(k_gemm_nt<kGemmSub>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
     else if (mode == kGemmSet)
-        hipLaunchKernelGGL(k_gemm_nt<kGemmSet>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
-                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0, CT);
+        hipLaunchKernelGGL(k_gemm_nt<kGemmSet>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
     else
-        hipLaunchKernelGGL(k_gemm_nt<kGemmSetT>, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P,
-                           ldp, Q, ldq, tm, K, lower_only ? 1 : 0, CT);
+        hipLaunchKernelGGL(k_gemm_nt<kGemmSetT>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+}
+
+void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
+                       int64_t N, int64_t K)
+{
+    const int64_t tm = N / BT;
+    if (tm <= 0 || K <= 0) return;
+    // super-tiles of 8 x 8 tiles, in groups of kXcds (one per XCD)
+    const int64_t st = (tm + 7) / 8;
+    const int64_t nsup = st * (st + 1) / 2;
+    const int64_t blocks = ((nsup + kXcds - 1) / kXcds) * kXcds * 64;
+    hipLaunchKernelGGL(k_syrk_lower, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P, ldp, tm, K);
 }
 
 }  // namespace mag

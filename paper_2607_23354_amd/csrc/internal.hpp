@@ -178,13 +178,14 @@ void launch_check_finite(hipStream_t s, const double *X, int64_t count, int *sta
 
 // gemm_mfma.hip: C (M x N) = [C] - P * Q^T or C = P * Q^T, column-major operands.
 // P is M x K (P[p*ldp + i]), Q is N x K (Q[p*ldq + j]); M, N multiples of 128,
-// K multiple of 16.  lower_only skips tiles with tile_col > tile_row (C
-// assumed square-aligned, i.e. diagonal tiles at equal tile indices).
-// kGemmSetT also writes C^T to CT (CT(j, i) at CT[i * ldc + j]).
+// K multiple of 16.  kGemmSetT also writes C^T to CT (CT(j, i) at CT[i * ldc + j]).
 enum GemmMode { kGemmSub = 0, kGemmSet = 1, kGemmSetT = 2 };
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K,
-                    GemmMode mode, bool lower_only, float *CT = nullptr);
+                    GemmMode mode, float *CT = nullptr);
+// C (N x N, lower 128-tiles only) -= P P^T with P N x K; N multiple of 128.
+void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
+                       int64_t N, int64_t K);
 
 // potrf.hip: factor the 128 x 128 diagonal block at (k0, k0) of A in place and
 // write its inverse to Linv (128 x 128 column-major).  Breakdown -> status.
