@@ -57,10 +57,14 @@ int mag_set_stream(mag_ctx *ctx, void *hip_stream);
 
 /* ---- options and diagnostics --------------------------------------------- */
 enum {
-    MAG_AUTO = 0,        /* MAG_FP32_IR                                                  */
+    MAG_AUTO = 0,        /* MAG_FP32_IR when its FP32 npad^2 factor fits in 3/4 of the    *
+                          * device memory, else MAG_HODLR                                */
     MAG_FP64_DENSE = 1,  /* FP64 Z in HBM + rocSOLVER dpotrf/dpotrs (dense comparator)   */
     MAG_FP32_IR = 2,     /* FP32 MFMA Cholesky + FP64 GMRES iterative refinement         */
-    MAG_HODLR = 3        /* HODLR preconditioner + FP64 GMRES (largest sizes)            */
+    MAG_HODLR = 3        /* HODLR preconditioner + FP64 GMRES (largest sizes, Sec. 3.2): *
+                          * points reordered by recursive coordinate bisection, leaf    *
+                          * blocks exact, sibling blocks Z(I,J) ~ U_I V_J^T sampled     *
+                          * with a Gaussian test matrix; m <= 16                        */
 };
 
 typedef struct {
@@ -69,10 +73,13 @@ typedef struct {
     int32_t gmres_restart; /* Krylov dimension per refinement step, default 30            */
     int32_t max_gmres;     /* total inner iterations over the whole solve, default 200    */
     double tol;            /* target ||1 - Z w||_inf, default 1e-12                       */
-    double inner_tol;      /* relative reduction asked of each inner GMRES, default 1e-8  */
-    int32_t leaf;          /* HODLR leaf size, default 256                                */
-    int32_t max_rank;      /* HODLR off-diagonal rank, default 64                         */
-    int32_t oversample;    /* HODLR sampling oversampling, default 16                     */
+    double inner_tol;      /* relative reduction asked of each inner GMRES, default 1e-10 */
+    int32_t leaf;          /* HODLR largest leaf, 2..128, default 128 (else MAG_EINVAL)   */
+    int32_t max_rank;      /* HODLR rank of the top level's sibling blocks, default 256;  *
+                            * level l samples max_rank 2^{-l/2} + oversample columns,     *
+                            * rounded up to a multiple of 64 within [64, 512] and the     *
+                            * smaller child's size                                        */
+    int32_t oversample;    /* HODLR extra sample columns, default 16                      */
     int32_t profile;       /* 1: time phases with HIP events (adds a sync per phase)      */
     uint64_t seed;         /* HODLR sampling seed                                          */
 } mag_opts;

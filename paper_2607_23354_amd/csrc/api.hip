@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 namespace mag {
@@ -232,18 +233,20 @@ struct RefineStats {
 // left-preconditioned system (L L^T)^{-1} Z d = (L L^T)^{-1} r.  The best
 // iterate goes to xout (device npad).  Stops when ||b - Z x||_inf <= tol *
 // max(1, ||b||_inf), on stagnation, or at the iteration limits.
-int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const Factor32 &F,
-                 const double *b, double bnorm, double *xout, const mag_opts &o, RefineStats &st)
+// prec(in, out, tmp): out = M^{-1} in for device npad vectors (tmp: npad scratch)
+using PrecFn = std::function<void(const double *, double *, double *)>;
+
+int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64_t npad,
+                const PrecFn &prec, const double *b, double bnorm, double *xout, const mag_opts &o,
+                RefineStats &st)
 {
     hipStream_t s = ctx->stream;
-    const int64_t npad = F.npad;
     const int restart = std::max(1, o.gmres_restart);
     Vecs v;
     CHK(carve_vecs(ctx, npad, restart, v));
     double *partial = (double *)ctx->partial.p;
     int *ints = (int *)ctx->ints.p;
     int *status = ints + kIntStatus;
-    int *counters = ints + kIntCounters;
     double *hs = ctx->host_scalars;
     const double tol = (o.tol > 0 ? o.tol : 1e-12) * std::max(1.0, bnorm);
     const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-10;
@@ -256,7 +259,7 @@ int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, cons
         bb = v.rhs;
     }
     // x0 = M^{-1} b
-    launch_prec_apply(s, F.A, npad, F.dinv, bb, v.ytmp, v.x, counters, status);
+    prec(bb, v.x, v.ytmp);
 
     Gmres G;
     G.restart = restart;
@@ -286,7 +289,7 @@ int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, cons
         if (outer > 0 && rnorm > 0.5 * prev) break;  // stagnation
         if (inner_total >= max_gmres) break;
         // GMRES(restart) on M^{-1} Z d = M^{-1} r, d0 = 0
-        launch_prec_apply(s, F.A, npad, F.dinv, v.r, v.ytmp, v.z, counters, status);
+        prec(v.r, v.z, v.ytmp);
         launch_nrm2(s, v.z, npad, partial, v.dsc + 1);
         HIPCHK(hipMemcpyAsync(hs + 1, v.dsc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -301,7 +304,7 @@ int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, cons
             double *Vk = v.V + (size_t)k * npad;
             double *Vk1 = v.V + (size_t)(k + 1) * npad;
             launch_zmv(s, X, n, m, t, Vk, v.u, nullptr, 0, partial, nullptr);
-            launch_prec_apply(s, F.A, npad, F.dinv, v.u, v.ytmp, Vk1, counters, status);
+            prec(v.u, Vk1, v.ytmp);
             // classical Gram-Schmidt, twice
             launch_multidot(s, v.V, npad, k + 1, Vk1, npad, partial, v.hdev);
             launch_multi_axpy(s, v.V, npad, k + 1, v.hdev, Vk1, npad, -1.0);
@@ -347,6 +350,20 @@ int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, cons
     st.inner = inner_total;
     st.resid = best_norm;
     return rc;
+}
+
+// GMRES-IR with the FP32 Cholesky factor F as the preconditioner (L L^T)^{-1}.
+int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const Factor32 &F,
+                 const double *b, double bnorm, double *xout, const mag_opts &o, RefineStats &st)
+{
+    int *ints = (int *)ctx->ints.p;
+    int *status = ints + kIntStatus;
+    int *counters = ints + kIntCounters;
+    hipStream_t s = ctx->stream;
+    const PrecFn prec = [&](const double *in, double *out, double *tmp) {
+        launch_prec_apply(s, F.A, F.npad, F.dinv, in, tmp, out, counters, status);
+    };
+    return refine_core(ctx, X, n, m, t, F.npad, prec, b, bnorm, xout, o, st);
 }
 
 // sum, min, argmin of w[0..n) -> host
@@ -504,6 +521,62 @@ int solve_fp64_dense(mag_ctx *ctx, const double *X, int64_t n, int m, double t, 
 }
 
 
+// HODLR preconditioner (hodlr.hip) + FP64 GMRES-IR with matrix-free Z v.
+int solve_hodlr(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double *w,
+                const mag_opts &o, mag_info *info)
+{
+    hipStream_t s = ctx->stream;
+    const int restart = std::max(1, o.gmres_restart);
+    const int leaf = o.leaf > 0 ? o.leaf : hodlr_max_leaf();
+    if (leaf < 2 || leaf > hodlr_max_leaf() || m > 16) return MAG_EINVAL;
+    CHK(ensure_solver(ctx, n, m, restart));
+    Timer tm;
+    tm.start(o.profile != 0, s);
+    tm.mark(0);
+    HodlrFactor H;
+    CHK(hodlr_factor(ctx, X, n, m, t, leaf, std::max(0, o.max_rank), std::max(0, o.oversample), o.seed, H));
+    tm.mark(1);
+    tm.mark(2);
+    Vecs v;
+    CHK(carve_vecs(ctx, H.npad, restart, v));
+    const PrecFn prec = [&](const double *in, double *out, double *) { hodlr_apply(s, H, in, out); };
+    RefineStats st;
+    int rc = refine_core(ctx, X, n, m, t, H.npad, prec, nullptr, 1.0, v.best, o, st);
+    if (rc != MAG_OK && rc != MAG_ENOCONV) return rc;
+    tm.mark(3);
+    launch_copy(s, v.best, w, n);
+    double sum, mn;
+    int64_t am;
+    CHK(summarize(ctx, v.best, n, sum, mn, am));
+    tm.mark(4);
+    if (info) {
+        info->outer_iters = st.outer;
+        info->gmres_iters = st.inner;
+        info->resid_inf = st.resid;
+        info->magnitude = sum;
+        info->min_w = mn;
+        info->argmin_w = am;
+        if (o.profile) {
+            info->ms_tilegen = 0.0;
+            info->ms_factor = tm.ms(0, 1);
+            info->ms_refine = tm.ms(2, 3);
+            info->ms_total = tm.ms(0, 4);
+        }
+    }
+    return rc;
+}
+
+// MAG_AUTO: the dense FP32 factor when its npad^2 floats fit in three quarters
+// of the device memory (counting what this context already holds for it),
+// else the HODLR preconditioner.
+bool auto_dense(mag_ctx *ctx, int64_t n)
+{
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return true;
+    const double npad = (double)round_up(n, kPad);
+    return 4.0 * npad * npad <= 0.75 * ((double)fr + (double)ctx->factor.bytes);
+}
+
 // dw/dt = Z^{-1} (D o Z) w with the factor F of Z(t) (differentiating
 // eq. weighting in t).  w, out: device npad vectors.  Uses ctx->vecs.
 int dwdt_with_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const Factor32 &F,
@@ -613,8 +686,8 @@ void mag_opts_default(mag_opts *o)
     o->max_gmres = 200;
     o->tol = 1e-12;
     o->inner_tol = 1e-10;
-    o->leaf = 256;
-    o->max_rank = 64;
+    o->leaf = 128;
+    o->max_rank = 256;
     o->oversample = 16;
     o->profile = 0;
     o->seed = 0x9E3779B97F4A7C15ull;
@@ -657,7 +730,7 @@ void mag_destroy(mag_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints, &c->aux, &c->bfactor,
                       &c->bdinv, &c->bvec, &c->bscal, &c->bpartial, &c->bints, &c->bdesc, &c->barena,
-                      &c->bstage})
+                      &c->bstage, &c->hodlr})
         if (b->p) hipFree(b->p);
     if (c->bhost) hipHostFree(c->bhost);
     if (c->blas) rocblas_destroy_handle((rocblas_handle)c->blas);
@@ -710,7 +783,10 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
     } else if (rc == MAG_OK) {
         switch (o.solver) {
         case MAG_FP64_DENSE: rc = solve_fp64_dense(c, X, n, m, t, w, o, info); break;
-        case MAG_AUTO:
+        case MAG_HODLR: rc = solve_hodlr(c, X, n, m, t, w, o, info); break;
+        case MAG_AUTO: rc = auto_dense(c, n) ? solve_fp32_ir(c, X, n, m, t, w, o, info)
+                                             : solve_hodlr(c, X, n, m, t, w, o, info);
+            break;
         case MAG_FP32_IR: rc = solve_fp32_ir(c, X, n, m, t, w, o, info); break;
         default: rc = MAG_EINVAL; break;
         }

@@ -1,0 +1,952 @@
+// hodlr.hip -- hierarchical off-diagonal low-rank (HODLR) preconditioner for
+// Z w = 1 at sizes where a dense factor is not the best tool.
+//
+// Section 3.2 of the paper solves the weighting system with a hierarchical
+// (rank-structured) factorization whose compression step evaluates kernel
+// entries and whose factorization step dominates the time.  This file builds
+// a HODLR approximation H of Z and its inverse in product form; GMRES with the
+// exact FP64 matrix-free Z v (gemv64.hip) then solves Z w = 1 to full
+// accuracy, so H only has to be a good preconditioner.
+//
+// Cluster tree.  Points are ordered by recursive coordinate bisection: each
+// node is split at the median of its widest coordinate (ties by index).  The
+// tree is perfect with L levels (2^l nodes at level l, leaves at level L,
+// every leaf holding at most 128 points); node (l, i) covers the permuted
+// index range [bnd_l[i], bnd_l[i+1]).
+//
+// Off-diagonal blocks.  For node N = (l, i) with children I (left) and J
+// (right), Z(I, J) ~ U_I V_J^T with U_I an orthonormal basis of the sample
+// Z(I, J) Omega (Omega Gaussian with k_l columns) and V_J = Z(J, I) U_I.  Z
+// entries are regenerated in FP64 from the coordinates (exact differences).
+// The basis width k_l is a multiple of 64 that shrinks towards the leaves:
+// across a cut, the points within the kernel's reach of the other side
+// grow with the node, and so does the rank a given accuracy needs.  P_l
+// (n x k_l, row-major) holds U_I on the rows of every left child and V_J on
+// the rows of every right child.
+//
+// Inverse in product form.  With D_N = diag(H_I, H_J),
+//   H_N = D_N (I + Ut_N Vt_N^T),   Ut_N = diag(H_I^{-1} U_I, H_J^{-1} V_J),
+//   Vt_N^T x = [V_J^T x_J ; U_I^T x_I],
+//   H_N^{-1} = (I - Ut_N K_N^{-1} Vt_N^T) D_N^{-1},
+//   K_N = I + Vt_N^T Ut_N = [[I, B], [C, I]],  B = V_J^T H_J^{-1} V_J,  C = U_I^T H_I^{-1} U_I,
+// and K_N^{-1} [s1; s2] = [x1; s2 - C x1] with x1 = (I - B C)^{-1} (s1 - B s2),
+// so only the k x k Schur complement S = I - B C is inverted.  Then
+// H^{-1} = W_0 W_1 ... W_{L-1} D_L^{-1}, W_l the block-diagonal corrections
+// of level l and D_L the exact leaf blocks.  Ph_l holds H_child^{-1} P_l: it
+// starts as D_L^{-1} P_l and receives the corrections of every deeper level,
+// bottom-up.
+//
+// Sampling, Gram and row products, leaf inverses and the apply are kernels of
+// this file; the per-node k x k algebra (Cholesky and triangular inverse of
+// the Gram matrices, the Schur complements and their LU inverses, products of
+// k x k blocks) goes to rocSOLVER / rocBLAS.  Everything is FP64.
+#include "internal.hpp"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+namespace mag {
+namespace {
+
+constexpr int SL = 64;      // slab / tile width of every basis
+constexpr int KMAXC = 8;    // widest basis: KMAXC * SL columns
+constexpr int LMAX = 128;   // largest leaf
+constexpr int MMAXH = 16;   // largest point dimension
+constexpr int ZR = 64;      // rows per sampling workgroup
+constexpr int ZC = 64;      // points per sampling column chunk
+constexpr int NT = 256;     // threads per workgroup
+
+__device__ inline double sq_acc(double s, double e)
+{
+#pragma clang fp contract(off)
+    double p = e * e;
+    return s + p;
+}
+
+// SplitMix64 output function (Steele, Lea and Flood, 2014).
+__host__ __device__ inline uint64_t mix64(uint64_t z)
+{
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Omega (n x ld): N(0, 1) entries (Box-Muller on two hashed uniforms) in the
+// first kcols columns, zero in the rest.
+__global__ void __launch_bounds__(NT) k_omega(double *__restrict__ Om, int64_t n, int ld, int kcols,
+                                              uint64_t seed)
+{
+    const int64_t total = n * ld;
+    for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+        const int c = (int)(e % ld);
+        double v = 0.0;
+        if (c < kcols) {
+            const uint64_t h1 = mix64(seed ^ mix64(2 * (uint64_t)e));
+            const uint64_t h2 = mix64(seed ^ mix64(2 * (uint64_t)e + 1));
+            const double u1 = (double)((h1 >> 11) + 1) * 0x1.0p-53;  // (0, 1]
+            const double u2 = (double)(h2 >> 11) * 0x1.0p-53;        // [0, 1)
+            v = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+        }
+        Om[e] = v;
+    }
+}
+
+// Sampling product over the sibling pairs of one level, 64-column slab
+// blockIdx.y of B and out (both n x ld, row-major):
+//   out[r, slab] = sum_{c in C} Z(r, c) B[c, slab]   for r in R,
+// mode 0: R = left child, C = right child;  mode 1: R = right, C = left.
+// bnd: bounds of the children level (2 * tasks + 1 entries).  One workgroup
+// per 64-row block of R and slab; Z is formed 64 x 64 at a time in LDS.
+__global__ void __launch_bounds__(NT)
+k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restrict__ bnd, int mode,
+         int rbmax, const double *B, double *out, int ld)
+{
+    __shared__ double Bs[ZC][SL];
+    __shared__ double Zs[ZR][ZC + 1];
+    __shared__ double Xc[MMAXH][ZC];
+    const int task = blockIdx.x / rbmax, rb = blockIdx.x % rbmax;
+    const int col0 = blockIdx.y * SL;
+    const int64_t a = bnd[2 * task], b = bnd[2 * task + 1], c = bnd[2 * task + 2];
+    const int64_t rlo = mode ? b : a, rhi = mode ? c : b;
+    const int64_t clo = mode ? a : b, chi = mode ? b : c;
+    const int64_t r0 = rlo + (int64_t)rb * ZR;
+    if (r0 >= rhi) return;  // uniform per workgroup
+    const int nr = (int)min((int64_t)ZR, rhi - r0);
+    const int tid = threadIdx.x;
+    const int gr = tid & 63, gp = tid >> 6;  // Z-tile generation: row, 16-point group
+    const int ty = tid >> 4, tx = tid & 15;  // accumulation: rows 4ty.., columns 4tx..
+    double xr[MMAXH];
+#pragma unroll
+    for (int l = 0; l < MMAXH; ++l) xr[l] = (l < m && gr < nr) ? Xp[(r0 + gr) * m + l] : 0.0;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+
+    for (int64_t c0 = clo; c0 < chi; c0 += ZC) {
+        const int cnt = (int)min((int64_t)ZC, chi - c0);
+        __syncthreads();
+        for (int e = tid; e < ZC * SL; e += NT) {
+            const int p = e / SL, q = e % SL;
+            Bs[p][q] = (p < cnt) ? B[(c0 + p) * ld + col0 + q] : 0.0;
+        }
+        for (int e = tid; e < m * ZC; e += NT) {
+            const int l = e / ZC, p = e % ZC;
+            Xc[l][p] = (p < cnt) ? Xp[(c0 + p) * m + l] : 0.0;
+        }
+        __syncthreads();
+        for (int q = 0; q < 16; ++q) {
+            const int p = gp * 16 + q;
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < MMAXH; ++l)
+                if (l < m) s = sq_acc(s, xr[l] - Xc[l][p]);
+            Zs[gr][p] = (p < cnt && gr < nr) ? exp(-(t * sqrt(s))) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int p = 0; p < ZC; ++p) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = Zs[4 * ty + i][p];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[p][4 * tx + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * ty + i;
+        if (r < nr) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) out[(r0 + r) * ld + col0 + 4 * tx + j] = acc[i][j];
+        }
+    }
+}
+
+// Row range of task i: [bnd[ts*i + to], bnd[ts*i + to + 1]).
+__device__ inline void task_range(const int64_t *bnd, int ts, int to, int i, int64_t &lo, int64_t &hi)
+{
+    lo = bnd[ts * i + to];
+    hi = bnd[ts * i + to + 1];
+}
+
+// Gram partials A[R]^T B[R] (lda x ldb) per task, per chunk of crows rows,
+// per 64 x 64 tile y = (ai, bj) (blockIdx.y):
+//   partial[((task * cmax + ch) * ntile + y) * 4096 ..] (tile, row-major).
+__global__ void __launch_bounds__(NT)
+k_gram_partial(const double *__restrict__ A, int lda, const double *__restrict__ B, int ldb,
+               const int64_t *__restrict__ bnd, int ts, int to, int crows, int cmax,
+               double *__restrict__ partial)
+{
+    __shared__ double As[32][SL];
+    __shared__ double Bs[32][SL];
+    const int task = blockIdx.x / cmax, ch = blockIdx.x % cmax;
+    const int nbj = ldb / SL, y = blockIdx.y, ntile = gridDim.y;
+    const int ac = (y / nbj) * SL, bc = (y % nbj) * SL;
+    int64_t lo, hi;
+    task_range(bnd, ts, to, task, lo, hi);
+    const int64_t r0 = lo + (int64_t)ch * crows;
+    const int64_t r1 = min(hi, r0 + crows);
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int64_t rs = r0; rs < r1; rs += 32) {
+        const int cnt = (int)min((int64_t)32, r1 - rs);
+        __syncthreads();
+        for (int e = tid; e < 32 * SL; e += NT) {
+            const int rr = e / SL, q = e % SL;
+            As[rr][q] = (rr < cnt) ? A[(rs + rr) * lda + ac + q] : 0.0;
+            Bs[rr][q] = (rr < cnt) ? B[(rs + rr) * ldb + bc + q] : 0.0;
+        }
+        __syncthreads();
+        for (int rr = 0; rr < 32; ++rr) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[rr][4 * ty + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bs[rr][4 * tx + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+    }
+    double *o = partial + ((int64_t)(task * cmax + ch) * ntile + y) * (SL * SL);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[(4 * ty + i) * SL + 4 * tx + j] = acc[i][j];
+}
+
+// Sum of the chunk partials (fixed order) into out[task] = lda x ldb,
+// column-major with leading dimension lda.  grid (tasks * ntile, 16)
+__global__ void __launch_bounds__(NT)
+k_gram_reduce(const double *__restrict__ partial, int cmax, int lda, int ldb, double *__restrict__ out)
+{
+    const int nbj = ldb / SL, ntile = (lda / SL) * nbj;
+    const int task = blockIdx.x / ntile, y = blockIdx.x % ntile;
+    const int e = blockIdx.y * NT + threadIdx.x;  // within the tile, row-major
+    double s = 0.0;
+    for (int ch = 0; ch < cmax; ++ch) s += partial[((int64_t)(task * cmax + ch) * ntile + y) * (SL * SL) + e];
+    const int row = (y / nbj) * SL + e / SL, col = (y % nbj) * SL + e % SL;
+    out[(int64_t)task * lda * ldb + (int64_t)col * lda + row] = s;
+}
+
+// G_task += s I with s = 11 (rows k + k (k + 1)) u tr(G), the shift of
+// shifted CholeskyQR (Fukaya, Kannan, Nakatsukasa, Yamamoto and Yanagisawa,
+// 2020), so the Cholesky of the Gram matrix of a rank-deficient sample still
+// succeeds; an all-zero G becomes the identity.  One workgroup per task.
+__global__ void __launch_bounds__(NT)
+k_gram_shift(double *__restrict__ G, int k, const int64_t *__restrict__ bnd, int ts, int to)
+{
+    __shared__ double red[NT];
+    double *g = G + (int64_t)blockIdx.x * k * k;
+    double tr = 0.0;
+    for (int i = threadIdx.x; i < k; i += NT) tr += g[(int64_t)i * k + i];
+    red[threadIdx.x] = tr;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    int64_t lo, hi;
+    task_range(bnd, ts, to, blockIdx.x, lo, hi);
+    const double trace = red[0];
+    const double s = (trace > 0.0 && isfinite(trace))
+                         ? 11.0 * ((double)(hi - lo) * k + (double)k * (k + 1)) * 0x1.0p-53 * trace
+                         : 1.0;
+    for (int i = threadIdx.x; i < k; i += NT) g[(int64_t)i * k + i] += s;
+}
+
+// Zero the strictly lower triangle of each k x k column-major block (the
+// Cholesky leaves it untouched), so the block is R^{-1} for the row products.
+__global__ void k_zero_lower(double *__restrict__ R, int k, int64_t count)
+{
+    const int64_t per = (int64_t)k * k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count * per;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t w = e % per;
+        const int col = (int)(w / k), row = (int)(w % k);
+        if (row > col) R[e] = 0.0;
+    }
+}
+
+// Row-block products: out[r, slab] = (sub ? out[r, slab] - : ) A[r, :] M[:, slab]
+// for the rows r of each task, M = Mb + task * mstride (lda x ldo,
+// column-major, leading dimension lda); grid (tasks * rbmax, ldo / 64).
+// out must not alias A.
+__global__ void __launch_bounds__(NT)
+k_rowmul(const double *__restrict__ A, int lda, double *__restrict__ out, int ldo,
+         const double *__restrict__ Mb, int64_t mstride, const int64_t *__restrict__ bnd, int ts, int to,
+         int rbmax, int sub)
+{
+    __shared__ double As[64][SL + 1];
+    __shared__ double Ms[SL][SL + 1];
+    const int task = blockIdx.x / rbmax, rb = blockIdx.x % rbmax;
+    const int col0 = blockIdx.y * SL;
+    int64_t lo, hi;
+    task_range(bnd, ts, to, task, lo, hi);
+    const int64_t r0 = lo + (int64_t)rb * 64;
+    if (r0 >= hi) return;  // uniform
+    const int nr = (int)min((int64_t)64, hi - r0);
+    const double *M = Mb + (int64_t)task * mstride;
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < lda; k0 += SL) {
+        __syncthreads();
+        for (int e = tid; e < 64 * SL; e += NT) {
+            const int rr = e / SL, q = e % SL;
+            As[rr][q] = (rr < nr) ? A[(r0 + rr) * lda + k0 + q] : 0.0;
+            // Ms[kk][j] = M(k0 + kk, col0 + j), read down the columns of M
+            const int j = e / SL, kk = e % SL;
+            Ms[kk][j] = M[(int64_t)(col0 + j) * lda + k0 + kk];
+        }
+        __syncthreads();
+        for (int kk = 0; kk < SL; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = As[4 * ty + i][kk];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Ms[kk][4 * tx + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * ty + i;
+        if (r < nr) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                double *p = out + (r0 + r) * ldo + col0 + 4 * tx + j;
+                *p = sub ? (*p - acc[i][j]) : acc[i][j];
+            }
+        }
+    }
+}
+
+// Copy the rows of the tasks' ranges from src to dst (both n x ld).
+__global__ void __launch_bounds__(NT)
+k_copy_rows(const double *__restrict__ src, double *__restrict__ dst, int ld, const int64_t *__restrict__ bnd,
+            int ts, int to, int rbmax)
+{
+    const int task = blockIdx.x / rbmax, rb = blockIdx.x % rbmax;
+    int64_t lo, hi;
+    task_range(bnd, ts, to, task, lo, hi);
+    const int64_t r0 = lo + (int64_t)rb * 64;
+    const int64_t r1 = min(hi, r0 + 64);
+    for (int64_t e = r0 * ld + threadIdx.x; e < r1 * ld; e += NT) dst[e] = src[e];
+}
+
+// Inverse of each leaf block Z(leaf, leaf) (exact FP64 entries) by the sweep
+// operator (Goodnight, 1979): sweeping every pivot of a symmetric positive
+// definite A turns it into -A^{-1}; pivots are the Schur-complement
+// diagonals, positive for SPD A.  Dinv: LMAX x LMAX per leaf (symmetric; the
+// padding is the identity).  A pivot that is not positive marks status.
+__global__ void __launch_bounds__(NT)
+k_leaf_inv(const double *__restrict__ Xp, int m, double t, const int64_t *__restrict__ bndL,
+           double *__restrict__ Dinv, int *__restrict__ status)
+{
+    __shared__ double A[LMAX][LMAX + 1];
+    __shared__ double colk[LMAX];
+    const int tid = threadIdx.x;
+    const int64_t lo = bndL[blockIdx.x], hi = bndL[blockIdx.x + 1];
+    const int s = (int)(hi - lo);
+    for (int e = tid; e < LMAX * LMAX; e += NT) {
+        const int i = e / LMAX, j = e % LMAX;
+        double v;
+        if (i == j) {
+            v = 1.0;
+        } else if (i < s && j < s) {
+            double d2 = 0.0;
+            for (int l = 0; l < m; ++l) d2 = sq_acc(d2, Xp[(lo + i) * m + l] - Xp[(lo + j) * m + l]);
+            v = exp(-(t * sqrt(d2)));
+        } else {
+            v = 0.0;
+        }
+        A[i][j] = v;
+    }
+    bool bad = false;
+    for (int k = 0; k < s; ++k) {
+        __syncthreads();
+        if (tid < LMAX) colk[tid] = A[tid][k];
+        __syncthreads();
+        double akk = colk[k];
+        if (!(akk > 0.0) || !isfinite(akk)) {
+            bad = true;
+            akk = 1.0;
+        }
+        const double inv = 1.0 / akk;
+        for (int e = tid; e < LMAX * LMAX; e += NT) {
+            const int i = e / LMAX, j = e % LMAX;
+            if (i == k && j == k) A[i][j] = -inv;
+            else if (i == k) A[i][j] = colk[j] * inv;
+            else if (j == k) A[i][j] = colk[i] * inv;
+            else A[i][j] -= colk[i] * colk[j] * inv;
+        }
+    }
+    __syncthreads();
+    double *D = Dinv + (int64_t)blockIdx.x * LMAX * LMAX;
+    for (int e = tid; e < LMAX * LMAX; e += NT) {
+        const int i = e / LMAX, j = e % LMAX;
+        D[e] = (i < s && j < s) ? -A[i][j] : (i == j ? 1.0 : 0.0);
+    }
+    if (bad && tid == 0) atomicCAS(&status[kStBreakdown], 0, (int)(lo + 1));
+}
+
+// Ph[leaf rows, slab] = Dinv_leaf P[leaf rows, slab] (both n x ld); grid
+// (leaves, ld / 64).  Dinv streamed through LDS 32 columns at a time.
+__global__ void __launch_bounds__(NT)
+k_leaf_apply(const double *__restrict__ Dinv, const int64_t *__restrict__ bndL, const double *__restrict__ P,
+             double *__restrict__ Ph, int ld)
+{
+    __shared__ double Bs[LMAX][SL];
+    __shared__ double Ms[LMAX][33];
+    const int64_t lo = bndL[blockIdx.x], hi = bndL[blockIdx.x + 1];
+    const int s = (int)(hi - lo);
+    const int col0 = blockIdx.y * SL;
+    const double *M = Dinv + (int64_t)blockIdx.x * LMAX * LMAX;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < LMAX * SL; e += NT) {
+        const int rr = e / SL, q = e % SL;
+        Bs[rr][q] = (rr < s) ? P[(lo + rr) * ld + col0 + q] : 0.0;
+    }
+    const int ty = tid >> 3, tx = tid & 7;  // rows 4ty.., columns 8tx..
+    double acc[4][8];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
+    for (int kc = 0; kc < LMAX; kc += 32) {
+        __syncthreads();
+        for (int e = tid; e < LMAX * 32; e += NT) {
+            const int i = e / 32, j = e % 32;
+            Ms[i][j] = M[i * LMAX + kc + j];
+        }
+        __syncthreads();
+        for (int kk = 0; kk < 32; ++kk) {
+            double av[4], bv[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = Ms[4 * ty + i][kk];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bv[j] = Bs[kc + kk][8 * tx + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 4 * ty + i;
+        if (r < s) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Ph[(lo + r) * ld + col0 + 8 * tx + j] = acc[i][j];
+        }
+    }
+}
+
+// Per node i (batch of `count`): Bm = G[2i+1], Cm = G[2i] (k x k each, from
+// the children's Gram matrices) and S = I, in node storage [Bm | Cm | S].
+__global__ void k_node_setup(const double *__restrict__ G, int k, int64_t count, double *__restrict__ W)
+{
+    const int64_t kk = (int64_t)k * k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count * kk;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / kk, w = e % kk;
+        double *Wi = W + i * 3 * kk;
+        Wi[w] = G[(2 * i + 1) * kk + w];
+        Wi[kk + w] = G[(2 * i) * kk + w];
+        Wi[2 * kk + w] = (w / k == w % k) ? 1.0 : 0.0;
+    }
+}
+
+// ---- preconditioner apply ------------------------------------------------------
+__global__ void k_gather(const double *__restrict__ r, const int64_t *__restrict__ perm, int64_t n,
+                         double *__restrict__ xp)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        xp[i] = r[perm[i]];
+}
+
+// z[perm[i]] = xp[i]; z zero on [n, npad)
+__global__ void k_scatter(const double *__restrict__ xp, const int64_t *__restrict__ perm, int64_t n,
+                          int64_t npad, double *__restrict__ z)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < npad; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < n) z[perm[i]] = xp[i];
+        else z[i] = 0.0;
+    }
+}
+
+// x[leaf] = Dinv_leaf x[leaf] in place (Dinv symmetric: column access coalesces)
+__global__ void __launch_bounds__(NT)
+k_leaf_gemv(const double *__restrict__ Dinv, const int64_t *__restrict__ bndL, double *__restrict__ x)
+{
+    __shared__ double xs[LMAX];
+    __shared__ double hs[LMAX];
+    const int64_t lo = bndL[blockIdx.x], hi = bndL[blockIdx.x + 1];
+    const int s = (int)(hi - lo);
+    const int tid = threadIdx.x, row = tid & (LMAX - 1), half = tid >> 7;
+    if (tid < LMAX) xs[tid] = (tid < s) ? x[lo + tid] : 0.0;
+    __syncthreads();
+    const double *D = Dinv + (int64_t)blockIdx.x * LMAX * LMAX;
+    double acc = 0.0;
+    for (int k = half * 64; k < half * 64 + 64; ++k) acc = fma(D[k * LMAX + row], xs[k], acc);
+    if (half == 1) hs[row] = acc;
+    __syncthreads();
+    if (half == 0 && row < s) x[lo + row] = acc + hs[row];
+}
+
+// partial[(c * cmax + ch) * ld + q] = sum_{r in chunk} P[r, q] x[r] over the
+// children c, slab blockIdx.y
+__global__ void __launch_bounds__(NT)
+k_node_dots(const double *__restrict__ P, int ld, const double *__restrict__ x, const int64_t *__restrict__ bnd,
+            int crows, int cmax, double *__restrict__ partial)
+{
+    __shared__ double red[4][SL];
+    const int c = blockIdx.x / cmax, ch = blockIdx.x % cmax;
+    const int64_t lo = bnd[c], hi = bnd[c + 1];
+    const int64_t r0 = lo + (int64_t)ch * crows, r1 = min(hi, r0 + crows);
+    const int ql = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int q = blockIdx.y * SL + ql;
+    double acc = 0.0;
+    for (int64_t r = r0 + g; r < r1; r += 4) acc = fma(P[r * ld + q], x[r], acc);
+    red[g][ql] = acc;
+    __syncthreads();
+    if (g == 0) partial[((int64_t)c * cmax + ch) * ld + q] = ((red[0][ql] + red[1][ql]) + red[2][ql]) + red[3][ql];
+}
+
+// Node correction coefficients (one workgroup per node i, k <= 512):
+//   s1 = V_J^T x_J, s2 = U_I^T x_I (sums of the dot partials),
+//   x1 = S^{-1} (s1 - B s2),  x2 = s2 - C x1,   tv[i] = [x1; x2].
+__global__ void __launch_bounds__(NT)
+k_node_small(const double *__restrict__ partial, int cmax, int k, const double *__restrict__ W,
+             double *__restrict__ tv)
+{
+    __shared__ double s1[KMAXC * SL], s2[KMAXC * SL], u[KMAXC * SL], x1[KMAXC * SL];
+    const int i0 = blockIdx.x, tid = threadIdx.x;
+    const int64_t kk = (int64_t)k * k;
+    const double *Bm = W + (int64_t)i0 * 3 * kk, *Cm = Bm + kk, *Si = Bm + 2 * kk;
+    for (int q = tid; q < k; q += NT) {
+        double a = 0.0, b = 0.0;
+        for (int ch = 0; ch < cmax; ++ch) {
+            a += partial[((int64_t)(2 * i0 + 1) * cmax + ch) * k + q];
+            b += partial[((int64_t)(2 * i0) * cmax + ch) * k + q];
+        }
+        s1[q] = a;
+        s2[q] = b;
+    }
+    __syncthreads();
+    for (int r = tid; r < k; r += NT) {  // u = s1 - B s2 (column-major: coalesced over r)
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc = fma(Bm[(int64_t)j * k + r], s2[j], acc);
+        u[r] = s1[r] - acc;
+    }
+    __syncthreads();
+    for (int r = tid; r < k; r += NT) {  // x1 = S^{-1} u
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc = fma(Si[(int64_t)j * k + r], u[j], acc);
+        x1[r] = acc;
+    }
+    __syncthreads();
+    double *o = tv + (int64_t)i0 * 2 * k;
+    for (int r = tid; r < k; r += NT) {  // x2 = s2 - C x1
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc = fma(Cm[(int64_t)j * k + r], x1[j], acc);
+        o[r] = x1[r];
+        o[k + r] = s2[r] - acc;
+    }
+}
+
+// x[r] -= Ph[r, :] tv[c/2][(c%2) k ...] for the rows of child c; one
+// workgroup per 64-row block, 4 threads per row.
+__global__ void __launch_bounds__(NT)
+k_node_update(const double *__restrict__ Ph, int k, const int64_t *__restrict__ bnd, int rbmax,
+              const double *__restrict__ tv, double *__restrict__ x)
+{
+    const int c = blockIdx.x / rbmax, rb = blockIdx.x % rbmax;
+    const int64_t lo = bnd[c], hi = bnd[c + 1];
+    const int64_t r = lo + (int64_t)rb * 64 + (threadIdx.x >> 2);
+    const int part = threadIdx.x & 3;
+    const int q = k / 4;
+    const double *tvec = tv + (int64_t)(c >> 1) * 2 * k + (c & 1) * k + part * q;
+    double acc = 0.0;
+    if (r < hi) {
+        const double *row = Ph + r * k + part * q;
+        for (int j = 0; j < q; ++j) acc = fma(row[j], tvec[j], acc);
+    }
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (r < hi && part == 0) x[r] -= acc;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t boff(int l) { return ((int64_t)1 << l) - 1 + l; }
+
+}  // namespace
+
+// ---- host side -------------------------------------------------------------------
+
+int hodlr_max_leaf() { return LMAX; }
+int hodlr_max_cols() { return KMAXC * SL; }
+
+// Perfect tree of L levels over n points: level bounds and the permutation
+// (recursive coordinate bisection, median of the widest coordinate).
+static void build_tree(const std::vector<double> &X, int64_t n, int m, int L, std::vector<int64_t> &perm,
+                       std::vector<int64_t> &bnd)
+{
+    perm.resize(n);
+    std::iota(perm.begin(), perm.end(), (int64_t)0);
+    bnd.assign(boff(L + 1), 0);
+    bnd[boff(0)] = 0;
+    bnd[boff(0) + 1] = n;
+    for (int l = 0; l < L; ++l) {
+        const int64_t nn = (int64_t)1 << l;
+        int64_t *b = bnd.data() + boff(l);
+        int64_t *c = bnd.data() + boff(l + 1);
+        for (int64_t i = 0; i < nn; ++i) {
+            const int64_t lo = b[i], hi = b[i + 1], mid = lo + (hi - lo) / 2;
+            c[2 * i] = lo;
+            c[2 * i + 1] = mid;
+            c[2 * i + 2] = hi;
+            if (hi - lo < 2) continue;
+            int ax = 0;
+            double wbest = -1.0;
+            for (int a = 0; a < m; ++a) {
+                double mn = INFINITY, mx = -INFINITY;
+                for (int64_t p = lo; p < hi; ++p) {
+                    const double v = X[perm[p] * m + a];
+                    mn = std::min(mn, v);
+                    mx = std::max(mx, v);
+                }
+                if (mx - mn > wbest) {
+                    wbest = mx - mn;
+                    ax = a;
+                }
+            }
+            std::nth_element(perm.begin() + lo, perm.begin() + mid, perm.begin() + hi,
+                             [&](int64_t u, int64_t v) {
+                                 const double xu = X[u * m + ax], xv = X[v * m + ax];
+                                 return xu < xv || (xu == xv && u < v);
+                             });
+        }
+    }
+}
+
+int hodlr_levels(int64_t n, int leaf)
+{
+    int L = 0;
+    while (cdiv(n, (int64_t)1 << L) > leaf) ++L;
+    return L;
+}
+
+// Basis width of level l: rank0 2^{-l/2} + oversample rounded up to a
+// multiple of 64, at least 64, at most KMAXC * 64 and at most the smaller
+// child (rounded down to 64, but never below 64).
+static int level_cols(int l, int rank0, int oversample, int64_t minchild)
+{
+    const double want = rank0 * std::pow(2.0, -0.5 * l) + oversample;
+    int c = (int)std::ceil(want / SL);
+    c = std::max(1, std::min(c, KMAXC));
+    const int cap = (int)std::max<int64_t>(1, minchild / SL);
+    return SL * std::min(c, cap);
+}
+
+struct HodlrPlan {
+    std::vector<int> k;              // basis width per level
+    std::vector<int64_t> poff;       // offset of P_l / Ph_l (doubles)
+    std::vector<int64_t> woff;       // offset of level l's node storage (doubles)
+    std::vector<int64_t> csz, cmin;  // largest / smallest child of level l's nodes
+    std::vector<int> crows, cmax;    // Gram chunking per level
+    int64_t ptotal = 0, wtotal = 0, gpart = 0, gout = 0, tbuf = 0, apart = 0, ipiv = 0;
+    int kmax = SL;
+};
+
+static HodlrPlan make_plan(int64_t n, int L, const std::vector<int64_t> &bnd, int rank0, int oversample)
+{
+    HodlrPlan pl;
+    pl.k.resize(L);
+    pl.poff.resize(L + 1);
+    pl.woff.resize(L + 1);
+    pl.csz.resize(L);
+    pl.cmin.resize(L);
+    pl.crows.resize(L);
+    pl.cmax.resize(L);
+    int64_t po = 0, wo = 0;
+    for (int l = 0; l < L; ++l) {
+        const int64_t nch = (int64_t)2 << l;
+        const int64_t *b = bnd.data() + boff(l + 1);
+        int64_t mx = 0, mn = INT64_MAX;
+        for (int64_t c = 0; c < nch; ++c) {
+            mx = std::max(mx, b[c + 1] - b[c]);
+            mn = std::min(mn, b[c + 1] - b[c]);
+        }
+        pl.csz[l] = mx;
+        pl.cmin[l] = mn;
+        pl.k[l] = level_cols(l, rank0, oversample, mn);
+        pl.kmax = std::max(pl.kmax, pl.k[l]);
+        // chunks of at least 256 rows, at most 64 chunks per child
+        pl.crows[l] = (int)std::max<int64_t>(256, cdiv(cdiv(mx, 64), 32) * 32);
+        pl.cmax[l] = (int)cdiv(mx, pl.crows[l]);
+        pl.poff[l] = po;
+        po += n * pl.k[l];
+        pl.woff[l] = wo;
+        wo += ((int64_t)1 << l) * 3 * (int64_t)pl.k[l] * pl.k[l];
+    }
+    pl.poff[L] = po;
+    pl.woff[L] = wo;
+    pl.ptotal = po;
+    pl.wtotal = wo;
+    // scratch: Gram partials / results, T, apply partials, pivots
+    for (int l = 0; l < L; ++l) {
+        const int64_t nch = (int64_t)2 << l;
+        for (int lp = 0; lp <= l; ++lp) {
+            const int64_t kk = (int64_t)pl.k[l] * pl.k[lp];
+            pl.gpart = std::max(pl.gpart, nch * pl.cmax[l] * kk);
+            pl.gout = std::max(pl.gout, nch * kk);
+            pl.tbuf = std::max(pl.tbuf, (nch / 2) * kk);
+        }
+        pl.apart = std::max(pl.apart, nch * pl.cmax[l] * (int64_t)pl.k[l]);
+        pl.ipiv = std::max(pl.ipiv, (nch / 2) * (int64_t)pl.k[l]);
+    }
+    return pl;
+}
+
+static int blas_handle(mag_ctx *ctx, rocblas_handle &h)
+{
+    if (!ctx->blas) {
+        rocblas_handle nh;
+        if (rocblas_create_handle(&nh) != rocblas_status_success) return MAG_EHIP;
+        ctx->blas = nh;
+    }
+    h = (rocblas_handle)ctx->blas;
+    return rocblas_set_stream(h, ctx->stream) == rocblas_status_success ? MAG_OK : MAG_EHIP;
+}
+
+#define RBCHK(x)                                                                                   \
+    do {                                                                                           \
+        if ((x) != rocblas_status_success) return MAG_EHIP;                                        \
+    } while (0)
+
+int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int leaf, int rank0,
+                 int oversample, uint64_t seed, HodlrFactor &H)
+{
+    hipStream_t s = ctx->stream;
+    if (m > MMAXH || leaf < 2 || leaf > LMAX || rank0 < 0 || oversample < 0) return MAG_EINVAL;
+    const int L = hodlr_levels(n, leaf);
+    const int64_t npad = round_up(n, kPad);
+    rocblas_handle bh = nullptr;
+    if (L > 0 && blas_handle(ctx, bh) != MAG_OK) return MAG_EHIP;
+
+    // tree on the host (coordinates copied once)
+    std::vector<double> Xh((size_t)n * m);
+    if (hipMemcpyAsync(Xh.data(), X, sizeof(double) * n * m, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return MAG_EHIP;
+    std::vector<int64_t> perm, bnd;
+    build_tree(Xh, n, m, L, perm, bnd);
+    for (int64_t i = 0; i < ((int64_t)1 << L); ++i)  // the leaf kernels hold a leaf in LDS
+        if (bnd[boff(L) + i + 1] - bnd[boff(L) + i] > LMAX) return MAG_EINTERNAL;
+    std::vector<double> Xp((size_t)n * m);
+    for (int64_t i = 0; i < n; ++i)
+        for (int l = 0; l < m; ++l) Xp[i * m + l] = Xh[perm[i] * m + l];
+    const HodlrPlan pl = make_plan(n, L, bnd, rank0, oversample);
+
+    // device workspace
+    const int64_t leaves = (int64_t)1 << L;
+    const size_t nd = (size_t)n * m + 2 * (size_t)pl.ptotal + 2 * (size_t)n * pl.kmax +
+                      (size_t)leaves * LMAX * LMAX + (size_t)pl.wtotal + (size_t)pl.gpart + 2 * (size_t)pl.gout +
+                      (size_t)pl.tbuf + (size_t)pl.apart + (size_t)leaves * 2 * pl.kmax + 2 * (size_t)npad + 64;
+    const size_t nint = (size_t)n + bnd.size() + 16;
+    const size_t nsmall = (size_t)pl.ipiv + leaves + 64;  // rocsolver pivots and infos (int32)
+    if (ensure(ctx, ctx->hodlr, sizeof(double) * nd + sizeof(int64_t) * nint + sizeof(int) * nsmall + 1024) !=
+        MAG_OK)
+        return MAG_ENOMEM;
+    double *p = (double *)ctx->hodlr.p;
+    H.Xp = p; p += (size_t)n * m;
+    H.P = p; p += pl.ptotal;
+    H.Ph = p; p += pl.ptotal;
+    double *Om = p; p += (size_t)n * pl.kmax;
+    double *W2 = p; p += (size_t)n * pl.kmax;
+    H.Dinv = p; p += (size_t)leaves * LMAX * LMAX;
+    H.W = p; p += pl.wtotal;
+    double *gpart = p; p += pl.gpart;
+    double *G = p; p += pl.gout;
+    double *G2 = p; p += pl.gout;
+    double *T = p; p += pl.tbuf;
+    H.apart = p; p += pl.apart;
+    H.tv = p; p += (size_t)leaves * 2 * pl.kmax;
+    H.xp = p; p += (size_t)2 * npad;
+    p += 64;
+    int64_t *ip = (int64_t *)p;
+    H.perm = ip; ip += n;
+    H.bnd = ip; ip += bnd.size();
+    int *ipiv = (int *)(ip + 8);
+    int *rinfo = ipiv + pl.ipiv;
+    H.n = n;
+    H.m = m;
+    H.t = t;
+    H.L = L;
+    H.npad = npad;
+    H.bnd_host = bnd;
+    H.k = pl.k;
+    H.poff = pl.poff;
+    H.woff = pl.woff;
+    H.crows = pl.crows;
+    H.cmax = pl.cmax;
+    H.csz = pl.csz;
+    int *status = (int *)ctx->ints.p;  // status words at the start of the int block
+
+    if (hipMemcpyAsync(H.Xp, Xp.data(), sizeof(double) * n * m, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(H.perm, perm.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(H.bnd, bnd.data(), sizeof(int64_t) * bnd.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+        return MAG_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MAG_EHIP;  // the host vectors must outlive the copies
+    launch_fill_ints(s, status, 8, 0);
+
+    auto gram = [&](const double *A, int lda, const double *B, int ldb, const int64_t *b, int ts, int to,
+                    int64_t tasks, int l, double *out) {
+        const int nt = (lda / SL) * (ldb / SL);
+        hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)(tasks * pl.cmax[l]), (unsigned)nt), dim3(NT), 0, s, A,
+                           lda, B, ldb, b, ts, to, pl.crows[l], pl.cmax[l], gpart);
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(tasks * nt), SL * SL / NT), dim3(NT), 0, s, gpart,
+                           pl.cmax[l], lda, ldb, out);
+    };
+    const double one = 1.0, mone = -1.0, zero = 0.0;
+
+    // 1. bases of every level: sample, orthonormalise (shifted CholeskyQR, three passes), project
+    for (int l = 0; l < L; ++l) {
+        const int k = pl.k[l];
+        const int64_t tasks = (int64_t)1 << l;
+        const int64_t *bch = H.bnd + boff(l + 1);
+        const int rb = (int)cdiv(pl.csz[l], 64);
+        double *Pl = H.P + pl.poff[l];
+        hipLaunchKernelGGL(k_omega, dim3(2048), dim3(NT), 0, s, Om, n, k, k,
+                           mix64(seed + 0x51ed2701ull * (uint64_t)(l + 1)));
+        hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rb), (unsigned)(k / SL)), dim3(NT), 0, s, H.Xp, m, t,
+                           bch, 0, rb, Om, Pl, k);
+        double *src = Pl, *dst = W2;
+        for (int pass = 0; pass < 3; ++pass) {
+            gram(src, k, src, k, bch, 2, 0, tasks, l, G);
+            hipLaunchKernelGGL(k_gram_shift, dim3((unsigned)tasks), dim3(NT), 0, s, G, k, bch, 2, 0);
+            RBCHK(rocsolver_dpotrf_strided_batched(bh, rocblas_fill_upper, k, G, k, (rocblas_stride)k * k, rinfo,
+                                                   (rocblas_int)tasks));
+            RBCHK(rocsolver_dtrtri_strided_batched(bh, rocblas_fill_upper, rocblas_diagonal_non_unit, k, G, k,
+                                                   (rocblas_stride)k * k, rinfo, (rocblas_int)tasks));
+            hipLaunchKernelGGL(k_zero_lower, dim3(1024), dim3(NT), 0, s, G, k, tasks);
+            hipLaunchKernelGGL(k_rowmul, dim3((unsigned)(tasks * rb), (unsigned)(k / SL)), dim3(NT), 0, s, src, k,
+                               dst, k, G, (int64_t)k * k, bch, 2, 0, rb, 0);
+            std::swap(src, dst);
+        }
+        // three passes end in W2: copy the left children's rows back
+        hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)(tasks * rb)), dim3(NT), 0, s, src, Pl, k, bch, 2, 0, rb);
+        hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rb), (unsigned)(k / SL)), dim3(NT), 0, s, H.Xp, m, t,
+                           bch, 1, rb, Pl, Pl, k);
+    }
+
+    // 2. leaves: exact inverses, applied to every level's basis
+    const int64_t *bL = H.bnd + boff(L);
+    hipLaunchKernelGGL(k_leaf_inv, dim3((unsigned)leaves), dim3(NT), 0, s, H.Xp, m, t, bL, H.Dinv, status);
+    for (int l = 0; l < L; ++l)
+        hipLaunchKernelGGL(k_leaf_apply, dim3((unsigned)leaves, (unsigned)(pl.k[l] / SL)), dim3(NT), 0, s, H.Dinv,
+                           bL, H.P + pl.poff[l], H.Ph + pl.poff[l], pl.k[l]);
+
+    // 3. bottom-up Woodbury factors
+    for (int l = L - 1; l >= 0; --l) {
+        const int k = pl.k[l];
+        const int64_t kk = (int64_t)k * k;
+        const int64_t tasks = (int64_t)1 << l, nch = 2 * tasks;
+        const int64_t *bch = H.bnd + boff(l + 1);
+        const int rb = (int)cdiv(pl.csz[l], 64);
+        double *Pl = H.P + pl.poff[l];
+        double *Phl = H.Ph + pl.poff[l];
+        double *Wl = H.W + pl.woff[l];
+        // B = V_J^T H_J^{-1} V_J, C = U_I^T H_I^{-1} U_I;  S = I - B C;  S^{-1} by LU
+        gram(Pl, k, Phl, k, bch, 1, 0, nch, l, G);
+        hipLaunchKernelGGL(k_node_setup, dim3(1024), dim3(NT), 0, s, G, k, tasks, Wl);
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_none, k, k, k, &mone, Wl, k,
+                                            3 * kk, Wl + kk, k, 3 * kk, &one, Wl + 2 * kk, k, 3 * kk,
+                                            (rocblas_int)tasks));
+        RBCHK(rocsolver_dgetrf_strided_batched(bh, k, k, Wl + 2 * kk, k, 3 * kk, ipiv, k, rinfo, (rocblas_int)tasks));
+        RBCHK(rocsolver_dgetri_strided_batched(bh, k, Wl + 2 * kk, k, 3 * kk, ipiv, k, rinfo, (rocblas_int)tasks));
+        // corrections of the coarser levels' bases: for each l' < l, with
+        // S_c = P_l[c]^T Ph_l'[c]:  X1 = S^{-1} (S_J - B S_I),  X2 = S_I - C X1,
+        //   Ph_l'[I] -= Ph_l[I] X1,   Ph_l'[J] -= Ph_l[J] X2
+        for (int lp = 0; lp < l; ++lp) {
+            const int kp = pl.k[lp];
+            const int64_t kkp = (int64_t)k * kp;
+            double *Phlp = H.Ph + pl.poff[lp];
+            gram(Pl, k, Phlp, kp, bch, 1, 0, nch, l, G2);
+            // G2[2i+1] := S_J - B S_I (in place)
+            RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_none, k, kp, k, &mone,
+                                                Wl, k, 3 * kk, G2, k, 2 * kkp, &one, G2 + kkp, k, 2 * kkp,
+                                                (rocblas_int)tasks));
+            // T[i] := S^{-1} G2[2i+1]
+            RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_none, k, kp, k, &one,
+                                                Wl + 2 * kk, k, 3 * kk, G2 + kkp, k, 2 * kkp, &zero, T, k, kkp,
+                                                (rocblas_int)tasks));
+            // G2[2i] := S_I - C T[i]
+            RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_none, k, kp, k, &mone,
+                                                Wl + kk, k, 3 * kk, T, k, kkp, &one, G2, k, 2 * kkp,
+                                                (rocblas_int)tasks));
+            hipLaunchKernelGGL(k_rowmul, dim3((unsigned)(tasks * rb), (unsigned)(kp / SL)), dim3(NT), 0, s, Phl, k,
+                               Phlp, kp, T, kkp, bch, 2, 0, rb, 1);
+            hipLaunchKernelGGL(k_rowmul, dim3((unsigned)(tasks * rb), (unsigned)(kp / SL)), dim3(NT), 0, s, Phl, k,
+                               Phlp, kp, G2, 2 * kkp, bch, 2, 1, rb, 1);
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return MAG_EHIP;
+    int st[8];
+    if (hipMemcpyAsync(st, status, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return MAG_EHIP;
+    if (st[kStBreakdown] > 0) return MAG_ENOTPD;  // a leaf block is not positive definite
+    return MAG_OK;
+}
+
+// z = H^{-1} r (r, z: npad vectors in the caller's point order; z zero in the padding)
+void hodlr_apply(hipStream_t s, const HodlrFactor &H, const double *r, double *z)
+{
+    const int64_t n = H.n;
+    const int L = H.L;
+    const int64_t leaves = (int64_t)1 << L;
+    const unsigned gb = (unsigned)std::min<int64_t>(cdiv(H.npad, 256), 2048);
+    hipLaunchKernelGGL(k_gather, dim3(gb), dim3(256), 0, s, r, H.perm, n, H.xp);
+    hipLaunchKernelGGL(k_leaf_gemv, dim3((unsigned)leaves), dim3(NT), 0, s, H.Dinv, H.bnd + boff(L), H.xp);
+    for (int l = L - 1; l >= 0; --l) {
+        const int k = H.k[l];
+        const int64_t tasks = (int64_t)1 << l, nch = 2 * tasks;
+        const int rb = (int)cdiv(H.csz[l], 64);
+        const int64_t *bch = H.bnd + boff(l + 1);
+        hipLaunchKernelGGL(k_node_dots, dim3((unsigned)(nch * H.cmax[l]), (unsigned)(k / SL)), dim3(NT), 0, s,
+                           H.P + H.poff[l], k, H.xp, bch, H.crows[l], H.cmax[l], H.apart);
+        hipLaunchKernelGGL(k_node_small, dim3((unsigned)tasks), dim3(NT), 0, s, H.apart, H.cmax[l], k,
+                           H.W + H.woff[l], H.tv);
+        hipLaunchKernelGGL(k_node_update, dim3((unsigned)(nch * rb)), dim3(NT), 0, s, H.Ph + H.poff[l], k, bch, rb,
+                           H.tv, H.xp);
+    }
+    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(256), 0, s, H.xp, H.perm, n, H.npad, z);
+}
+
+}  // namespace mag

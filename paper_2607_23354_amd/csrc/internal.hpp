@@ -130,6 +130,7 @@ struct mag_ctx {
     mag::DevBuf aux;       // FP64 vectors of the cutoff search and the adjoint
     // batched solves
     mag::DevBuf bfactor, bdinv, bvec, bscal, bpartial, bints, bdesc, barena, bstage;
+    mag::DevBuf hodlr;     // HODLR preconditioner workspace
     void *bhost = nullptr;   // pinned host staging for work lists and descriptors
     size_t bhost_bytes = 0;
     double *host_scalars = nullptr;  // pinned host staging (64 doubles)
@@ -229,5 +230,33 @@ void launch_amax(hipStream_t s, const double *x, int64_t len, double *partial, d
 void launch_affine_ones(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len);
 // y = a*x on [0, n), zero on [n, len)
 void launch_scale(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len);
+
+// ---- hodlr.hip: HODLR preconditioner ---------------------------------------------
+// Device pointers into ctx->hodlr (valid until the next HODLR factorisation on
+// the same context).  Points are in tree order (perm[i] = caller index of the
+// i-th point); node (l, i) covers [bnd[2^l - 1 + l + i], ... + 1).  Level l's
+// bases have k[l] columns (a multiple of 64) at P + poff[l] / Ph + poff[l];
+// its nodes' [B | C | S^{-1}] blocks (k[l] x k[l] each) start at W + woff[l].
+struct HodlrFactor {
+    int64_t n = 0, npad = 0;
+    int m = 0, L = 0;
+    double t = 0.0;
+    double *Xp = nullptr, *P = nullptr, *Ph = nullptr, *Dinv = nullptr, *W = nullptr;
+    double *apart = nullptr, *tv = nullptr, *xp = nullptr;
+    int64_t *perm = nullptr, *bnd = nullptr;
+    std::vector<int64_t> bnd_host, poff, woff, csz;
+    std::vector<int> k, crows, cmax;
+};
+int hodlr_max_leaf();
+int hodlr_max_cols();
+int hodlr_levels(int64_t n, int leaf);
+// Build the factor of Z(t) for the points X (device, n x m); rank0 is the
+// basis rank of the top level (halved every two levels), oversample the extra
+// sample columns.  Status words in ctx->ints.  MAG_ENOTPD when a leaf block
+// is not positive definite.
+int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int leaf, int rank0,
+                 int oversample, uint64_t seed, HodlrFactor &H);
+// z = H^{-1} r; r, z device vectors of length npad (z zero on [n, npad)).
+void hodlr_apply(hipStream_t s, const HodlrFactor &H, const double *r, double *z);
 
 }  // namespace mag
