@@ -24,14 +24,15 @@ sys.path.insert(0, ROOT)
 
 FP32_MFMA_PEAK_TFLOPS = 157.3
 FP64_MFMA_PEAK_TFLOPS = 78.6
-SYRK_SOURCE = os.path.join(ROOT, "paper_2607_23354_amd", "csrc", "gemm_mfma.hip")
+SYRK_SOURCES = [os.path.join(ROOT, "paper_2607_23354_amd", "csrc", f) for f in ("gemm_mfma.hip", "chol32.hip")]
 SYRK_TRAFFIC = os.path.join(ROOT, "profiles", "k_syrk_lower_gaussian_n32768_m3_traffic.txt")
 
 
 def counter_traffic(n):
     """HBM bytes per launch of the trailing-update kernel, from the committed
     FETCH_SIZE + WRITE_SIZE counter summary, or None when there is none for
-    this size or the kernel source changed after the counters were taken."""
+    this size or the kernel or its launch schedule changed after the counters
+    were taken (hash of both sources)."""
     import hashlib
     try:
         kv = {}
@@ -40,8 +41,11 @@ def counter_traffic(n):
                 if ":" in line and not line.startswith((" ", "#", "|")):
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
-        with open(SYRK_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        h = hashlib.sha256()
+        for src in SYRK_SOURCES:
+            with open(src, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()
         if kv.get("source_sha256") != sha or int(kv.get("n", -1)) != n:
             return None
         return float(kv["traffic_bytes_per_launch"])
@@ -198,7 +202,7 @@ def main():
                    "seed": args.seed, "solver": "fp32_ir", "parallelism": "single-gpu"},
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_syrk_lower (trailing update A22 -= L21 L21^T, K = 256, FP32 MFMA 32x32x2)",
+            "kernel": "k_syrk_lower (trailing update A22 -= L21 L21^T, K = 512, FP32 MFMA 32x32x2)",
             "achieved": achieved,
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -2,17 +2,20 @@
 //
 // Z is symmetric positive definite for distinct Euclidean points (Sections 2
 // and 3.2), so Z = L L^T exists; this factor is computed in FP32 and used as
-// the preconditioner of the FP64 refinement.  For each panel of nb = 256
-// columns starting at k (two 128-column sub-panels s):
+// the preconditioner of the FP64 refinement.  For each panel of nb = 512
+// columns starting at k (256 for a last, narrower panel), made of 128-column
+// sub-panels s:
 //   1. potrf128   factor of the 128 x 128 diagonal block and its inverse
 //   2. trsm       rows below:  L21 = A21 * inv(L11)^T     (MFMA, in place),
 //                 with L21^T written into the upper triangle
-//   3. (s = 0)    update the second sub-panel's columns with the first
-//   4. syrk       trailing update  A22 -= L21 L21^T, K = 256, lower tiles only
-// The panel inverses of the diagonal 128-blocks are kept (dinv) for the
+//   3. update     the panel's later sub-panels by this one (K = 128)
+//   4. syrk       trailing update  A22 -= L21 L21^T, K = nb, lower tiles only
+// A deep K in step 4 amortises the load and store of each C tile over more
+// MFMA work.  The inverses of the diagonal 128-blocks are kept (dinv) for the
 // preconditioner's triangular solves.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <vector>
 
 namespace mag {
@@ -24,8 +27,11 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
                    FactorTimer *timer)
 {
     const int64_t T = kTile;
-    for (int64_t k = 0; k < npad; k += kPanel) {
-        for (int sub = 0; sub < kPanel / T; ++sub) {
+    constexpr int64_t kNb = 512;
+    for (int64_t k = 0; k < npad; k += kNb) {
+        const int64_t nb = std::min<int64_t>(kNb, npad - k);
+        const int64_t nsub = nb / T;
+        for (int64_t sub = 0; sub < nsub; ++sub) {
             const int64_t kk = k + sub * T;
             float *Linv = dinv + (kk / T) * T * T;
             launch_potrf128(s, A, npad, kk, Linv, status);
@@ -35,17 +41,18 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
                 float *A12 = A + (kk + T) * npad + kk;  // upper triangle: L21^T
                 launch_gemm_nt(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSetT, A12);
             }
-            if (sub + 1 < kPanel / T && below > 0) {
-                // update the next sub-panel's columns (rows kk+T ..) with this sub-panel
+            if (sub + 1 < nsub) {
+                // the panel's remaining sub-panels (rows kk+T ..) by this sub-panel;
+                // tiles above their diagonal are rewritten later by their own trsm
                 float *C = A + (kk + T) * npad + kk + T;
                 const float *P = A + kk * npad + kk + T;
-                launch_gemm_nt(s, C, npad, P, npad, P, npad, below, T, T, kGemmSub);
+                launch_gemm_nt(s, C, npad, P, npad, P, npad, below, (nsub - sub - 1) * T, T, kGemmSub);
             }
         }
-        const int64_t trail = npad - k - kPanel;
+        const int64_t trail = npad - k - nb;
         if (trail > 0) {
-            float *C = A + (k + kPanel) * npad + k + kPanel;
-            const float *P = A + k * npad + k + kPanel;
+            float *C = A + (k + nb) * npad + k + nb;
+            const float *P = A + k * npad + k + nb;
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (timer) {
                 if (timer->used + 2 > timer->ev.size()) {
@@ -58,11 +65,11 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
                 e0 = timer->ev[timer->used++];
                 e1 = timer->ev[timer->used++];
                 // algorithmic flops of the trailing update restricted to the true n
-                const int64_t nt = n - (k + kPanel);
-                timer->flops.push_back(nt > 0 ? (double)kPanel * (double)nt * (double)(nt + 1) : 0.0);
+                const int64_t nt = n - (k + nb);
+                timer->flops.push_back(nt > 0 ? (double)nb * (double)nt * (double)(nt + 1) : 0.0);
                 hipEventRecord(e0, s);
             }
-            launch_syrk_lower(s, C, npad, P, npad, trail, kPanel);
+            launch_syrk_lower(s, C, npad, P, npad, trail, nb);
             if (timer) hipEventRecord(e1, s);
         }
     }

@@ -24,7 +24,7 @@ namespace mag {
 
 constexpr int kPad = 256;      // npad multiple (panel width of the factor)
 constexpr int kTile = 128;     // MFMA tile edge and diagonal-block size
-constexpr int kPanel = 256;    // panel width nb of the blocked Cholesky
+constexpr int kPanel = 256;    // npad multiple; panel width of the batched factorisation
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
