@@ -18,7 +18,7 @@
 // 128-byte contiguous column segment for a half-wave, which makes both the
 // initial load of C and the final store coalesced.
 // K is staged through LDS in chunks of 16, double-buffered, one barrier per
-// stage.
+// stage; the accumulators start at zero and C is added in the epilogue.
 #include "internal.hpp"
 
 namespace mag {
@@ -61,58 +61,48 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
     const int l32 = lane & 31;
     const int hi = lane >> 5;
 
+    // accumulate from zero (for kGemmSub with Q negated, so acc = -P Q^T);
+    // C is read only in the epilogue, which keeps the stage loop free of
+    // waits on loads other than the operand prefetch
     v16f acc[2][2];
-    if (MODE == kGemmSub) {
 #pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
+    for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-            for (int ib = 0; ib < 2; ++ib) {
-                const int64_t i = i0 + wi + ib * 32 + l32;
+        for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-                    acc[jb][ib][r] = C[j * ldc + i];
-                }
-            }
-    } else {
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-            for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[jb][ib][r] = 0.0f;
-    }
+            for (int r = 0; r < 16; ++r) acc[jb][ib][r] = 0.0f;
 
     // global -> register staging: thread loads float4 at (row 4*(tid%32), p = tid/32 (+8))
     const int lr = 4 * (threadIdx.x & 31);
     const int lp = threadIdx.x >> 5;
-    float4 pa[2], qa[2];
-    auto gload = [&](int64_t kk) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            pa[s] = *reinterpret_cast<const float4 *>(P + (kk + lp + 8 * s) * ldp + i0 + lr);
-            qa[s] = *reinterpret_cast<const float4 *>(Q + (kk + lp + 8 * s) * ldq + j0 + lr);
-        }
-    };
-    auto swrite = [&](int buf) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            float4 q = qa[s];
-            if (MODE == kGemmSub) {
-                q.x = -q.x; q.y = -q.y; q.z = -q.z; q.w = -q.w;
-            }
-            *reinterpret_cast<float4 *>(&Ps[buf][lp + 8 * s][lr]) = pa[s];
-            *reinterpret_cast<float4 *>(&Qs[buf][lp + 8 * s][lr]) = q;
-        }
-    };
+    const float *pg0 = P + lp * ldp + i0 + lr, *pg1 = P + (lp + 8) * ldp + i0 + lr;
+    const float *qg0 = Q + lp * ldq + j0 + lr, *qg1 = Q + (lp + 8) * ldq + j0 + lr;
+    const int64_t stepP = KC * ldp, stepQ = KC * ldq;
+    const float qs = (MODE == kGemmSub) ? -1.0f : 1.0f;
+    float4 pa0 = *reinterpret_cast<const float4 *>(pg0);
+    float4 pa1 = *reinterpret_cast<const float4 *>(pg1);
+    float4 qa0 = *reinterpret_cast<const float4 *>(qg0);
+    float4 qa1 = *reinterpret_cast<const float4 *>(qg1);
+    *reinterpret_cast<float4 *>(&Ps[0][lp][lr]) = pa0;
+    *reinterpret_cast<float4 *>(&Ps[0][lp + 8][lr]) = pa1;
+    *reinterpret_cast<float4 *>(&Qs[0][lp][lr]) = make_float4(qs * qa0.x, qs * qa0.y, qs * qa0.z, qs * qa0.w);
+    *reinterpret_cast<float4 *>(&Qs[0][lp + 8][lr]) = make_float4(qs * qa1.x, qs * qa1.y, qs * qa1.z, qs * qa1.w);
+    __syncthreads();
 
     const int nst = (int)(K / KC);
-    gload(0);
-    swrite(0);
-    __syncthreads();
     for (int st = 0; st < nst; ++st) {
         const int buf = st & 1;
-        if (st + 1 < nst) gload((int64_t)(st + 1) * KC);
+        const bool more = st + 1 < nst;
+        if (more) {
+            pg0 += stepP;
+            pg1 += stepP;
+            qg0 += stepQ;
+            qg1 += stepQ;
+            pa0 = *reinterpret_cast<const float4 *>(pg0);
+            pa1 = *reinterpret_cast<const float4 *>(pg1);
+            qa0 = *reinterpret_cast<const float4 *>(qg0);
+            qa1 = *reinterpret_cast<const float4 *>(qg1);
+        }
 #pragma unroll
         for (int kp = 0; kp < KC / 2; ++kp) {
             const int p = 2 * kp + hi;
@@ -125,7 +115,14 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
             acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q1, p0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q1, p1, acc[1][1], 0, 0, 0);
         }
-        if (st + 1 < nst) swrite(buf ^ 1);
+        if (more) {
+            *reinterpret_cast<float4 *>(&Ps[buf ^ 1][lp][lr]) = pa0;
+            *reinterpret_cast<float4 *>(&Ps[buf ^ 1][lp + 8][lr]) = pa1;
+            *reinterpret_cast<float4 *>(&Qs[buf ^ 1][lp][lr]) =
+                make_float4(qs * qa0.x, qs * qa0.y, qs * qa0.z, qs * qa0.w);
+            *reinterpret_cast<float4 *>(&Qs[buf ^ 1][lp + 8][lr]) =
+                make_float4(qs * qa1.x, qs * qa1.y, qs * qa1.z, qs * qa1.w);
+        }
         __syncthreads();
     }
 
@@ -134,10 +131,24 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) {
             const int64_t i = i0 + wi + ib * 32 + l32;
+            if (MODE == kGemmSub) {
+                float cv[16];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-                C[j * ldc + i] = acc[jb][ib][r];
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                    cv[r] = C[j * ldc + i];
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                    C[j * ldc + i] = cv[r] + acc[jb][ib][r];
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                    C[j * ldc + i] = acc[jb][ib][r];
+                }
             }
         }
     if (MODE == kGemmSetT) {
