@@ -6,13 +6,16 @@
 // (exact differences, uncontracted squared sum in ascending l, sqrt, then
 // exp(-(t d))), in FP64.
 //
-// Grid: (row blocks of 256 rows, one row per thread) x (column splits).  Each
-// workgroup stages 256-column chunks of coordinates and v in LDS and sweeps
-// its column range; partial row sums go to a split-major buffer and a second
-// kernel adds the splits in fixed order (deterministic), optionally forming
-// b - Z v and its max-norm.
+// Single solves use the symmetry of Z: only the 128 x 128 tiles (I, J) with
+// J <= I are evaluated; each off-diagonal tile adds Z_IJ v_J to block I and
+// Z_IJ^T v_I to block J, so every entry is formed once.  Per-tile row and
+// column sums go to a tile-major buffer and a second kernel adds them per
+// block in a fixed order (deterministic), optionally forming b - Z v and its
+// max-norm.  The batched path keeps the row-per-thread form: (row blocks of
+// 256 rows) x (column splits), partial row sums split-major.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace mag {
@@ -87,6 +90,154 @@ __device__ __forceinline__ void zmv_partial_body(const double *__restrict__ X, i
         }
     }
     if (j < npad) partial[by * npad + j] = live ? acc : 0.0;
+}
+
+constexpr int TS = 128;       // symmetric tile edge
+constexpr int MMAX_SYM = 16;  // largest dimension of the symmetric product
+
+// Lower tile index -> (I, J), J <= I, idx = I (I + 1) / 2 + J.
+__device__ inline void tri_tile(int64_t idx, int64_t &I, int64_t &J)
+{
+    int64_t r = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
+    while (r * (r + 1) / 2 > idx) --r;
+    while ((r + 1) * (r + 2) / 2 <= idx) ++r;
+    I = r;
+    J = idx - r * (r + 1) / 2;
+}
+
+// One lower tile (I, J) of Z per workgroup; thread (ty, tx) owns rows 8 ty ..
+// and columns 8 tx .. of the tile.  part[tile * 2 TS + p]: row sums
+// sum_c Z(r0 + p, c) v_c over the tile's columns; part[tile * 2 TS + TS + p]:
+// column sums sum_r Z(r, c0 + p) v_r (off-diagonal tiles only; a diagonal
+// tile is summed over its full square as rows).  M > 0: compile-time m.
+template <int M>
+__global__ void __launch_bounds__(256)
+k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const double *__restrict__ v,
+          double *__restrict__ part)
+{
+    constexpr int MM = (M > 0) ? M : MMAX_SYM;
+    __shared__ double Xr[MM][TS];
+    __shared__ double Xc[MM][TS];
+    __shared__ double vr[TS], vc[TS];
+    __shared__ double red[4][TS];
+    const int m = (M > 0) ? M : m_rt;
+    int64_t I, J;
+    tri_tile(blockIdx.x, I, J);
+    const int64_t r0 = I * TS, c0 = J * TS;
+    const bool diag = (I == J);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < m * TS; e += 256) {
+        const int l = e / TS, p = e % TS;
+        Xr[l][p] = (r0 + p < n) ? X[(r0 + p) * m + l] : 0.0;
+        Xc[l][p] = (c0 + p < n) ? X[(c0 + p) * m + l] : 0.0;
+    }
+    if (tid < TS) {
+        vr[tid] = (r0 + tid < n) ? v[r0 + tid] : 0.0;
+        vc[tid] = (c0 + tid < n) ? v[c0 + tid] : 0.0;
+    }
+    __syncthreads();
+    const int ty = tid >> 4, tx = tid & 15;
+    const int nr = (int)min((int64_t)TS, n - r0), nc = (int)min((int64_t)TS, n - c0);
+    double xr[8][(M > 0) ? M : 1];
+    if (M > 0) {
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii)
+#pragma unroll
+            for (int l = 0; l < ((M > 0) ? M : 1); ++l) xr[ii][l] = Xr[l][8 * ty + ii];
+    }
+    double rowacc[8], colsum[8];
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) rowacc[ii] = 0.0;
+    // one column at a time: the 8 row entries of a column are independent
+    // exp evaluations, enough parallelism without unrolling the columns
+#pragma unroll 1
+    for (int jj = 0; jj < 8; ++jj) {
+        const int c = 8 * tx + jj;
+        double xc[MM];
+#pragma unroll
+        for (int l = 0; l < MM; ++l) xc[l] = (l < m) ? Xc[l][c] : 0.0;
+        const double vcj = vc[c];
+        double colacc = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii) {
+            const int r = 8 * ty + ii;
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < MM; ++l) {
+                if (l < m) {
+                    const double xrv = (M > 0) ? xr[ii][(M > 0) ? l : 0] : Xr[l][r];
+                    s = sq_acc(s, xrv - xc[l]);
+                }
+            }
+            double z;
+            if (r >= nr || c >= nc) z = 0.0;
+            else if (diag && r == c) z = 1.0;
+            else z = exp(-(t * sqrt(s)));
+            rowacc[ii] = fma(z, vcj, rowacc[ii]);
+            colacc = fma(z, vr[r], colacc);
+        }
+        colsum[jj] = colacc;
+    }
+    double *pt = part + (int64_t)blockIdx.x * 2 * TS;
+    // rows: sum over the 16 tx lanes (contiguous) by a fixed butterfly
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) {
+        double a = rowacc[ii];
+        a += __shfl_xor(a, 1);
+        a += __shfl_xor(a, 2);
+        a += __shfl_xor(a, 4);
+        a += __shfl_xor(a, 8);
+        rowacc[ii] = a;
+    }
+    if (tx == 0) {
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii) pt[8 * ty + ii] = rowacc[ii];
+    }
+    if (diag) return;  // uniform per workgroup
+    // columns: sum over the 4 ty of a wave (lanes 16 and 32 apart), then the 4 waves
+    const int wave = tid >> 6, tyw = (tid >> 4) & 3;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) {
+        double a = colsum[jj];
+        a += __shfl_xor(a, 16);
+        a += __shfl_xor(a, 32);
+        colsum[jj] = a;
+    }
+    if (tyw == 0) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) red[wave][8 * tx + jj] = colsum[jj];
+    }
+    __syncthreads();
+    if (tid < TS) pt[TS + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
+// Block I of y (rows r0 .. r0 + TS): sum of the row sums of tiles (I, 0..I)
+// and the column sums of tiles (I+1..T-1, I), in that order.  mode 0: y = Z v;
+// mode 1: y = b - Z v (b == NULL: ones) and blkmax[I] = max |y| over the block.
+__global__ void __launch_bounds__(TS)
+k_zmv_sym_reduce(const double *__restrict__ part, int64_t T, int64_t n, int64_t npad, double *__restrict__ y,
+                 const double *__restrict__ b, int mode, double *__restrict__ blkmax)
+{
+    __shared__ double red[TS];
+    const int64_t I = blockIdx.x;
+    const int p = threadIdx.x;
+    const int64_t row = I * TS + p;
+    double s = 0.0;
+    const int64_t base = I * (I + 1) / 2;
+    for (int64_t Jt = 0; Jt <= I; ++Jt) s += part[(base + Jt) * 2 * TS + p];
+    for (int64_t It = I + 1; It < T; ++It) s += part[(It * (It + 1) / 2 + I) * 2 * TS + TS + p];
+    double val = 0.0;
+    if (row < n) val = (mode == 0) ? s : (b ? b[row] : 1.0) - s;
+    if (row < npad) y[row] = val;
+    if (mode == 1) {
+        red[p] = fabs(val);
+        __syncthreads();
+        for (int w = TS / 2; w > 0; w >>= 1) {
+            if (p < w) red[p] = fmax(red[p], red[p + w]);
+            __syncthreads();
+        }
+        if (p == 0) blkmax[I] = red[0];
+    }
 }
 
 template <int M>
@@ -221,7 +372,9 @@ __global__ void __launch_bounds__(256) k_max_final_b(const BProb *__restrict__ P
 size_t zmv_partial_doubles(int64_t n)
 {
     Plan p = plan_for(n);
-    return (size_t)(p.splits * p.npad + p.npad / 256 + 8);
+    const int64_t T = (p.npad + TS - 1) / TS;
+    const size_t sym = (size_t)(T * (T + 1) / 2) * 2 * TS + (size_t)T + 8;
+    return std::max(sym, (size_t)(p.splits * p.npad + p.npad / 256 + 8));
 }
 
 int64_t zmv_b_units(int64_t n)
@@ -251,30 +404,45 @@ void launch_zmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const B
         hipLaunchKernelGGL(k_max_final_b, dim3(wz.na), dim3(256), 0, s, P, wz, norm_off);
 }
 
-void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
-                double *y, const double *b, int mode, double *partial, double *out_norm)
+// Row-per-thread form (any m): (row blocks) x (column splits), then the split reduce.
+static void launch_zmv_split(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
+                             double *y, const double *b, int mode, double *partial, double *out_norm)
 {
     Plan p = plan_for(n);
     dim3 grid((unsigned)p.rowblocks, (unsigned)p.splits);
-    switch (m) {
-    case 1: hipLaunchKernelGGL(k_zmv_partial<1>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    case 2: hipLaunchKernelGGL(k_zmv_partial<2>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    case 3: hipLaunchKernelGGL(k_zmv_partial<3>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    case 4: hipLaunchKernelGGL(k_zmv_partial<4>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    case 5: hipLaunchKernelGGL(k_zmv_partial<5>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    case 6: hipLaunchKernelGGL(k_zmv_partial<6>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    case 7: hipLaunchKernelGGL(k_zmv_partial<7>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    case 8: hipLaunchKernelGGL(k_zmv_partial<8>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    default: hipLaunchKernelGGL(k_zmv_partial<0>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad); break;
-    }
-    // rows beyond rowblocks*RT but below npad are written by the reduce kernel as zero
+    hipLaunchKernelGGL(k_zmv_partial<0>, grid, dim3(RT), 0, s, X, n, m, t, v, partial, p.cps, p.npad);
     const int64_t rb = p.npad / 256;
     double *blkmax = partial + p.splits * p.npad;
-    // the partial kernel covers rows < rowblocks*RT; make rows up to npad defined
-    hipLaunchKernelGGL(k_zmv_reduce, dim3((unsigned)rb), dim3(256), 0, s, partial, p.npad, n,
-                       (int)p.splits, y, b, mode, blkmax);
+    hipLaunchKernelGGL(k_zmv_reduce, dim3((unsigned)rb), dim3(256), 0, s, partial, p.npad, n, (int)p.splits, y, b,
+                       mode, blkmax);
     if (mode == 1 && out_norm)
         hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, blkmax, rb, out_norm);
+}
+
+void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
+                double *y, const double *b, int mode, double *partial, double *out_norm)
+{
+    if (m > MMAX_SYM) {
+        launch_zmv_split(s, X, n, m, t, v, y, b, mode, partial, out_norm);
+        return;
+    }
+    const int64_t npad = (n + kPad - 1) / kPad * kPad;
+    const int64_t T = npad / TS;
+    const int64_t tiles = T * (T + 1) / 2;
+    const dim3 grid((unsigned)tiles);
+    switch (m) {
+    case 1: hipLaunchKernelGGL(k_zmv_sym<1>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 2: hipLaunchKernelGGL(k_zmv_sym<2>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 3: hipLaunchKernelGGL(k_zmv_sym<3>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 4: hipLaunchKernelGGL(k_zmv_sym<4>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 8: hipLaunchKernelGGL(k_zmv_sym<8>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    default: hipLaunchKernelGGL(k_zmv_sym<0>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    }
+    double *blkmax = partial + tiles * 2 * TS;
+    hipLaunchKernelGGL(k_zmv_sym_reduce, dim3((unsigned)T), dim3(TS), 0, s, partial, T, n, npad, y, b, mode,
+                       blkmax);
+    if (mode == 1 && out_norm)
+        hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, blkmax, T, out_norm);
 }
 
 }  // namespace mag
