@@ -8,11 +8,14 @@
 //
 //   for each 32-column block J (right-looking):
 //     1. one wave factors the 32 x 32 diagonal block in registers
-//        (lane = row, pivot and columns broadcast with readlane);
-//     2. rows below it are solved against L_JJ^T (one thread per row);
-//     3. the trailing part of the block is updated (4 x 4 register blocks).
-//   then the inverse: diagonal 32 x 32 blocks by substitution (one wave
-//   each), off-diagonal blocks by Inv_IJ = -Inv_II sum_{K=J}^{I-1} L_IK Inv_KJ.
+//        (lane = row, pivots and columns broadcast with readlane) and
+//        inverts it by substitution;
+//     2. the blocks below are solved against it, L_IJ = A_IJ inv(L_JJ)^T;
+//     3. the trailing blocks are updated, A_IK -= L_IJ L_KJ^T;
+//   then the off-diagonal blocks of the inverse, by distance from the
+//   diagonal: Inv_IJ = -Inv_II sum_{K=J}^{I-1} L_IK Inv_KJ.
+// Steps 2, 3 and the inverse are 32 x 32 x 32 products on MFMA
+// (v_mfma_f32_32x32x2f32, one product per wave).
 //
 // A pivot that is not positive (or not finite) marks status[0] with the
 // global pivot index + 1 and is replaced by 1 so the kernel still finishes;
@@ -21,6 +24,8 @@
 
 namespace mag {
 namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int NB = 128;
 constexpr int LDS_LD = 129;  // padded column stride of the LDS copy
@@ -31,12 +36,49 @@ __device__ inline float bcast(float v, int src_lane)
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src_lane));
 }
 
+// acc += X Y for 32 x 32 blocks in column-major LDS (X(i, k) = X[k * xld + i]).
+// YT: Y is given transposed, Y(k, j) = Yb(j, k); else Y(k, j) = Yb[j * yld + k].
+// Accumulator lane l holds column-of-X-rows i = l % 32; register r holds
+// j = 8 (r / 4) + 4 (l / 32) + r % 4.
+template <bool YT>
+__device__ inline v16f blk_mma(const float *X, int xld, const float *Yb, int yld, v16f acc, int lane)
+{
+    const int q = lane & 31, kq = lane >> 5;
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 2) {
+        const float aop = YT ? Yb[(kk + kq) * yld + q] : Yb[q * yld + kk + kq];
+        const float bop = X[(kk + kq) * xld + q];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(aop, bop, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// dst(i, j) = (accumulate ? dst(i, j) : 0) + sign * acc for a 32 x 32 block
+__device__ inline void blk_store(float *dst, int ld, const v16f &acc, int lane, float sign, bool accumulate)
+{
+    const int i = lane & 31, hi = lane >> 5;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = 8 * (r >> 2) + 4 * hi + (r & 3);
+        float *p = dst + j * ld + i;
+        *p = accumulate ? (*p + sign * acc[r]) : sign * acc[r];
+    }
+}
+
+__device__ inline v16f zero16()
+{
+    v16f z;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) z[r] = 0.0f;
+    return z;
+}
+
 __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld, int64_t k0,
                                               float *__restrict__ Linv, int *__restrict__ status)
 {
     __shared__ float S[NB * LDS_LD];    // L, column-major, S[c*LDS_LD + r]
-    __shared__ float V[NB * LDS_LD];    // L^{-1}
-    __shared__ float T[3 * 32 * TLD];   // scratch for the off-diagonal inverse blocks
+    __shared__ float V[NB * LDS_LD];    // L^{-1}, same layout
+    __shared__ float T[3 * 32 * TLD];   // per-wave scratch for the off-diagonal inverse blocks
     __shared__ int bad;
 
     const int tid = threadIdx.x;
@@ -69,7 +111,7 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
 
     for (int J = 0; J < 4; ++J) {
         const int j0 = 32 * J;
-        // 1. factor the diagonal 32 x 32 block in wave 0 (lanes 32..63 mirror 0..31)
+        // 1. factor and invert the diagonal 32 x 32 block in wave 0 (lanes 32..63 mirror 0..31)
         if (wave == 0) {
             const int rr = lane & 31;
             float a[32];
@@ -82,9 +124,8 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
                     if (lane == 0 && bad == 0) bad = (int)(k0 + j0 + c + 1);
                     piv = 1.0f;
                 }
-                const float d = sqrtf(piv);
-                const float inv = 1.0f / d;
-                if (rr == c) a[c] = d;
+                const float inv = rsqrtf(piv);
+                if (rr == c) a[c] = piv * inv;
                 else if (rr > c) a[c] = a[c] * inv;
 #pragma unroll
                 for (int k = c + 1; k < 32; ++k) {
@@ -97,53 +138,45 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
                 for (int c = 0; c < 32; ++c)
                     if (c <= rr) S[(j0 + c) * LDS_LD + j0 + rr] = a[c];
             }
-        }
-        __syncthreads();
-        // 2. rows below: x L_JJ^T = a  (forward substitution along the row)
-        const int nrow = NB - 32 - j0;
-        if (tid < nrow) {
-            const int i = j0 + 32 + tid;
+            // inverse of L_JJ by substitution, lane jc = column (rows i < jc stay 0)
+            const int jc = lane & 31;
             float x[32];
 #pragma unroll
-            for (int c = 0; c < 32; ++c) {
-                float v = S[(j0 + c) * LDS_LD + i];
+            for (int i = 0; i < 32; ++i) {
+                float v = (i == jc) ? 1.0f : 0.0f;
 #pragma unroll
-                for (int k = 0; k < c; ++k) v = v - x[k] * S[(j0 + k) * LDS_LD + j0 + c];
-                x[c] = v / S[(j0 + c) * LDS_LD + j0 + c];
+                for (int k = 0; k < i; ++k) v = v - S[(j0 + k) * LDS_LD + j0 + i] * x[k];
+                x[i] = v * __builtin_amdgcn_rcpf(S[(j0 + i) * LDS_LD + j0 + i]);
             }
+            if (lane < 32) {
 #pragma unroll
-            for (int c = 0; c < 32; ++c) S[(j0 + c) * LDS_LD + i] = x[c];
+                for (int i = 0; i < 32; ++i) V[(j0 + jc) * LDS_LD + j0 + i] = x[i];
+            }
         }
         __syncthreads();
-        // 3. trailing update of rows/cols j0+32 .. 127 (lower 4 x 4 blocks)
-        const int rem = NB - 32 - j0;
-        const int nb4 = rem / 4;
-        for (int b = tid; b < nb4 * nb4; b += 256) {
-            const int bi = b % nb4, bk = b / nb4;
-            if (bk > bi) continue;
-            const int ib = j0 + 32 + 4 * bi, kb = j0 + 32 + 4 * bk;
-            float acc[4][4];
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = 0.0f;
-            for (int c = 0; c < 32; ++c) {
-                const float *col = S + (j0 + c) * LDS_LD;
-                float xi[4], xk[4];
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    xi[x] = col[ib + x];
-                    xk[x] = col[kb + x];
-                }
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] += xi[x] * xk[y];
+        // 2. blocks below: L_IJ = A_IJ inv(L_JJ)^T, one block per wave
+        {
+            const int I = J + 1 + wave;
+            if (I < 4) {
+                v16f acc = blk_mma<true>(S + j0 * LDS_LD + 32 * I, LDS_LD, V + j0 * LDS_LD + j0, LDS_LD,
+                                         zero16(), lane);
+                blk_store(S + j0 * LDS_LD + 32 * I, LDS_LD, acc, lane, 1.0f, false);
             }
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) S[(kb + y) * LDS_LD + ib + x] -= acc[x][y];
+        }
+        __syncthreads();
+        // 3. trailing blocks (I, K), J < K <= I: A_IK -= L_IJ L_KJ^T
+        {
+            const int rem = 3 - J;                 // block rows below J
+            const int npair = rem * (rem + 1) / 2;
+            for (int pidx = wave; pidx < npair; pidx += 4) {
+                int Kr = 0;
+                while ((Kr + 1) * (Kr + 2) / 2 <= pidx) ++Kr;  // pidx -> (Ir >= Kr) pairs
+                const int Ir = Kr, Kc = pidx - Kr * (Kr + 1) / 2;
+                const int I = J + 1 + Ir, K = J + 1 + Kc;
+                v16f acc = blk_mma<true>(S + j0 * LDS_LD + 32 * I, LDS_LD, S + j0 * LDS_LD + 32 * K, LDS_LD,
+                                         zero16(), lane);
+                blk_store(S + (32 * K) * LDS_LD + 32 * I, LDS_LD, acc, lane, -1.0f, true);
+            }
         }
         __syncthreads();
     }
@@ -161,44 +194,18 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
         *reinterpret_cast<float4 *>(Ablk + (int64_t)c * ld + r4) = v;
     }
 
-    // inverse, diagonal 32 x 32 blocks: wave w inverts block w; lane%32 = column
-    {
-        const int base = 32 * wave;
-        const int jc = lane & 31;
-        float x[32];
-#pragma unroll
-        for (int i = 0; i < 32; ++i) {
-            float v = (i == jc) ? 1.0f : 0.0f;
-#pragma unroll
-            for (int k = 0; k < i; ++k) v = v - S[(base + k) * LDS_LD + base + i] * x[k];
-            x[i] = v / S[(base + i) * LDS_LD + base + i];
-        }
-        if (lane < 32) {
-#pragma unroll
-            for (int i = 0; i < 32; ++i) V[(base + jc) * LDS_LD + base + i] = x[i];
-        }
-    }
-    __syncthreads();
-    // off-diagonal blocks by distance d = I - J
+    // off-diagonal blocks of the inverse by distance d = I - J (one block per wave)
     for (int d = 1; d < 4; ++d) {
-        const int nblk = 4 - d;
-        for (int e = tid; e < nblk * 1024; e += 256) {
-            const int blk = e >> 10, rr = e & 31, cc = (e >> 5) & 31;
-            const int J = blk, I = J + d;
-            float v = 0.0f;
+        const int J = wave, I = J + d;
+        if (I < 4) {
+            float *Tw = T + wave * 32 * TLD;
+            v16f acc = zero16();
             for (int K = J; K < I; ++K)
-                for (int q = 0; q < 32; ++q)
-                    v += S[(32 * K + q) * LDS_LD + 32 * I + rr] * V[(32 * J + cc) * LDS_LD + 32 * K + q];
-            T[blk * 32 * TLD + cc * TLD + rr] = v;
-        }
-        __syncthreads();
-        for (int e = tid; e < nblk * 1024; e += 256) {
-            const int blk = e >> 10, rr = e & 31, cc = (e >> 5) & 31;
-            const int J = blk, I = J + d;
-            float v = 0.0f;
-            for (int q = 0; q < 32; ++q)
-                v += V[(32 * I + q) * LDS_LD + 32 * I + rr] * T[blk * 32 * TLD + cc * TLD + q];
-            V[(32 * J + cc) * LDS_LD + 32 * I + rr] = -v;
+                acc = blk_mma<false>(S + (32 * K) * LDS_LD + 32 * I, LDS_LD, V + (32 * J) * LDS_LD + 32 * K,
+                                     LDS_LD, acc, lane);
+            blk_store(Tw, TLD, acc, lane, 1.0f, false);
+            v16f acc2 = blk_mma<false>(V + (32 * I) * LDS_LD + 32 * I, LDS_LD, Tw, TLD, zero16(), lane);
+            blk_store(V + (32 * J) * LDS_LD + 32 * I, LDS_LD, acc2, lane, -1.0f, false);
         }
         __syncthreads();
     }
