@@ -90,7 +90,7 @@ void mag_opts_default(mag_opts *opts);
 typedef struct {
     int32_t status;        /* return code of the call                                     */
     int32_t outer_iters;   /* residual evaluations                                        */
-    int32_t gmres_iters;   /* inner GMRES iterations                                      */
+    int32_t gmres_iters;   /* inner corrections: plain refinement steps + GMRES iterations */
     int32_t shifted;       /* 1 if the FP32 factor was taken of Z + shift*I after breakdown */
     double shift;          /* the diagonal shift used (0 if none)                          */
     double resid_inf;      /* ||1 - Z w||_inf as last evaluated on the device (FP64)       */

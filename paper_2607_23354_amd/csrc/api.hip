@@ -271,23 +271,52 @@ int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64
     double rnorm = INFINITY, best_norm = INFINITY;
     int rc = MAG_ENOCONV;
     int outer = 0, inner_total = 0;
-    for (outer = 0; outer < std::max(1, o.max_outer); ++outer) {
+    // Corrections start as plain refinement steps x += M^{-1} r, which gain
+    // about -log10(cond(M^{-1} Z) - 1) digits each when the factor is accurate
+    // for this Z; as soon as one gains less than two digits (or none), the
+    // iteration restarts from the best iterate with GMRES corrections.
+    bool plain = true, last_plain = false;
+    auto residual = [&]() -> int {
         launch_zmv(s, X, n, m, t, v.x, v.r, bb, 1, partial, v.dsc);
         HIPCHK(hipMemcpyAsync(hs, v.dsc, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hs + 8, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (((const int *)(hs + 8))[kStSpinTimeout]) return MAG_EINTERNAL;
+        return MAG_OK;
+    };
+    for (outer = 0; outer < std::max(1, o.max_outer); ++outer) {
+        CHK(residual());
         const double prev = rnorm;
         rnorm = hs[0];
-        if (!(rnorm < best_norm)) break;  // no progress: keep the best iterate
-        best_norm = rnorm;
-        launch_copy(s, v.x, v.best, npad);
+        bool reverted = false;
+        if (!(rnorm < best_norm)) {
+            if (!last_plain) break;  // no progress: keep the best iterate
+            // the plain step did not help: back to the best iterate, GMRES from there
+            plain = last_plain = false;
+            reverted = true;
+            launch_copy(s, v.best, v.x, npad);
+            if (++outer >= std::max(1, o.max_outer)) break;
+            CHK(residual());
+            rnorm = hs[0];
+        } else {
+            best_norm = rnorm;
+            launch_copy(s, v.x, v.best, npad);
+        }
         if (rnorm <= tol) {
             rc = MAG_OK;
             break;
         }
-        if (outer > 0 && rnorm > 0.5 * prev) break;  // stagnation
+        if (last_plain && rnorm > 1e-2 * prev) plain = false;
+        else if (!last_plain && !reverted && outer > 0 && rnorm > 0.5 * prev) break;  // stagnation
         if (inner_total >= max_gmres) break;
+        if (plain) {
+            prec(v.r, v.z, v.ytmp);
+            launch_axpy1(s, v.z, v.x, npad);
+            ++inner_total;
+            last_plain = true;
+            continue;
+        }
+        last_plain = false;
         // GMRES(restart) on M^{-1} Z d = M^{-1} r, d0 = 0
         prec(v.r, v.z, v.ytmp);
         launch_nrm2(s, v.z, npad, partial, v.dsc + 1);

@@ -26,9 +26,11 @@ def test_weighting_batch_uneven(mag):
         assert np.abs(oracle.residual(Xb, t, wb)).max() <= 1e-12, b
         ref = oracle.weighting(Xb, t)
         assert abs(Ms[b] - ref.M) / abs(ref.M) <= 1e-10
+        # the single solve takes other correction steps (plain refinement first),
+        # so the two agree to the solves' accuracy, not bitwise
         single = mag.weighting(dev(Xb), t)
         ws = single.w.cpu().numpy()
-        assert np.abs(wb - ws).max() <= 1e-12 * max(1.0, np.abs(ws).max())
+        assert np.abs(wb - ws).max() <= 1e-10 * max(1.0, np.abs(ws).max())
         assert infos[b]["argmin_w"] == int(np.argmin(wb))
 
 
