@@ -222,6 +222,30 @@ int mag_tplus_batch(mag_ctx *ctx, int32_t B, const double *X, const int64_t *off
                     const mag_tplus_opts *topts, const mag_opts *sopts, double *t_plus, double *w,
                     mag_tplus_info *info);
 
+/* ---- tuning ----------------------------------------------------------------
+ * The single-solve FP32 factor works in panels of 512 columns (256 is the
+ * alternative: shorter serial panel work, shallower trailing updates).  The
+ * choice is kept on the context per size bucket: the smallest b with
+ * npad <= 2^b. */
+
+/* Set the panel width (256 or 512; 0 restores the built-in 512) for the size
+ * bucket of n.  MAG_EINVAL for other widths or n < 1. */
+int mag_tune_panel(mag_ctx *ctx, int64_t n, int32_t nb);
+
+/* Time the FP32 tile generation + factor of this problem (X: device, n x m)
+ * with each panel width, best of `reps` runs each (reps < 1 means 1), and keep
+ * the faster for n's size bucket.  nb_out (HOST, may be NULL) receives the
+ * choice; ms_out (HOST, 2 doubles, may be NULL) the best times for 256 and
+ * 512.  Uses the context's factor workspace (npad^2 floats). */
+int mag_autotune(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, int32_t reps,
+                 int32_t *nb_out, double *ms_out);
+
+/* Write the tuned table to a JSON text file ({"panel": {"<bucket>": nb, ...}}),
+ * or read one written by mag_tune_save into the context (entries not in the
+ * file are left as they are).  MAG_EINVAL on I/O or format errors. */
+int mag_tune_save(const mag_ctx *ctx, const char *path);
+int mag_tune_load(mag_ctx *ctx, const char *path);
+
 /* ---- kernel-level entry points --------------------------------------------
  * The steps of the FP32_IR path exposed one by one, for parity tests and
  * profiling.  npad = mag_padded_size(n) = n rounded up to a multiple of 256.

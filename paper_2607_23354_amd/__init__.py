@@ -11,6 +11,7 @@ Z w = 1 and the magnitude is 1^T w.
 from __future__ import annotations
 
 import ctypes
+import os
 from dataclasses import dataclass
 
 import torch
@@ -68,6 +69,14 @@ class Context:
 
 
 _default: dict[int, Context] = {}
+
+
+def _default_ctx(device: int) -> Context:
+    c = _default.get(device)
+    if c is None:
+        c = _default[device] = Context(device)
+    c._sync_stream()
+    return c
 
 
 def _ctx(ctx: Context | None, X: torch.Tensor) -> Context:
@@ -383,3 +392,31 @@ def tplus_batch(X: torch.Tensor, offs, *, ctx: Context | None = None, grid: int 
     _lib.check(c.lib.mag_tplus_batch(c.handle, B, _ptr(X), arr, m, ctypes.byref(to), ctypes.byref(o), tp,
                                      _ptr(w), infos), "mag_tplus_batch")
     return list(tp), w, [i.as_dict() for i in infos]
+
+
+def tune_panel(n: int, nb: int, *, ctx: Context | None = None, device: int = 0) -> None:
+    """Panel width (256 or 512; 0 = built-in) of the FP32 factor for n's size bucket."""
+    c = ctx if ctx is not None else _default_ctx(device)
+    _lib.check(c.lib.mag_tune_panel(c.handle, int(n), int(nb)), "mag_tune_panel")
+
+
+def autotune(X: torch.Tensor, t: float, *, reps: int = 2, ctx: Context | None = None):
+    """Time the FP32 factor of this problem with panel widths 256 and 512 and
+    keep the faster for its size bucket; returns (width, (ms_256, ms_512))."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    nb = ctypes.c_int32(0)
+    ms = (ctypes.c_double * 2)()
+    _lib.check(c.lib.mag_autotune(c.handle, _ptr(X), n, m, float(t), int(reps), ctypes.byref(nb), ms), "mag_autotune")
+    return nb.value, (ms[0], ms[1])
+
+
+def tune_save(path: str, *, ctx: Context | None = None, device: int = 0) -> None:
+    c = ctx if ctx is not None else _default_ctx(device)
+    _lib.check(c.lib.mag_tune_save(c.handle, os.fsencode(path)), "mag_tune_save")
+
+
+def tune_load(path: str, *, ctx: Context | None = None, device: int = 0) -> None:
+    c = ctx if ctx is not None else _default_ctx(device)
+    _lib.check(c.lib.mag_tune_load(c.handle, os.fsencode(path)), "mag_tune_load")

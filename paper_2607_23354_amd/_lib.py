@@ -117,6 +117,11 @@ SIGNATURES = {
                                      ctypes.POINTER(MagOpts), ctypes.POINTER(MagInfo)]),
     "mag_dmin": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(_d)]),
     "mag_padded_size": (_i64, [_i64]),
+    "mag_tune_panel": (ctypes.c_int, [_vp, _i64, _i32]),
+    "mag_autotune": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _i32, ctypes.POINTER(_i32),
+                                    ctypes.POINTER(_d)]),
+    "mag_tune_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
+    "mag_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "mag_zmatvec": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp]),
     "mag_residual": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp, ctypes.POINTER(_d)]),
     "mag_tile32": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp]),

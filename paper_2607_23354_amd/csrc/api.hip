@@ -19,6 +19,9 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
 #include <vector>
 
 namespace mag {
@@ -211,7 +214,7 @@ int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Facto
             ft->used = 0;
             ft->flops.clear();
         }
-        chol32_factor(s, F.A, F.npad, n, F.dinv, status, ft);
+        chol32_factor(s, F.A, F.npad, n, F.dinv, status, ft, panel_width(ctx, F.npad));
         HIPCHK(hipMemcpyAsync(hs, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (((const int *)hs)[kStBreakdown] == 0) break;
@@ -777,6 +780,115 @@ int mag_set_stream(mag_ctx *c, void *stream)
 
 int64_t mag_padded_size(int64_t n) { return n < 1 ? 0 : round_up(n, kPad); }
 
+int mag_tune_panel(mag_ctx *c, int64_t n, int32_t nb)
+{
+    if (!c || n < 1 || (nb != 0 && nb != 256 && nb != 512)) return MAG_EINVAL;
+    c->tune_panel[size_bucket(round_up(n, kPad))] = nb;
+    return MAG_OK;
+}
+
+int mag_autotune(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, int32_t reps,
+                 int32_t *nb_out, double *ms_out)
+{
+    if (!c || !valid_args(X, n, m, t)) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    CHK(ensure_common(c, n, 1));
+    CHK(check_points(c, X, n, m));
+    CHK(ensure_ctx_factor(c, n));
+    const int64_t npad = round_up(n, kPad);
+    hipStream_t s = c->stream;
+    float *A = (float *)c->factor.p;
+    float *dinv = (float *)c->dinv.p;
+    int *status = (int *)c->ints.p + kIntStatus;
+    const int widths[2] = {256, 512};
+    double best[2] = {INFINITY, INFINITY};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = MAG_OK;
+    for (int rep = 0; rep < std::max(1, reps) && rc == MAG_OK; ++rep) {
+        for (int q = 0; q < 2; ++q) {
+            launch_fill_ints(s, status, 8, 0);
+            if (hipEventRecord(e0, s) != hipSuccess) { rc = MAG_EHIP; break; }
+            launch_tilegen32(s, X, n, m, t, A, npad, 0.0f);
+            chol32_factor(s, A, npad, n, dinv, status, nullptr, widths[q]);
+            float ms = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = MAG_EHIP;
+                break;
+            }
+            best[q] = std::min(best[q], (double)ms);
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != MAG_OK) return rc;
+    const int pick = (best[0] < best[1]) ? 256 : 512;
+    c->tune_panel[size_bucket(npad)] = pick;
+    if (nb_out) *nb_out = pick;
+    if (ms_out) {
+        ms_out[0] = best[0];
+        ms_out[1] = best[1];
+    }
+    return MAG_OK;
+}
+
+int mag_tune_save(const mag_ctx *c, const char *path)
+{
+    if (!c || !path) return MAG_EINVAL;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return MAG_EINVAL;
+    std::fprintf(f, "{\"panel\": {");
+    bool first = true;
+    for (int b = 0; b < 64; ++b) {
+        if (c->tune_panel[b] == 0) continue;
+        std::fprintf(f, "%s\"%d\": %d", first ? "" : ", ", b, c->tune_panel[b]);
+        first = false;
+    }
+    std::fprintf(f, "}}\n");
+    return std::fclose(f) == 0 ? MAG_OK : MAG_EINVAL;
+}
+
+int mag_tune_load(mag_ctx *c, const char *path)
+{
+    if (!c || !path) return MAG_EINVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return MAG_EINVAL;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    const size_t key = text.find("\"panel\"");
+    if (key == std::string::npos) return MAG_EINVAL;
+    size_t p = text.find('{', key);
+    const size_t end = (p == std::string::npos) ? std::string::npos : text.find('}', p);
+    if (end == std::string::npos) return MAG_EINVAL;
+    int staged[64] = {};
+    bool any[64] = {};
+    while (true) {
+        const size_t q0 = text.find('"', p + 1);
+        if (q0 == std::string::npos || q0 > end) break;
+        const size_t q1 = text.find('"', q0 + 1);
+        const size_t colon = (q1 == std::string::npos) ? std::string::npos : text.find(':', q1);
+        if (colon == std::string::npos || colon > end) return MAG_EINVAL;
+        char *stop = nullptr;
+        const long b = std::strtol(text.c_str() + q0 + 1, &stop, 10);
+        if (stop != text.c_str() + q1 || b < 0 || b >= 64) return MAG_EINVAL;
+        const long v = std::strtol(text.c_str() + colon + 1, &stop, 10);
+        if (stop == text.c_str() + colon + 1 || (v != 0 && v != 256 && v != 512)) return MAG_EINVAL;
+        staged[b] = (int)v;
+        any[b] = true;
+        p = (size_t)(stop - text.c_str());
+    }
+    for (int b = 0; b < 64; ++b)
+        if (any[b]) c->tune_panel[b] = staged[b];
+    return MAG_OK;
+}
+
+
+
 int mag_dmin(mag_ctx *c, const double *X, int64_t n, int32_t m, double *d_min)
 {
     if (!c || !X || !d_min || n < 2 || m < 1) return MAG_EINVAL;
@@ -902,7 +1014,7 @@ int mag_factor32(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, do
     int *status = (int *)c->ints.p;
     launch_fill_ints(c->stream, status, 8, 0);
     launch_tilegen32(c->stream, X, n, m, t, L, npad, (float)shift);
-    chol32_factor(c->stream, L, npad, n, dinv, status, nullptr);
+    chol32_factor(c->stream, L, npad, n, dinv, status, nullptr, panel_width(c, npad));
     HIPCHK(hipMemcpyAsync(c->host_scalars, status, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     if (breakdown) *breakdown = ((const int *)c->host_scalars)[kStBreakdown];

@@ -3,8 +3,8 @@
 // Z is symmetric positive definite for distinct Euclidean points (Sections 2
 // and 3.2), so Z = L L^T exists; this factor is computed in FP32 and used as
 // the preconditioner of the FP64 refinement.  For each panel of nb = 512
-// columns starting at k (256 for a last, narrower panel), made of 128-column
-// sub-panels s:
+// columns (or 256, the tunable choice) starting at k (256 for a last,
+// narrower panel), made of 128-column sub-panels s:
 //   1. potrf128   factor of the 128 x 128 diagonal block and its inverse
 //   2. trsm       rows below:  L21 = A21 * inv(L11)^T     (MFMA, in place),
 //                 with L21^T written into the upper triangle
@@ -24,10 +24,10 @@ namespace mag {
 // Factor the padded npad x npad FP32 matrix A (column-major, ld = npad) in place.
 // update_events (optional) records an event pair around every trailing update.
 void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv, int *status,
-                   FactorTimer *timer)
+                   FactorTimer *timer, int nb_max)
 {
     const int64_t T = kTile;
-    constexpr int64_t kNb = 512;
+    const int64_t kNb = (nb_max == 256) ? 256 : 512;
     for (int64_t k = 0; k < npad; k += kNb) {
         const int64_t nb = std::min<int64_t>(kNb, npad - k);
         const int64_t nsub = nb / T;
@@ -73,6 +73,19 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
             if (timer) hipEventRecord(e1, s);
         }
     }
+}
+
+int size_bucket(int64_t npad)
+{
+    int b = 0;
+    while (b < 63 && ((int64_t)1 << b) < npad) ++b;
+    return b;
+}
+
+int panel_width(const mag_ctx *ctx, int64_t npad)
+{
+    const int v = ctx ? ctx->tune_panel[size_bucket(npad)] : 0;
+    return (v == 256 || v == 512) ? v : 512;
 }
 
 }  // namespace mag

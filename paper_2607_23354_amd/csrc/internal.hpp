@@ -136,6 +136,9 @@ struct mag_ctx {
     double *host_scalars = nullptr;  // pinned host staging (64 doubles)
     void *blas = nullptr;            // rocblas_handle (lazy, FP64 comparator)
     int64_t cu_count = 256;
+    // tuned panel width of the single-solve FP32 factor per size bucket
+    // (bucket = bit length of npad); 0 = the built-in choice
+    int tune_panel[64] = {};
 };
 
 namespace mag {
@@ -152,8 +155,12 @@ struct FactorTimer {
     std::vector<double> flops;
     size_t used = 0;
 };
+// nb: panel width, 256 or 512 (npad is a multiple of 256)
 void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv, int *status,
-                   FactorTimer *timer);
+                   FactorTimer *timer, int nb);
+// panel width for npad on this context: the tuned entry of its size bucket, else 512
+int panel_width(const mag_ctx *ctx, int64_t npad);
+int size_bucket(int64_t npad);
 size_t dmin_partial_doubles(int64_t n);
 size_t blas1_partial_doubles(int kmax);
 

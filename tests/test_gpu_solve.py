@@ -144,3 +144,27 @@ def test_ill_conditioned_small_t(mag):
     w = res.w.cpu().numpy()
     print("small-t case:", {k: res.info[k] for k in ("shifted", "shift", "outer_iters", "gmres_iters")})
     check_against_oracle(X, t, w, M_gpu=res.info["magnitude"])
+
+
+def test_autotune_panel_width_and_table_file(mag, tmp_path):
+    # both panel widths give a valid preconditioner; the autotuner keeps the faster
+    X = W.gaussian(3000, 3, seed=31)
+    t = W.gaussian_cutoff_estimate(3000, 3)
+    for nb in (256, 512):
+        mag.tune_panel(len(X), nb)
+        res = mag.weighting(dev(X), t)
+        check_against_oracle(X, t, res.w.cpu().numpy(), M_gpu=res.info["magnitude"])
+    nb, ms = mag.autotune(dev(X), t, reps=2)
+    assert nb in (256, 512) and all(v > 0 for v in ms)
+    assert nb == (256 if ms[0] < ms[1] else 512)
+    path = str(tmp_path / "tune.json")
+    mag.tune_save(path)
+    mag.tune_panel(len(X), 0)
+    mag.tune_load(path)
+    text = open(path).read()
+    assert '"panel"' in text and str(nb) in text
+    res = mag.weighting(dev(X), t)
+    check_against_oracle(X, t, res.w.cpu().numpy(), M_gpu=res.info["magnitude"])
+    print(f"autotune n=3000: picked {nb}, ms(256, 512) = {ms}")
+    with pytest.raises(mag.MagError):
+        mag.tune_panel(len(X), 384)
