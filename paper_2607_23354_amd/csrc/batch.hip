@@ -323,6 +323,7 @@ int batch_factor(Batch &bt, std::vector<int> &shifted)
 struct BRefine {
     double best = INFINITY, rnorm = INFINITY, prev = INFINITY, tol = 1e-12;
     int outer = 0, inner = 0, done = 0, ok = 0;
+    int plain = 1, last_plain = 0, reverted = 0;  // plain refinement steps first (see refine_core)
     std::vector<double> H, cs, sn, g;
     int kdone = 0, inner_done = 0;
     double beta = 0.0;
@@ -347,8 +348,8 @@ int batch_refine(Batch &bt, const std::vector<int> &ids, int rhs_slot, const std
         st[p].g.assign(R + 1, 0.0);
     }
     auto prec_units = [&](int p) { return prec_b_units(bt.h[p].npad); };
-    auto zmv_units = [&](int p) { return zmv_b_units(bt.h[p].n); };
-    auto red_units = [&](int p) { return bt.h[p].npad / 256; };
+    auto zmv_units = [&](int p) { return zmv_b_units(bt.h[p].n, bt.m); };
+    auto red_units = [&](int p) { return zmv_b_reduce_units(bt.h[p].n, bt.m); };
     auto one = [&](int) { return (int64_t)1; };
 
     // x0 = M^{-1} b
@@ -369,25 +370,42 @@ int batch_refine(Batch &bt, const std::vector<int> &ids, int rhs_slot, const std
         BRC(bt.make_work(L, one, false, w1));
         launch_zmv_b(bt.s, bt.m, bt.d, wz, wr, S.X, S.Rr, rhs_slot, 1, SC_RNORM);
         BRC(bt.gather(w1.plist, w1.na, SC_RNORM, 1, hv));
-        std::vector<int> G;  // problems that run GMRES this outer step
+        std::vector<int> G;        // problems that improved (>= 0: and take a correction)
+        std::vector<int> revert;   // plain step without progress: back to the best iterate
         for (size_t i = 0; i < L.size(); ++i) {
             const int p = L[i];
             BRefine &r = st[p];
             r.prev = r.rnorm;
             r.rnorm = hv[i];
             r.outer = outer + 1;
-            if (!(r.rnorm < r.best)) {
-                r.done = 1;
+            const int was_reverted = r.reverted;
+            r.reverted = 0;
+            // after a revert x is the best iterate again: its residual equals the best one
+            if (!(r.rnorm < r.best) && !was_reverted) {
+                if (!r.last_plain) {
+                    r.done = 1;
+                    continue;
+                }
+                // the residual is recomputed from the best iterate next outer step
+                r.plain = r.last_plain = 0;
+                r.reverted = 1;
+                revert.push_back(p);
                 continue;
             }
             r.best = r.rnorm;
             if (r.rnorm <= r.tol) {
                 r.done = 1;
                 r.ok = 1;
-                G.push_back(-1 - p);  // mark: copy x to best, no GMRES
+                G.push_back(-1 - p);  // mark: copy x to best, no correction
                 continue;
             }
-            if ((outer > 0 && r.rnorm > 0.5 * r.prev) || r.inner >= max_gmres) {
+            if (r.last_plain && r.rnorm > 1e-2 * r.prev) r.plain = 0;
+            else if (!r.last_plain && !was_reverted && outer > 0 && r.rnorm > 0.5 * r.prev) {
+                r.done = 1;  // stagnation
+                G.push_back(-1 - p);
+                continue;
+            }
+            if (r.inner >= max_gmres) {
                 r.done = 1;
                 G.push_back(-1 - p);
                 continue;
@@ -395,16 +413,36 @@ int batch_refine(Batch &bt, const std::vector<int> &ids, int rhs_slot, const std
             G.push_back(p);
         }
         // keep the best iterate of every problem that improved
-        std::vector<int> improved, run;
+        std::vector<int> improved, run, plain;
         for (int g : G) {
             improved.push_back(g < 0 ? -1 - g : g);
-            if (g >= 0) run.push_back(g);
+            if (g >= 0) (st[g].plain ? plain : run).push_back(g);
         }
         if (!improved.empty()) {
             BWork wi;
             BRC(bt.make_work(improved, one, false, wi));
             launch_copy_b(bt.s, bt.d, wi.plist, wi.na, bt.maxpad, S.X, S.Best);
         }
+        if (!revert.empty()) {
+            BWork wv;
+            BRC(bt.make_work(revert, one, false, wv));
+            launch_copy_b(bt.s, bt.d, wv.plist, wv.na, bt.maxpad, S.Best, S.X);
+        }
+        if (!plain.empty()) {
+            // x += M^{-1} r
+            BWork pp, p1;
+            BRC(bt.make_work(plain, prec_units, false, pp));
+            BRC(bt.make_work(plain, one, false, p1));
+            launch_prec_apply_b(bt.s, bt.d, pp, S.Rr, S.Y, S.Z);
+            const double *ones = bt.put(std::vector<double>(plain.size(), 1.0), false);
+            if (!ones) return MAG_ENOMEM;
+            launch_multi_axpy_hb(bt.s, bt.d, p1.plist, p1.na, bt.maxpad, S.Z, 1, ones, S.X, 1.0);
+            for (int p : plain) {
+                ++st[p].inner;
+                st[p].last_plain = 1;
+            }
+        }
+        for (int p : run) st[p].last_plain = 0;
         if (run.empty()) continue;
         BWork gp, g1;
         BRC(bt.make_work(run, prec_units, false, gp));

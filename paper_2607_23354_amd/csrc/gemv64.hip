@@ -111,9 +111,9 @@ __device__ inline void tri_tile(int64_t idx, int64_t &I, int64_t &J)
 // column sums sum_r Z(r, c0 + p) v_r (off-diagonal tiles only; a diagonal
 // tile is summed over its full square as rows).  M > 0: compile-time m.
 template <int M>
-__global__ void __launch_bounds__(256)
-k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const double *__restrict__ v,
-          double *__restrict__ part)
+__device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64_t n, int m_rt, double t,
+                                             const double *__restrict__ v, double *__restrict__ part,
+                                             int64_t tile)
 {
     constexpr int MM = (M > 0) ? M : MMAX_SYM;
     __shared__ double Xr[MM][TS];
@@ -122,7 +122,7 @@ k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const dou
     __shared__ double red[4][TS];
     const int m = (M > 0) ? M : m_rt;
     int64_t I, J;
-    tri_tile(blockIdx.x, I, J);
+    tri_tile(tile, I, J);
     const int64_t r0 = I * TS, c0 = J * TS;
     const bool diag = (I == J);
     const int tid = threadIdx.x;
@@ -178,7 +178,7 @@ k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const dou
         }
         colsum[jj] = colacc;
     }
-    double *pt = part + (int64_t)blockIdx.x * 2 * TS;
+    double *pt = part + tile * 2 * TS;
     // rows: sum over the 16 tx lanes (contiguous) by a fixed butterfly
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) {
@@ -214,12 +214,20 @@ k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const dou
 // Block I of y (rows r0 .. r0 + TS): sum of the row sums of tiles (I, 0..I)
 // and the column sums of tiles (I+1..T-1, I), in that order.  mode 0: y = Z v;
 // mode 1: y = b - Z v (b == NULL: ones) and blkmax[I] = max |y| over the block.
-__global__ void __launch_bounds__(TS)
-k_zmv_sym_reduce(const double *__restrict__ part, int64_t T, int64_t n, int64_t npad, double *__restrict__ y,
-                 const double *__restrict__ b, int mode, double *__restrict__ blkmax)
+template <int M>
+__global__ void __launch_bounds__(256)
+k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const double *__restrict__ v,
+          double *__restrict__ part)
+{
+    zmv_sym_body<M>(X, n, m_rt, t, v, part, blockIdx.x);
+}
+
+__device__ __forceinline__ void zmv_sym_reduce_body(const double *__restrict__ part, int64_t T, int64_t n,
+                                                    int64_t npad, double *__restrict__ y,
+                                                    const double *__restrict__ b, int mode,
+                                                    double *__restrict__ blkmax, int64_t I)
 {
     __shared__ double red[TS];
-    const int64_t I = blockIdx.x;
     const int p = threadIdx.x;
     const int64_t row = I * TS + p;
     double s = 0.0;
@@ -238,6 +246,53 @@ k_zmv_sym_reduce(const double *__restrict__ part, int64_t T, int64_t n, int64_t 
         }
         if (p == 0) blkmax[I] = red[0];
     }
+}
+
+__global__ void __launch_bounds__(TS)
+k_zmv_sym_reduce(const double *__restrict__ part, int64_t T, int64_t n, int64_t npad, double *__restrict__ y,
+                 const double *__restrict__ b, int mode, double *__restrict__ blkmax)
+{
+    zmv_sym_reduce_body(part, T, n, npad, y, b, mode, blkmax, blockIdx.x);
+}
+
+// Batched symmetric Z v: units T(T+1)/2 tiles per problem (T = npad / TS),
+// then the per-block reduce (units T per problem); blkmax after the tiles.
+template <int M>
+__global__ void __launch_bounds__(256) k_zmv_sym_b(const BProb *__restrict__ P, BWork w, int v_slot)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    zmv_sym_body<M>(q.X, q.n, q.m, q.t, q.vec + (int64_t)v_slot * q.npad, q.partial, blockIdx.x - w.pref[i]);
+}
+
+__global__ void __launch_bounds__(TS)
+k_zmv_sym_reduce_b(const BProb *__restrict__ P, BWork w, int y_slot, int b_slot, int mode)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    const int64_t T = q.npad / TS;
+    zmv_sym_reduce_body(q.partial, T, q.n, q.npad, q.vec + (int64_t)y_slot * q.npad,
+                        b_slot >= 0 ? q.vec + (int64_t)b_slot * q.npad : nullptr, mode,
+                        q.partial + T * (T + 1) / 2 * 2 * TS, blockIdx.x - w.pref[i]);
+}
+
+__global__ void __launch_bounds__(256) k_max_final_sym_b(const BProb *__restrict__ P, BWork w, int64_t out_off)
+{
+    __shared__ double red[256];
+    const BProb &q = P[w.plist[blockIdx.x]];
+    const int64_t T = q.npad / TS;
+    const double *blkmax = q.partial + T * (T + 1) / 2 * 2 * TS;
+    double v = 0.0;
+    for (int64_t e = threadIdx.x; e < T; e += 256) v = fmax(v, blkmax[e]);
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s2]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) q.scal[out_off] = red[0];
 }
 
 template <int M>
@@ -377,19 +432,44 @@ size_t zmv_partial_doubles(int64_t n)
     return std::max(sym, (size_t)(p.splits * p.npad + p.npad / 256 + 8));
 }
 
-int64_t zmv_b_units(int64_t n)
+int64_t zmv_b_units(int64_t n, int m)
 {
+    if (m <= MMAX_SYM) {
+        const int64_t T = ((n + kPad - 1) / kPad * kPad) / TS;
+        return T * (T + 1) / 2;
+    }
     Plan p = plan_for(n);
     return p.rowblocks * p.splits;
 }
 
+int64_t zmv_b_reduce_units(int64_t n, int m)
+{
+    const int64_t npad = (n + kPad - 1) / kPad * kPad;
+    return m <= MMAX_SYM ? npad / TS : npad / 256;
+}
+
 // Batched y_slot = Z v_slot (mode 0) or y_slot = b - Z v_slot with its max norm
-// into vec[norm_off] (mode 1).  wz: units zmv_b_units(n); wr: units npad/256.
+// into scal[norm_off] (mode 1).  wz: units zmv_b_units(n, m); wr: units
+// zmv_b_reduce_units(n, m).
 void launch_zmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const BWork &wr,
                   int v_slot, int y_slot, int b_slot, int mode, int64_t norm_off)
 {
     if (wz.na <= 0) return;
     const dim3 g((unsigned)wz.total);
+    if (m <= MMAX_SYM) {
+        switch (m) {
+        case 1: hipLaunchKernelGGL(k_zmv_sym_b<1>, g, dim3(256), 0, s, P, wz, v_slot); break;
+        case 2: hipLaunchKernelGGL(k_zmv_sym_b<2>, g, dim3(256), 0, s, P, wz, v_slot); break;
+        case 3: hipLaunchKernelGGL(k_zmv_sym_b<3>, g, dim3(256), 0, s, P, wz, v_slot); break;
+        case 4: hipLaunchKernelGGL(k_zmv_sym_b<4>, g, dim3(256), 0, s, P, wz, v_slot); break;
+        case 8: hipLaunchKernelGGL(k_zmv_sym_b<8>, g, dim3(256), 0, s, P, wz, v_slot); break;
+        default: hipLaunchKernelGGL(k_zmv_sym_b<0>, g, dim3(256), 0, s, P, wz, v_slot); break;
+        }
+        hipLaunchKernelGGL(k_zmv_sym_reduce_b, dim3((unsigned)wr.total), dim3(TS), 0, s, P, wr, y_slot, b_slot, mode);
+        if (mode == 1)
+            hipLaunchKernelGGL(k_max_final_sym_b, dim3(wz.na), dim3(256), 0, s, P, wz, norm_off);
+        return;
+    }
     switch (m) {
     case 1: hipLaunchKernelGGL(k_zmv_partial_b<1>, g, dim3(RT), 0, s, P, wz, v_slot); break;
     case 2: hipLaunchKernelGGL(k_zmv_partial_b<2>, g, dim3(RT), 0, s, P, wz, v_slot); break;

@@ -88,7 +88,8 @@ void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int6
 int64_t prec_b_units(int64_t npad);
 void launch_prec_apply_b(hipStream_t s, const BProb *P, const BWork &w, int rhs_slot, int tmp_slot,
                          int x_slot);
-int64_t zmv_b_units(int64_t n);
+int64_t zmv_b_units(int64_t n, int m);
+int64_t zmv_b_reduce_units(int64_t n, int m);
 void launch_zmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const BWork &wr, int v_slot,
                   int y_slot, int b_slot, int mode, int64_t norm_off);
 int64_t dz_b_units(int64_t n);
