@@ -7,14 +7,16 @@
 // Both are computed here by a single workgroup with the block held in LDS:
 //
 //   for each 32-column block J (right-looking):
-//     1. one wave factors the 32 x 32 diagonal block in registers
-//        (lane = row, pivots and columns broadcast with readlane) and
-//        inverts it by substitution;
-//     2. the blocks below are solved against it, L_IJ = A_IJ inv(L_JJ)^T;
-//     3. the trailing blocks are updated, A_IK -= L_IJ L_KJ^T;
-//   then the off-diagonal blocks of the inverse, by distance from the
-//   diagonal: Inv_IJ = -Inv_II sum_{K=J}^{I-1} L_IK Inv_KJ.
-// Steps 2, 3 and the inverse are 32 x 32 x 32 products on MFMA
+//     1. one wave factors the 32 x 32 diagonal block and builds its inverse
+//        in the same sweep, both as rank-1 updates on MFMA;
+//     2. the blocks below are solved against it, L_IJ = A_IJ inv(L_JJ)^T,
+//        and block row J of the inverse is scaled, Inv_JK = inv(L_JJ) Inv_JK;
+//     3. the trailing blocks are updated, A_IK -= L_IJ L_KJ^T, and so are
+//        the inverse's rows below, Inv_IK -= L_IJ Inv_JK; all but the block
+//        the next factor needs run on waves 1..3 while wave 0 factors.
+//   Steps 2 and 3 apply, block by block, L^{-1} = L_3^{-1} ... L_0^{-1}, where
+//   L_J is the identity with block column J of L.
+// Steps 2 and 3 are 32 x 32 x 32 products on MFMA
 // (v_mfma_f32_32x32x2f32, one product per wave).
 //
 // A pivot that is not positive (or not finite) marks status[0] with the
@@ -29,7 +31,6 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int NB = 128;
 constexpr int LDS_LD = 129;  // padded column stride of the LDS copy
-constexpr int TLD = 33;
 
 __device__ inline float bcast(float v, int src_lane)
 {
@@ -73,12 +74,40 @@ __device__ inline v16f zero16()
     return z;
 }
 
+// Step-J products after the panel solve, as a list of independent 32 x 32 items:
+//   trailing blocks    A_IK -= L_IJ L_KJ^T          (J < K <= I), pair (J+1, J+1) first
+//   inverse rows I>J   Inv_IK -= L_IJ Inv_JK        (K <= J; Inv_IJ starts at 0)
+// Items it = first, first + stride, ... < count run on this wave.
+__device__ inline void step_products(float *S, float *V, int J, int first, int stride, int lane)
+{
+    const int j0 = 32 * J;
+    const int rem = 3 - J;
+    const int npair = rem * (rem + 1) / 2;
+    const int nitems = npair + rem * (J + 1);
+    for (int it = first; it < nitems; it += stride) {
+        if (it < npair) {
+            int Kr = 0;
+            while ((Kr + 1) * (Kr + 2) / 2 <= it) ++Kr;
+            const int Kc = it - Kr * (Kr + 1) / 2;
+            const int I = J + 1 + Kr, K = J + 1 + Kc;
+            v16f acc = blk_mma<true>(S + j0 * LDS_LD + 32 * I, LDS_LD, S + j0 * LDS_LD + 32 * K, LDS_LD,
+                                     zero16(), lane);
+            blk_store(S + (32 * K) * LDS_LD + 32 * I, LDS_LD, acc, lane, -1.0f, true);
+        } else {
+            const int u = it - npair;
+            const int I = J + 1 + u / (J + 1), K = u % (J + 1);
+            v16f acc = blk_mma<false>(S + j0 * LDS_LD + 32 * I, LDS_LD, V + (32 * K) * LDS_LD + j0, LDS_LD,
+                                      zero16(), lane);
+            blk_store(V + (32 * K) * LDS_LD + 32 * I, LDS_LD, acc, lane, -1.0f, K < J);
+        }
+    }
+}
+
 __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld, int64_t k0,
                                               float *__restrict__ Linv, int *__restrict__ status)
 {
     __shared__ float S[NB * LDS_LD];    // L, column-major, S[c*LDS_LD + r]
     __shared__ float V[NB * LDS_LD];    // L^{-1}, same layout
-    __shared__ float T[3 * 32 * TLD];   // per-wave scratch for the off-diagonal inverse blocks
     __shared__ int bad;
 
     const int tid = threadIdx.x;
@@ -111,107 +140,111 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
 
     for (int J = 0; J < 4; ++J) {
         const int j0 = 32 * J;
-        // 1. factor and invert the diagonal 32 x 32 block in wave 0 (lanes 32..63 mirror 0..31)
-        if (wave == 0) {
-            const int rr = lane & 31;
-            float a[32];
+        // 1. factor the diagonal 32 x 32 block in wave 0 and invert it in the same
+        //    sweep, both as rank-1 updates on MFMA.  The symmetric block A is held
+        //    whole in an accumulator: lane (h, b), register r holds A(a, b) with
+        //    a = 8 (r / 4) + 4 h + r % 4, so row c (= column c) of A is register
+        //    r_c of the lanes of half h_c.  Step c: l = A(:, c) / sqrt(A(c, c)) is
+        //    column c of L; with m = l below the diagonal (zero elsewhere, and
+        //    zero in the other half so the MFMA's k-slot h_c carries it),
+        //    A -= m m^T.  The inverse Y (from I) takes the same elementary step
+        //    L_c^{-1} as one update Y += g Y(c, :) with g_c = 1/sqrt(A(c, c)) - 1
+        //    and g_k = -m_k / sqrt(A(c, c)) below.  Column c of L stays in the
+        //    lanes that computed it (register r_c) until the sweep ends.
+        if (wave != 0) {
+            // the previous step's products that this factor does not need (all but
+            // the trailing block (J, J), item 0), on waves 1..3 beside the factor
+            if (J > 0) step_products(S, V, J - 1, wave, 3, lane);
+        } else {
+            const int b = lane & 31, h = lane >> 5;
+            v16f accA, accY;
+            float Lc[16];
 #pragma unroll
-            for (int c = 0; c < 32; ++c) a[c] = S[(j0 + c) * LDS_LD + j0 + rr];
+            for (int r = 0; r < 16; ++r) {
+                const int a = 8 * (r >> 2) + 4 * h + (r & 3);
+                const int hiI = a > b ? a : b, loI = a > b ? b : a;
+                accA[r] = S[(j0 + loI) * LDS_LD + j0 + hiI];  // lower triangle, mirrored
+                accY[r] = (a == b) ? 1.0f : 0.0f;
+                Lc[r] = 0.0f;
+            }
+            int firstbad = -1;  // branch-free pivot check keeps the sweep one basic block
+            int bo = b, ho = h;
 #pragma unroll
             for (int c = 0; c < 32; ++c) {
-                float piv = bcast(a[c], c);
-                if (!(piv > 0.0f) || !isfinite(piv)) {
-                    if (lane == 0 && bad == 0) bad = (int)(k0 + j0 + c + 1);
-                    piv = 1.0f;
-                }
-                const float inv = rsqrtf(piv);
-                if (rr == c) a[c] = piv * inv;
-                else if (rr > c) a[c] = a[c] * inv;
-#pragma unroll
-                for (int k = c + 1; k < 32; ++k) {
-                    const float lkc = bcast(a[c], k);
-                    if (rr >= k) a[k] = a[k] - a[c] * lkc;
-                }
+                const int rc = 4 * (c >> 3) + (c & 3), hc = (c >> 2) & 1;
+                // lane predicates as 0/1 factors, recomputed per step (opaque lane ids
+                // keep the compiler from precomputing all 32 steps' masks at once)
+                asm volatile("" : "+v"(bo), "+v"(ho));
+                const float fm = (ho == hc) ? 1.0f : 0.0f;
+                const float fgt = (bo > c) ? fm : 0.0f;
+                const float feq = (bo == c) ? fm : 0.0f;
+                float piv = bcast(accA[rc], 32 * hc + c);
+                const bool okp = (piv > 0.0f) && (piv < INFINITY);
+                firstbad = (!okp && firstbad < 0) ? c : firstbad;
+                piv = okp ? piv : 1.0f;
+                const float inv = __builtin_amdgcn_rsqf(piv);
+                const float l = accA[rc] * inv;  // L(b, c) in the lanes of half hc
+                Lc[rc] = fmaf(fm, l - Lc[rc], Lc[rc]);
+                const float m = fgt * l;
+                const float g = fmaf(feq, inv - 1.0f, -(fgt * (l * inv)));
+                const float yc = fm * accY[rc];
+                accA = __builtin_amdgcn_mfma_f32_32x32x2f32(-m, m, accA, 0, 0, 0);
+                accY = __builtin_amdgcn_mfma_f32_32x32x2f32(g, yc, accY, 0, 0, 0);
             }
-            if (lane < 32) {
+            if (firstbad >= 0 && lane == 0 && bad == 0) bad = (int)(k0 + j0 + firstbad + 1);
+            // L(b, c) for the c of this half (entries above the diagonal land in the
+            // upper triangle of S's diagonal block, which is never read), and the inverse
 #pragma unroll
-                for (int c = 0; c < 32; ++c)
-                    if (c <= rr) S[(j0 + c) * LDS_LD + j0 + rr] = a[c];
-            }
-            // inverse of L_JJ by substitution, lane jc = column (rows i < jc stay 0)
-            const int jc = lane & 31;
-            float x[32];
-#pragma unroll
-            for (int i = 0; i < 32; ++i) {
-                float v = (i == jc) ? 1.0f : 0.0f;
-#pragma unroll
-                for (int k = 0; k < i; ++k) v = v - S[(j0 + k) * LDS_LD + j0 + i] * x[k];
-                x[i] = v * __builtin_amdgcn_rcpf(S[(j0 + i) * LDS_LD + j0 + i]);
-            }
-            if (lane < 32) {
-#pragma unroll
-                for (int i = 0; i < 32; ++i) V[(j0 + jc) * LDS_LD + j0 + i] = x[i];
+            for (int r = 0; r < 16; ++r) {
+                const int a = 8 * (r >> 2) + 4 * h + (r & 3);
+                S[(j0 + a) * LDS_LD + j0 + b] = Lc[r];
+                V[(j0 + b) * LDS_LD + j0 + a] = accY[r];
             }
         }
         __syncthreads();
-        // 2. blocks below: L_IJ = A_IJ inv(L_JJ)^T, one block per wave
-        {
-            const int I = J + 1 + wave;
-            if (I < 4) {
+        // 2. three independent 32 x 32 products, one per wave:
+        //    blocks below:      L_IJ = A_IJ inv(L_JJ)^T            (I = J+1 .. 3)
+        //    inverse, row J:    Inv_JK = inv(L_JJ) Inv_JK          (K = 0 .. J-1)
+        //    (the block-level form of the same product of elementary inverses)
+        if (wave < 3) {
+            if (wave < 3 - J) {
+                const int I = J + 1 + wave;
                 v16f acc = blk_mma<true>(S + j0 * LDS_LD + 32 * I, LDS_LD, V + j0 * LDS_LD + j0, LDS_LD,
                                          zero16(), lane);
                 blk_store(S + j0 * LDS_LD + 32 * I, LDS_LD, acc, lane, 1.0f, false);
+            } else {
+                const int K = wave - (3 - J);
+                v16f acc = blk_mma<false>(V + j0 * LDS_LD + j0, LDS_LD, V + (32 * K) * LDS_LD + j0, LDS_LD,
+                                          zero16(), lane);
+                blk_store(V + (32 * K) * LDS_LD + j0, LDS_LD, acc, lane, 1.0f, false);
             }
         }
         __syncthreads();
-        // 3. trailing blocks (I, K), J < K <= I: A_IK -= L_IJ L_KJ^T
-        {
-            const int rem = 3 - J;                 // block rows below J
-            const int npair = rem * (rem + 1) / 2;
-            for (int pidx = wave; pidx < npair; pidx += 4) {
-                int Kr = 0;
-                while ((Kr + 1) * (Kr + 2) / 2 <= pidx) ++Kr;  // pidx -> (Ir >= Kr) pairs
-                const int Ir = Kr, Kc = pidx - Kr * (Kr + 1) / 2;
-                const int I = J + 1 + Ir, K = J + 1 + Kc;
-                v16f acc = blk_mma<true>(S + j0 * LDS_LD + 32 * I, LDS_LD, S + j0 * LDS_LD + 32 * K, LDS_LD,
-                                         zero16(), lane);
-                blk_store(S + (32 * K) * LDS_LD + 32 * I, LDS_LD, acc, lane, -1.0f, true);
-            }
+        // 3. the trailing block (J+1, J+1), which the next factor needs first; the
+        //    step's other products run beside that factor
+        if (J < 3) {
+            if (wave == 0) step_products(S, V, J, 0, 1 << 30, lane);
+            __syncthreads();
         }
-        __syncthreads();
     }
 
-    // write L back (lower triangle including the diagonal) and L^T above it
+    // write L back (lower triangle including the diagonal) and L^T above it, and the
+    // inverse (zero above the diagonal)
 #pragma unroll 4
     for (int i = 0; i < 16; ++i) {
         const int e4 = tid + 256 * i;
         const int c = e4 >> 5, r4 = (e4 & 31) * 4;
-        float4 v;
+        float4 v, w;
         v.x = (r4 + 0 >= c) ? S[c * LDS_LD + r4 + 0] : S[(r4 + 0) * LDS_LD + c];
         v.y = (r4 + 1 >= c) ? S[c * LDS_LD + r4 + 1] : S[(r4 + 1) * LDS_LD + c];
         v.z = (r4 + 2 >= c) ? S[c * LDS_LD + r4 + 2] : S[(r4 + 2) * LDS_LD + c];
         v.w = (r4 + 3 >= c) ? S[c * LDS_LD + r4 + 3] : S[(r4 + 3) * LDS_LD + c];
+        w.x = (r4 + 0 >= c) ? V[c * LDS_LD + r4 + 0] : 0.0f;
+        w.y = (r4 + 1 >= c) ? V[c * LDS_LD + r4 + 1] : 0.0f;
+        w.z = (r4 + 2 >= c) ? V[c * LDS_LD + r4 + 2] : 0.0f;
+        w.w = (r4 + 3 >= c) ? V[c * LDS_LD + r4 + 3] : 0.0f;
         *reinterpret_cast<float4 *>(Ablk + (int64_t)c * ld + r4) = v;
-    }
-
-    // off-diagonal blocks of the inverse by distance d = I - J (one block per wave)
-    for (int d = 1; d < 4; ++d) {
-        const int J = wave, I = J + d;
-        if (I < 4) {
-            float *Tw = T + wave * 32 * TLD;
-            v16f acc = zero16();
-            for (int K = J; K < I; ++K)
-                acc = blk_mma<false>(S + (32 * K) * LDS_LD + 32 * I, LDS_LD, V + (32 * J) * LDS_LD + 32 * K,
-                                     LDS_LD, acc, lane);
-            blk_store(Tw, TLD, acc, lane, 1.0f, false);
-            v16f acc2 = blk_mma<false>(V + (32 * I) * LDS_LD + 32 * I, LDS_LD, Tw, TLD, zero16(), lane);
-            blk_store(V + (32 * J) * LDS_LD + 32 * I, LDS_LD, acc2, lane, -1.0f, false);
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < NB * NB; e += 256) {
-        const int r = e & (NB - 1), c = e >> 7;
-        Linv[c * NB + r] = (r >= c) ? V[c * LDS_LD + r] : 0.0f;
+        *reinterpret_cast<float4 *>(Linv + c * NB + r4) = w;
     }
     if (tid == 0 && bad != 0) atomicCAS(&status[kStBreakdown], 0, bad);
 }
