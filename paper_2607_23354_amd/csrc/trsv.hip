@@ -14,9 +14,10 @@
 //     on how many workgroups fit on the device;
 //   * block b streams its off-diagonal tiles in order (forward: L(b, j) from
 //     the lower triangle; backward: L^T(b, j) from the upper triangle, where
-//     the factorisation keeps the transpose); the tile is
-//     loaded into registers before waiting for the solution block it
-//     multiplies, so the HBM stream overlaps the dependency chain;
+//     the factorisation keeps the transpose); tiles are loaded into registers
+//     two steps ahead of the wait for the solution block they multiply, and
+//     the band's own right-hand side and inner tile before the first wait, so
+//     the HBM stream stays off the dependency chain;
 //   * a "ready" count (blocks [0, ready) are final) replaces per-block flags,
 //     since block b can only finish after block b-1 has; a band publishes
 //     both of its blocks at once.  It is published in
@@ -85,7 +86,7 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
 {
     __shared__ float Dl[2][BS * (BS + 1)];  // Dinv of the two blocks, row-major, padded stride
     __shared__ double xs[2][BS];
-    __shared__ double part[2][2][BS];
+    __shared__ double part[8][BS];          // per column group partial sums of a block's rows
     __shared__ int s_band, s_ready;
     const int tid = threadIdx.x;
     const int nband = nblk / 2;
@@ -98,9 +99,41 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     // blocks in solve order: forward (2 band, 2 band + 1), backward (2 band + 1, 2 band)
     const int b0 = BWD ? 2 * band + 1 : 2 * band;
     const int b1 = BWD ? 2 * band : 2 * band + 1;
+    // tile products: thread (rg, cg) owns rows 4 rg .. 4 rg + 3 and columns
+    // 16 cg .. 16 cg + 15 of a 128 x 128 tile (one float4 per column)
+    const int rg = tid & 31, cg = tid >> 5;
+    // block solves: thread (h, row) takes half h of row's dot product
     const int row = tid & (BS - 1);
     const int h = tid >> 7;
     int *ready = counters + (BWD ? kBwdReady : kFwdReady) + (band % kMirrors) * kSlot;
+
+    // tile (b, j): element (r, c) at L[(j BS + c) ld + b BS + r] -- forward L(b, j)
+    // from the lower triangle, backward L^T(b, j) from the upper triangle
+    auto load = [&](int b, int j, float4 (&t)[16]) {
+        const float *p = L + ((int64_t)j * BS + 16 * cg) * ld + (int64_t)b * BS + 4 * rg;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) t[c] = *reinterpret_cast<const float4 *>(p + (int64_t)c * ld);
+    };
+    auto gemv = [&](const float4 (&t)[16], const double *xv, double (&acc)[4]) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const double v = xv[16 * cg + c];
+            acc[0] += (double)t[c].x * v;
+            acc[1] += (double)t[c].y * v;
+            acc[2] += (double)t[c].z * v;
+            acc[3] += (double)t[c].w * v;
+        }
+    };
+
+    // the right-hand side of both blocks and the band's inner tile (b1, b0) do not
+    // depend on other bands: fetch them first, off the dependency chain
+    double rhs0 = 0.0, rhs1 = 0.0;
+    if (tid < BS) {
+        rhs0 = rhs[(int64_t)b0 * BS + tid];
+        rhs1 = rhs[(int64_t)b1 * BS + tid];
+    }
+    float4 ti[16];
+    load(b1, b0, ti);
 
     // Dinv (column-major in memory) into row-major padded LDS
     for (int q = 0; q < 2; ++q) {
@@ -110,48 +143,56 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
             Dl[q][rr * (BS + 1) + cc] = src[e];
         }
     }
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc0[4] = {0.0, 0.0, 0.0, 0.0}, acc1[4] = {0.0, 0.0, 0.0, 0.0};
     int known = 0;
-    // blocks outside the band, in the order they finish; ready counts finished blocks
+    // blocks outside the band, in the order they finish; ready counts finished blocks.
+    // Tiles are fetched one step ahead of the wait (two register sets), so both
+    // tiles of the last two steps -- whose blocks are published together -- are in
+    // flight while the band waits.
     const int nsteps = BWD ? (nblk - 2 - 2 * band) : 2 * band;
-    for (int s = 0; s < nsteps; ++s) {
-        const int j = BWD ? (nblk - 1 - s) : s;
-        float lt0[64], lt1[64];
-        const float *L0 = L + ((int64_t)j * BS + h * 64) * ld + (int64_t)b0 * BS + row;
-        const float *L1 = L + ((int64_t)j * BS + h * 64) * ld + (int64_t)b1 * BS + row;
-#pragma unroll
-        for (int c = 0; c < 64; ++c) {
-            lt0[c] = L0[(int64_t)c * ld];
-            lt1[c] = L1[(int64_t)c * ld];
-        }
-        if (s >= known) {
-            if (tid == 0) s_ready = wait_ready(ready, s + 1, status);
+    float4 ta0[16], ta1[16], tb0[16], tb1[16];
+    auto jof = [&](int st) { return BWD ? (nblk - 1 - st) : st; };
+    auto consume = [&](int st, const float4 (&t0)[16], const float4 (&t1)[16]) {
+        const int j = jof(st);
+        if (st >= known) {
+            if (tid == 0) s_ready = wait_ready(ready, st + 1, status);
             __syncthreads();
             known = s_ready;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        double *xb = xs[s & 1];
+        double *xb = xs[st & 1];
         if (tid < BS) xb[tid] = x[(int64_t)j * BS + tid];
         __syncthreads();
-#pragma unroll
-        for (int c = 0; c < 64; ++c) {
-            const double xv = xb[h * 64 + c];
-            acc0 += (double)lt0[c] * xv;
-            acc1 += (double)lt1[c] * xv;
+        gemv(t0, xb, acc0);
+        gemv(t1, xb, acc1);
+    };
+    if (nsteps > 0) {
+        load(b0, jof(0), ta0);
+        load(b1, jof(0), ta1);
+    }
+    for (int st = 0; st < nsteps; st += 2) {
+        if (st + 1 < nsteps) {
+            load(b0, jof(st + 1), tb0);
+            load(b1, jof(st + 1), tb1);
         }
+        consume(st, ta0, ta1);
+        if (st + 2 < nsteps) {
+            load(b0, jof(st + 2), ta0);
+            load(b1, jof(st + 2), ta1);
+        }
+        if (st + 1 < nsteps) consume(st + 1, tb0, tb1);
     }
-    // the band's inner tile (b1, b0), loaded while the first block is solved
-    float lti[64];
-    {
-        const float *Li = L + ((int64_t)b0 * BS + h * 64) * ld + (int64_t)b1 * BS + row;
-#pragma unroll
-        for (int c = 0; c < 64; ++c) lti[c] = Li[(int64_t)c * ld];
-    }
-    part[0][h][row] = acc0;
-    part[1][h][row] = acc1;
-    __syncthreads();
+
     // first block: x_b0 = Dinv_b0 (rhs_b0 - acc0)   (backward: Dinv^T)
-    if (tid < BS) xs[0][tid] = rhs[(int64_t)b0 * BS + tid] - (part[0][0][tid] + part[0][1][tid]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[cg][4 * rg + i] = acc0[i];
+    __syncthreads();
+    if (tid < BS) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) sacc += part[g][tid];
+        xs[0][tid] = rhs0 - sacc;
+    }
     __syncthreads();
     double v = 0.0;
 #pragma unroll 16
@@ -160,20 +201,25 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
         const float d = BWD ? Dl[0][cc * (BS + 1) + row] : Dl[0][row * (BS + 1) + cc];
         v += (double)d * xs[0][cc];
     }
-    part[0][h][row] = v;
+    part[h][row] = v;
     __syncthreads();
     if (tid < BS) {
-        const double xv = part[0][0][tid] + part[0][1][tid];
+        const double xv = part[0][tid] + part[1][tid];
         xs[1][tid] = xv;
         x[(int64_t)b0 * BS + tid] = xv;
     }
     __syncthreads();
     // second block: acc1 += L(b1, b0) x_b0, then x_b1 = Dinv_b1 (rhs_b1 - acc1)
+    gemv(ti, xs[1], acc1);
 #pragma unroll
-    for (int c = 0; c < 64; ++c) acc1 += (double)lti[c] * xs[1][h * 64 + c];
-    part[1][h][row] = acc1;
+    for (int i = 0; i < 4; ++i) part[cg][4 * rg + i] = acc1[i];
     __syncthreads();
-    if (tid < BS) xs[0][tid] = rhs[(int64_t)b1 * BS + tid] - (part[1][0][tid] + part[1][1][tid]);
+    if (tid < BS) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) sacc += part[g][tid];
+        xs[0][tid] = rhs1 - sacc;
+    }
     __syncthreads();
     v = 0.0;
 #pragma unroll 16
@@ -182,9 +228,9 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
         const float d = BWD ? Dl[1][cc * (BS + 1) + row] : Dl[1][row * (BS + 1) + cc];
         v += (double)d * xs[0][cc];
     }
-    part[1][h][row] = v;
+    part[h][row] = v;
     __syncthreads();
-    if (tid < BS) x[(int64_t)b1 * BS + tid] = part[1][0][tid] + part[1][1][tid];
+    if (tid < BS) x[(int64_t)b1 * BS + tid] = part[0][tid] + part[1][tid];
     __threadfence();
     __syncthreads();
     publish(counters + (BWD ? kBwdReady : kFwdReady), nsteps + 2);
