@@ -145,42 +145,50 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     }
     double acc0[4] = {0.0, 0.0, 0.0, 0.0}, acc1[4] = {0.0, 0.0, 0.0, 0.0};
     int known = 0;
-    // blocks outside the band, in the order they finish; ready counts finished blocks.
-    // Tiles are fetched one step ahead of the wait (two register sets), so both
-    // tiles of the last two steps -- whose blocks are published together -- are in
-    // flight while the band waits.
+    // blocks outside the band, in the order they finish, two at a time; ready
+    // counts finished blocks.  A pair's tiles are fetched before its wait, the
+    // next pair's right after it.
     const int nsteps = BWD ? (nblk - 2 - 2 * band) : 2 * band;
     float4 ta0[16], ta1[16], tb0[16], tb1[16];
     auto jof = [&](int st) { return BWD ? (nblk - 1 - st) : st; };
-    auto consume = [&](int st, const float4 (&t0)[16], const float4 (&t1)[16]) {
-        const int j = jof(st);
-        if (st >= known) {
-            if (tid == 0) s_ready = wait_ready(ready, st + 1, status);
+    // steps st and st + 1 (if any): one wait, one read of both solution blocks
+    // (bands publish two blocks at a time, so both are ready together)
+    auto consume2 = [&](int st, bool two) {
+        const int need = st + (two ? 2 : 1);
+        if (need > known) {
+            if (tid == 0) s_ready = wait_ready(ready, need, status);
             __syncthreads();
             known = s_ready;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        double *xb = xs[st & 1];
-        if (tid < BS) xb[tid] = x[(int64_t)j * BS + tid];
+        {
+            const int q = tid >> 7;  // threads 0..127: block of step st, 128..255: st + 1
+            if (q == 0 || two) xs[q][row] = x[(int64_t)jof(st + q) * BS + row];
+        }
         __syncthreads();
-        gemv(t0, xb, acc0);
-        gemv(t1, xb, acc1);
+        gemv(ta0, xs[0], acc0);
+        gemv(ta1, xs[0], acc1);
+        if (two) {
+            gemv(tb0, xs[1], acc0);
+            gemv(tb1, xs[1], acc1);
+        }
+        __syncthreads();  // xs is rewritten by the next step
     };
     if (nsteps > 0) {
         load(b0, jof(0), ta0);
         load(b1, jof(0), ta1);
     }
     for (int st = 0; st < nsteps; st += 2) {
-        if (st + 1 < nsteps) {
+        const bool two = st + 1 < nsteps;
+        if (two) {
             load(b0, jof(st + 1), tb0);
             load(b1, jof(st + 1), tb1);
         }
-        consume(st, ta0, ta1);
+        consume2(st, two);
         if (st + 2 < nsteps) {
             load(b0, jof(st + 2), ta0);
             load(b1, jof(st + 2), ta1);
         }
-        if (st + 1 < nsteps) consume(st + 1, tb0, tb1);
     }
 
     // first block: x_b0 = Dinv_b0 (rhs_b0 - acc0)   (backward: Dinv^T)
