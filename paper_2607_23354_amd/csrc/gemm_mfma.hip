@@ -17,14 +17,17 @@
 // accumulator lane maps to a row i of C: each accumulator register is a
 // 128-byte contiguous column segment for a half-wave, which makes both the
 // initial load of C and the final store coalesced.
-// K is staged through LDS in chunks of 16, double-buffered, one barrier per
-// stage; the accumulators start at zero and C is added in the epilogue.
+// K is staged through LDS in chunks of 16 by direct global-to-LDS loads,
+// double-buffered, one barrier per stage; the accumulators start at zero and
+// C is updated in the epilogue.
 #include "internal.hpp"
 
 namespace mag {
 namespace {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef const __attribute__((address_space(1))) void *gptr;  // global operand of a direct LDS load
+typedef __attribute__((address_space(3))) void *lptr;        // its LDS destination
 
 constexpr int BT = 128;
 constexpr int KC = 16;
@@ -61,9 +64,8 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
     const int l32 = lane & 31;
     const int hi = lane >> 5;
 
-    // accumulate from zero (for kGemmSub with Q negated, so acc = -P Q^T);
-    // C is read only in the epilogue, which keeps the stage loop free of
-    // waits on loads other than the operand prefetch
+    // accumulate P Q^T from zero; C is read only in the epilogue, which keeps the
+    // stage loop free of waits on loads other than the operand prefetch
     v16f acc[2][2];
 #pragma unroll
     for (int jb = 0; jb < 2; ++jb)
@@ -72,36 +74,34 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[jb][ib][r] = 0.0f;
 
-    // global -> register staging: thread loads float4 at (row 4*(tid%32), p = tid/32 (+8))
+    // global -> LDS staging by direct loads (global_load_lds_dwordx4): thread t
+    // fetches the float4 at row 4 (t % 32), k = t / 32 (and k + 8), and a wave's
+    // 64 lanes land as one contiguous 1 KB block, rows 2 w and 2 w + 1 of a stage
     const int lr = 4 * (threadIdx.x & 31);
     const int lp = threadIdx.x >> 5;
     const float *pg0 = P + lp * ldp + i0 + lr, *pg1 = P + (lp + 8) * ldp + i0 + lr;
     const float *qg0 = Q + lp * ldq + j0 + lr, *qg1 = Q + (lp + 8) * ldq + j0 + lr;
     const int64_t stepP = KC * ldp, stepQ = KC * ldq;
-    const float qs = (MODE == kGemmSub) ? -1.0f : 1.0f;
-    float4 pa0 = *reinterpret_cast<const float4 *>(pg0);
-    float4 pa1 = *reinterpret_cast<const float4 *>(pg1);
-    float4 qa0 = *reinterpret_cast<const float4 *>(qg0);
-    float4 qa1 = *reinterpret_cast<const float4 *>(qg1);
-    *reinterpret_cast<float4 *>(&Ps[0][lp][lr]) = pa0;
-    *reinterpret_cast<float4 *>(&Ps[0][lp + 8][lr]) = pa1;
-    *reinterpret_cast<float4 *>(&Qs[0][lp][lr]) = make_float4(qs * qa0.x, qs * qa0.y, qs * qa0.z, qs * qa0.w);
-    *reinterpret_cast<float4 *>(&Qs[0][lp + 8][lr]) = make_float4(qs * qa1.x, qs * qa1.y, qs * qa1.z, qs * qa1.w);
+    const int w2 = 2 * __builtin_amdgcn_readfirstlane(wave);
+    auto stage_in = [&](int b) {
+        __builtin_amdgcn_global_load_lds((gptr)pg0, (lptr)&Ps[b][w2][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gptr)pg1, (lptr)&Ps[b][w2 + 8][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gptr)qg0, (lptr)&Qs[b][w2][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gptr)qg1, (lptr)&Qs[b][w2 + 8][0], 16, 0, 0);
+    };
+    stage_in(0);
     __syncthreads();
 
     const int nst = (int)(K / KC);
     for (int st = 0; st < nst; ++st) {
         const int buf = st & 1;
-        const bool more = st + 1 < nst;
-        if (more) {
+        if (st + 1 < nst) {
+            // the other buffer was last read before the previous barrier
             pg0 += stepP;
             pg1 += stepP;
             qg0 += stepQ;
             qg1 += stepQ;
-            pa0 = *reinterpret_cast<const float4 *>(pg0);
-            pa1 = *reinterpret_cast<const float4 *>(pg1);
-            qa0 = *reinterpret_cast<const float4 *>(qg0);
-            qa1 = *reinterpret_cast<const float4 *>(qg1);
+            stage_in(buf ^ 1);
         }
 #pragma unroll
         for (int kp = 0; kp < KC / 2; ++kp) {
@@ -115,15 +115,7 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
             acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q1, p0, acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q1, p1, acc[1][1], 0, 0, 0);
         }
-        if (more) {
-            *reinterpret_cast<float4 *>(&Ps[buf ^ 1][lp][lr]) = pa0;
-            *reinterpret_cast<float4 *>(&Ps[buf ^ 1][lp + 8][lr]) = pa1;
-            *reinterpret_cast<float4 *>(&Qs[buf ^ 1][lp][lr]) =
-                make_float4(qs * qa0.x, qs * qa0.y, qs * qa0.z, qs * qa0.w);
-            *reinterpret_cast<float4 *>(&Qs[buf ^ 1][lp + 8][lr]) =
-                make_float4(qs * qa1.x, qs * qa1.y, qs * qa1.z, qs * qa1.w);
-        }
-        __syncthreads();
+        __syncthreads();  // waits for the direct loads of the next stage too
     }
 
 #pragma unroll
@@ -141,7 +133,7 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-                    C[j * ldc + i] = cv[r] + acc[jb][ib][r];
+                    C[j * ldc + i] = cv[r] - acc[jb][ib][r];
                 }
             } else {
 #pragma unroll
