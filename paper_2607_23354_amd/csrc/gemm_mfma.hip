@@ -118,31 +118,49 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
         __syncthreads();  // waits for the direct loads of the next stage too
     }
 
+    if (MODE == kGemmSub) {
+        // C -= acc through LDS (free after the last stage's barrier): 16 columns of the
+        // wave's 64 x 64 quadrant at a time, written in the accumulator layout and read
+        // back as 4 consecutive rows per lane, so C moves in float4 accesses.  Column
+        // stride 72 keeps both halves of the wave on distinct banks.
+        float *Tw = lds + wave * (16 * 72);
 #pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
+        for (int q = 0; q < 4; ++q) {
+            const int jb = q >> 1, rq = q & 1;
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib) {
-            const int64_t i = i0 + wi + ib * 32 + l32;
-            if (MODE == kGemmSub) {
-                float cv[16];
+            for (int rr = 0; rr < 8; ++rr) {
+                const int r = 8 * rq + rr;
+                const int c16 = 8 * (rr >> 2) + 4 * hi + (r & 3);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-                    cv[r] = C[j * ldc + i];
-                }
+                for (int ib = 0; ib < 2; ++ib) Tw[c16 * 72 + 32 * ib + l32] = acc[jb][ib][r];
+            }
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-                    C[j * ldc + i] = cv[r] - acc[jb][ib][r];
-                }
-            } else {
+            for (int rd = 0; rd < 4; ++rd) {
+                const int c16 = 4 * rd + (lane >> 4);
+                const float4 a = *reinterpret_cast<const float4 *>(&Tw[c16 * 72 + 4 * (lane & 15)]);
+                float4 *cp = reinterpret_cast<float4 *>(C + (j0 + wj + 32 * jb + 16 * rq + c16) * ldc + i0 + wi +
+                                                        4 * (lane & 15));
+                float4 c = *cp;
+                c.x -= a.x;
+                c.y -= a.y;
+                c.z -= a.z;
+                c.w -= a.w;
+                *cp = c;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) {
+                const int64_t i = i0 + wi + ib * 32 + l32;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
                     C[j * ldc + i] = acc[jb][ib][r];
                 }
             }
-        }
+    }
     if (MODE == kGemmSetT) {
         // transposed copy, 64 columns of the tile at a time through LDS (T[jl][i])
         float *T = lds;
