@@ -44,7 +44,10 @@ __device__ inline void tri_index(int64_t idx, int64_t &ti, int64_t &tj)
 }
 
 constexpr int TLD = BT + 1;
-constexpr int LDS_FLOATS = (2 * 2 * KC * BT > BT * (64 + 1)) ? 2 * 2 * KC * BT : BT * (64 + 1);
+// operand stages (2 buffers x P, Q); the SetT epilogue's transposed half tile needs a
+// little more.  32 KB for the other modes lets five workgroups share a CU's LDS.
+constexpr int LDS_STAGES = 2 * 2 * KC * BT;
+constexpr int LDS_SETT = (LDS_STAGES > BT * (64 + 1)) ? LDS_STAGES : BT * (64 + 1);
 
 template <int MODE>
 __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ldc,
@@ -53,7 +56,7 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
                                                int64_t ti, int64_t tj, int64_t K,
                                                float *__restrict__ CT)
 {
-    __shared__ float lds[LDS_FLOATS];
+    __shared__ float lds[MODE == kGemmSetT ? LDS_SETT : LDS_STAGES];
     float (*Ps)[KC][BT] = reinterpret_cast<float (*)[KC][BT]>(lds);
     float (*Qs)[KC][BT] = reinterpret_cast<float (*)[KC][BT]>(lds + 2 * KC * BT);
     const int64_t i0 = ti * BT, j0 = tj * BT;
