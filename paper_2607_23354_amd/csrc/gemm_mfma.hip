@@ -49,7 +49,7 @@ constexpr int TLD = BT + 1;
 constexpr int LDS_STAGES = 2 * 2 * KC * BT;
 constexpr int LDS_SETT = (LDS_STAGES > BT * (64 + 1)) ? LDS_STAGES : BT * (64 + 1);
 
-template <int MODE>
+template <int MODE, bool LDS_EPI = false>
 __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ldc,
                                                const float *__restrict__ P, int64_t ldp,
                                                const float *__restrict__ Q, int64_t ldq,
@@ -121,11 +121,12 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
         __syncthreads();  // waits for the direct loads of the next stage too
     }
 
-    if (MODE == kGemmSub) {
+    if (MODE == kGemmSub && LDS_EPI) {
         // C -= acc through LDS (free after the last stage's barrier): 16 columns of the
         // wave's 64 x 64 quadrant at a time, written in the accumulator layout and read
         // back as 4 consecutive rows per lane, so C moves in float4 accesses.  Column
-        // stride 72 keeps both halves of the wave on distinct banks.
+        // stride 72 keeps both halves of the wave on distinct banks.  (Short-K updates,
+        // bound by their latency, take the direct epilogue below.)
         float *Tw = lds + wave * (16 * 72);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -157,10 +158,24 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
 #pragma unroll
             for (int ib = 0; ib < 2; ++ib) {
                 const int64_t i = i0 + wi + ib * 32 + l32;
+                if (MODE == kGemmSub) {
+                    float cv[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
-                    C[j * ldc + i] = acc[jb][ib][r];
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                        cv[r] = C[j * ldc + i];
+                    }
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                        C[j * ldc + i] = cv[r] - acc[jb][ib][r];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                        C[j * ldc + i] = acc[jb][ib][r];
+                    }
                 }
             }
     }
@@ -219,7 +234,7 @@ k_syrk_lower(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, in
     const int64_t ti = si * 8 + within / 8;
     const int64_t tj = sj * 8 + within % 8;
     if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
-    gemm_tile_body<kGemmSub>(C, ldc, P, ldp, P, ldp, ti, tj, K, nullptr);
+    gemm_tile_body<kGemmSub, true>(C, ldc, P, ldp, P, ldp, ti, tj, K, nullptr);
 }
 
 // Batched factorisation updates at panel offset kk of every active problem.
@@ -248,8 +263,8 @@ k_gemm_b(const BProb *__restrict__ Pr, BWork w, int64_t kk)
         int64_t ti, tj;
         tri_index(u, ti, tj);
         const float *Pp = A + kk * np + kk + 2 * BT;
-        gemm_tile_body<kGemmSub>(A + (kk + 2 * BT) * np + kk + 2 * BT, np, Pp, np, Pp, np, ti, tj,
-                                 2 * BT, nullptr);
+        gemm_tile_body<kGemmSub, true>(A + (kk + 2 * BT) * np + kk + 2 * BT, np, Pp, np, Pp, np, ti, tj,
+                                       2 * BT, nullptr);
     }
 }
 
