@@ -63,7 +63,7 @@ using namespace mag;
 namespace mag {
 // Validate the coordinates: finite, and no duplicate points (Z would be
 // singular).  One host sync.
-int check_points(mag_ctx *ctx, const double *X, int64_t n, int m)
+int check_points(mag_ctx *ctx, const double *X, int64_t n, int m, bool pairs)
 {
     int *status = (int *)ctx->ints.p;
     CHK0(ensure(ctx, ctx->partial, sizeof(double) * std::max<size_t>(dmin_partial_doubles(n) + 8, 64)));
@@ -71,14 +71,15 @@ int check_points(mag_ctx *ctx, const double *X, int64_t n, int m)
     launch_fill_ints(ctx->stream, status, 8, 0);
     launch_check_finite(ctx->stream, X, n * (int64_t)m, status);
     double *dmin2 = partial + dmin_partial_doubles(n);
-    if (n >= 2) launch_dmin2(ctx->stream, X, n, m, partial, nullptr, dmin2);
+    pairs = pairs && n >= 2;
+    if (pairs) launch_dmin2(ctx->stream, X, n, m, partial, nullptr, dmin2);
     HIPCHK0(hipMemcpyAsync(ctx->host_scalars, status, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    if (n >= 2)
+    if (pairs)
         HIPCHK0(hipMemcpyAsync(ctx->host_scalars + 8, dmin2, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK0(hipStreamSynchronize(ctx->stream));
     const int *hs = (const int *)ctx->host_scalars;
     if (hs[kStNonFinite]) return MAG_EINVAL;
-    if (n >= 2 && !(ctx->host_scalars[8] > 0.0)) return MAG_ENOTPD;
+    if (pairs && !(ctx->host_scalars[8] > 0.0)) return MAG_ENOTPD;
     return MAG_OK;
 }
 
@@ -208,7 +209,8 @@ int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Facto
     F.shifted = 0;
     for (int attempt = 0;; ++attempt) {
         launch_fill_ints(s, status, 8, 0);
-        launch_tilegen32(s, X, n, m, t, F.A, F.npad, (float)F.shift);
+        // the tile generator also flags coincident points (Z singular)
+        launch_tilegen32(s, X, n, m, t, F.A, F.npad, (float)F.shift, status);
         if (tm && attempt == 0) tm->mark(1);
         if (ft) {
             ft->used = 0;
@@ -217,6 +219,7 @@ int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Facto
         chol32_factor(s, F.A, F.npad, n, F.dinv, status, ft, panel_width(ctx, F.npad));
         HIPCHK(hipMemcpyAsync(hs, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        if (((const int *)hs)[kStDuplicate]) return MAG_ENOTPD;
         if (((const int *)hs)[kStBreakdown] == 0) break;
         if (attempt >= 6) return MAG_ENOTPD;
         F.shift = (F.shift == 0.0) ? 1e-6 * std::max<double>(1.0, std::sqrt((double)n)) : F.shift * 10.0;
@@ -913,7 +916,9 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
     if (opts) o = *opts;
     else mag_opts_default(&o);
     CHK(ensure_common(c, n, std::max(1, o.gmres_restart)));
-    int rc = check_points(c, X, n, m);
+    // the FP32 path's tile generator checks the pairs itself (no separate O(n^2) pass)
+    const bool fp32 = o.solver == MAG_FP32_IR || (o.solver == MAG_AUTO && auto_dense(c, n));
+    int rc = check_points(c, X, n, m, !fp32);
     if (rc == MAG_OK && n == 1) {
         launch_fill(c->stream, w, 1, 1.0);
         HIPCHK(hipStreamSynchronize(c->stream));
@@ -925,8 +930,8 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
         switch (o.solver) {
         case MAG_FP64_DENSE: rc = solve_fp64_dense(c, X, n, m, t, w, o, info); break;
         case MAG_HODLR: rc = solve_hodlr(c, X, n, m, t, w, o, info); break;
-        case MAG_AUTO: rc = auto_dense(c, n) ? solve_fp32_ir(c, X, n, m, t, w, o, info)
-                                             : solve_hodlr(c, X, n, m, t, w, o, info);
+        case MAG_AUTO: rc = fp32 ? solve_fp32_ir(c, X, n, m, t, w, o, info)
+                                 : solve_hodlr(c, X, n, m, t, w, o, info);
             break;
         case MAG_FP32_IR: rc = solve_fp32_ir(c, X, n, m, t, w, o, info); break;
         default: rc = MAG_EINVAL; break;

@@ -39,6 +39,7 @@ enum StatusWord : int {
     kStBreakdown = 0,    // FP32 Cholesky met a non-positive pivot (index+1)
     kStSpinTimeout = 1,  // a bounded spin-wait gave up (should never happen)
     kStNonFinite = 2,    // non-finite coordinate seen
+    kStDuplicate = 3,    // two points at distance 0 seen by the FP32 tile generator
     kStCount = 8
 };
 
@@ -147,7 +148,8 @@ namespace mag {
 // Grow `b` to at least `bytes` (frees the old block; contents are lost).
 int ensure(mag_ctx *ctx, DevBuf &b, size_t bytes);
 // Coordinates finite and pairwise distinct (else MAG_EINVAL / MAG_ENOTPD); one host sync.
-int check_points(mag_ctx *ctx, const double *X, int64_t n, int m);
+// pairs = false checks finiteness only (the caller's FP32 tile generator checks the pairs).
+int check_points(mag_ctx *ctx, const double *X, int64_t n, int m, bool pairs = true);
 
 // Event pairs around the trailing-update launches of a factorisation, with
 // the algorithmic flops of each launch.
@@ -177,8 +179,9 @@ void launch_gradx(hipStream_t s, const double *X, int64_t n, int m, double t, co
 
 // ---- launchers (all enqueue on ctx->stream) --------------------------------
 // tilegen.hip
+// status (optional): status[kStDuplicate] = 1 if some pair j != k < n has d_jk = 0
 void launch_tilegen32(hipStream_t s, const double *X, int64_t n, int m, double t,
-                      float *A, int64_t npad, float shift);
+                      float *A, int64_t npad, float shift, int *status = nullptr);
 void launch_tilegen64(hipStream_t s, const double *X, int64_t n, int m, double t, double *A);
 // Writes min squared distance partials; returns number of partials in *np.
 void launch_dmin2(hipStream_t s, const double *X, int64_t n, int m, double *partial,

@@ -79,7 +79,7 @@ __device__ inline void block_sqdist(double (&s)[kPerThread], const double *X, in
 
 __device__ __forceinline__ void tilegen32_body(const double *__restrict__ X, int64_t n, int m,
                                                double t, float *__restrict__ A, int64_t npad,
-                                               float shift, int64_t blk)
+                                               float shift, int64_t blk, int *__restrict__ status)
 {
     __shared__ double Sr[kLC * kRows];
     __shared__ double Sc[kLC * kCols];
@@ -100,17 +100,19 @@ __device__ __forceinline__ void tilegen32_body(const double *__restrict__ X, int
             v = 1.0f + shift;
         else if (j >= n || k >= n)
             v = 0.0f;
-        else
+        else {
+            if (status && s[c] == 0.0) status[kStDuplicate] = 1;  // Z singular
             v = expf(-(tf * sqrtf((float)s[c])));
+        }
         A[k * npad + j] = v;
     }
 }
 
 __global__ void __launch_bounds__(kThreads)
 k_tilegen32(const double *__restrict__ X, int64_t n, int m, double t, float *__restrict__ A,
-            int64_t npad, float shift)
+            int64_t npad, float shift, int *__restrict__ status)
 {
-    tilegen32_body(X, n, m, t, A, npad, shift, blockIdx.x);
+    tilegen32_body(X, n, m, t, A, npad, shift, blockIdx.x, status);
 }
 
 // Batched: one launch for every active problem of a batch.
@@ -120,7 +122,7 @@ k_tilegen32_b(const BProb *__restrict__ P, BWork w)
     const int i = bfind(w.pref, w.na, blockIdx.x);
     const BProb &q = P[w.plist[i]];
     if (!q.active) return;
-    tilegen32_body(q.X, q.n, q.m, q.t, q.A, q.npad, (float)q.shift, blockIdx.x - w.pref[i]);
+    tilegen32_body(q.X, q.n, q.m, q.t, q.A, q.npad, (float)q.shift, blockIdx.x - w.pref[i], nullptr);
 }
 
 __global__ void __launch_bounds__(kThreads)
@@ -212,10 +214,10 @@ int64_t lower_blocks(int64_t rows)
 }  // namespace
 
 void launch_tilegen32(hipStream_t s, const double *X, int64_t n, int m, double t, float *A,
-                      int64_t npad, float shift)
+                      int64_t npad, float shift, int *status)
 {
     hipLaunchKernelGGL(k_tilegen32, dim3((unsigned)lower_blocks(npad)), dim3(kThreads), 0, s, X, n,
-                       m, t, A, npad, shift);
+                       m, t, A, npad, shift, status);
 }
 
 void launch_tilegen64(hipStream_t s, const double *X, int64_t n, int m, double t, double *A)

@@ -106,6 +106,18 @@ def test_duplicates_rejected(mag):
     assert e.value.code == -2
 
 
+@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_dense", "auto"])
+@pytest.mark.parametrize("pair", [(3, 4), (5, 1000), (1299, 0)])
+def test_duplicates_rejected_every_solver(mag, solver, pair):
+    # the FP32 path finds coincident points inside its tile generator: same tile,
+    # tiles far apart, and the last row against the first
+    X = W.gaussian(1300, 2, seed=4)
+    X[pair[0]] = X[pair[1]]
+    with pytest.raises(mag.MagError) as e:
+        mag.weighting(dev(X), 2.0, solver=solver)
+    assert e.value.code == -2
+
+
 @pytest.mark.parametrize("t", [0.0, -1.0, float("nan"), float("inf")])
 def test_bad_scale_rejected(mag, t):
     with pytest.raises(mag.MagError) as e:
