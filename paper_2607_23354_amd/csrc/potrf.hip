@@ -169,27 +169,46 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
             }
             int firstbad = -1;  // branch-free pivot check keeps the sweep one basic block
             int bo = b, ho = h;
+            // Columns in pairs (c, c + 1), both held by the same half (c even): column
+            // c + 1 is brought up to date against column c on the VALU, so one wait on
+            // the accumulator serves two pivots; then the four rank-1 MFMA updates.
 #pragma unroll
-            for (int c = 0; c < 32; ++c) {
-                const int rc = 4 * (c >> 3) + (c & 3), hc = (c >> 2) & 1;
+            for (int c = 0; c < 32; c += 2) {
+                const int r0 = 4 * (c >> 3) + (c & 3), r1 = r0 + 1, hc = (c >> 2) & 1;
                 // lane predicates as 0/1 factors, recomputed per step (opaque lane ids
-                // keep the compiler from precomputing all 32 steps' masks at once)
+                // keep the compiler from precomputing every step's masks at once)
                 asm volatile("" : "+v"(bo), "+v"(ho));
                 const float fm = (ho == hc) ? 1.0f : 0.0f;
-                const float fgt = (bo > c) ? fm : 0.0f;
-                const float feq = (bo == c) ? fm : 0.0f;
-                float piv = bcast(accA[rc], 32 * hc + c);
-                const bool okp = (piv > 0.0f) && (piv < INFINITY);
-                firstbad = (!okp && firstbad < 0) ? c : firstbad;
-                piv = okp ? piv : 1.0f;
-                const float inv = __builtin_amdgcn_rsqf(piv);
-                const float l = accA[rc] * inv;  // L(b, c) in the lanes of half hc
-                Lc[rc] = fmaf(fm, l - Lc[rc], Lc[rc]);
-                const float m = fgt * l;
-                const float g = fmaf(feq, inv - 1.0f, -(fgt * (l * inv)));
-                const float yc = fm * accY[rc];
-                accA = __builtin_amdgcn_mfma_f32_32x32x2f32(-m, m, accA, 0, 0, 0);
-                accY = __builtin_amdgcn_mfma_f32_32x32x2f32(g, yc, accY, 0, 0, 0);
+                const float fgt0 = (bo > c) ? fm : 0.0f, feq0 = (bo == c) ? fm : 0.0f;
+                const float fgt1 = (bo > c + 1) ? fm : 0.0f, feq1 = (bo == c + 1) ? fm : 0.0f;
+                // column c
+                float piv0 = bcast(accA[r0], 32 * hc + c);
+                const bool ok0 = (piv0 > 0.0f) && (piv0 < INFINITY);
+                firstbad = (!ok0 && firstbad < 0) ? c : firstbad;
+                piv0 = ok0 ? piv0 : 1.0f;
+                const float inv0 = __builtin_amdgcn_rsqf(piv0);
+                const float l0 = accA[r0] * inv0;       // L(b, c) in the lanes of half hc
+                const float s = bcast(l0, 32 * hc + c + 1);  // L(c + 1, c)
+                // column c + 1 after step c
+                const float x1 = fmaf(-l0, s, accA[r1]);
+                float piv1 = bcast(x1, 32 * hc + c + 1);
+                const bool ok1 = (piv1 > 0.0f) && (piv1 < INFINITY);
+                firstbad = (!ok1 && firstbad < 0) ? c + 1 : firstbad;
+                piv1 = ok1 ? piv1 : 1.0f;
+                const float inv1 = __builtin_amdgcn_rsqf(piv1);
+                const float l1 = x1 * inv1;             // L(b, c + 1)
+                Lc[r0] = fmaf(fm, l0 - Lc[r0], Lc[r0]);
+                Lc[r1] = fmaf(fm, l1 - Lc[r1], Lc[r1]);
+                const float m0 = fgt0 * l0, m1 = fgt1 * l1;
+                // inverse: row c as it stands, row c + 1 after step c
+                const float y0 = fm * accY[r0];
+                const float y1 = fm * fmaf(-(s * inv0), accY[r0], accY[r1]);
+                const float g0 = fmaf(feq0, inv0 - 1.0f, -(fgt0 * (l0 * inv0)));
+                const float g1 = fmaf(feq1, inv1 - 1.0f, -(fgt1 * (l1 * inv1)));
+                accA = __builtin_amdgcn_mfma_f32_32x32x2f32(-m0, m0, accA, 0, 0, 0);
+                accA = __builtin_amdgcn_mfma_f32_32x32x2f32(-m1, m1, accA, 0, 0, 0);
+                accY = __builtin_amdgcn_mfma_f32_32x32x2f32(g0, y0, accY, 0, 0, 0);
+                accY = __builtin_amdgcn_mfma_f32_32x32x2f32(g1, y1, accY, 0, 0, 0);
             }
             if (firstbad >= 0 && lane == 0 && bad == 0) bad = (int)(k0 + j0 + firstbad + 1);
             // L(b, c) for the c of this half (entries above the diagonal land in the
