@@ -82,7 +82,15 @@ typedef struct {
     int32_t oversample;    /* HODLR extra sample columns, default 16                      */
     int32_t profile;       /* 1: time phases with HIP events (adds a sync per phase)      */
     uint64_t seed;         /* HODLR sampling seed                                          */
+    int32_t inner_prec;    /* MAG_INNER_FP64 (default): every product with Z in FP64;      *
+                            * MAG_INNER_FP32: the products inside GMRES evaluate each      *
+                            * entry exp(-t d) in FP32 (sums in FP64; m <= 16, else FP64)   *
+                            * and ask at most a 1e-6 reduction of each inner solve; the    *
+                            * residuals 1 - Z w that decide convergence stay FP64          */
 } mag_opts;
+
+#define MAG_INNER_FP64 0
+#define MAG_INNER_FP32 1
 
 /* Fill *opts with the defaults above. */
 void mag_opts_default(mag_opts *opts);

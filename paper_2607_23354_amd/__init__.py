@@ -95,7 +95,7 @@ def make_opts(solver: str = "auto", tol: float = 1e-12, max_outer: int | None = 
               gmres_restart: int | None = None, max_gmres: int | None = None,
               inner_tol: float | None = None, profile: bool = False, leaf: int | None = None,
               max_rank: int | None = None, oversample: int | None = None,
-              seed: int | None = None) -> MagOpts:
+              seed: int | None = None, inner_prec: str = "fp64") -> MagOpts:
     o = MagOpts()
     _lib.load().mag_opts_default(ctypes.byref(o))
     o.solver = SOLVERS[solver]
@@ -117,6 +117,9 @@ def make_opts(solver: str = "auto", tol: float = 1e-12, max_outer: int | None = 
     if seed is not None:
         o.seed = seed
     o.profile = 1 if profile else 0
+    if inner_prec not in ("fp64", "fp32"):
+        raise ValueError(f"inner_prec must be 'fp64' or 'fp32', not {inner_prec!r}")
+    o.inner_prec = 0 if inner_prec == "fp64" else 1
     return o
 
 

@@ -39,6 +39,7 @@ class MagOpts(ctypes.Structure):
         ("oversample", ctypes.c_int32),
         ("profile", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("inner_prec", ctypes.c_int32),
     ]
 
 

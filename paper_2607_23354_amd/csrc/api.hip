@@ -255,7 +255,10 @@ int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64
     int *status = ints + kIntStatus;
     double *hs = ctx->host_scalars;
     const double tol = (o.tol > 0 ? o.tol : 1e-12) * std::max(1.0, bnorm);
-    const double inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-10;
+    // FP32 entries in the inner products: the correction equation is then solved
+    // for an operator within ~1e-7 of Z, so asking GMRES for more than 1e-6 is wasted
+    const bool f32_inner = o.inner_prec == MAG_INNER_FP32 && m <= 16;
+    const double inner_tol = std::max(o.inner_tol > 0 ? o.inner_tol : 1e-10, f32_inner ? 1e-6 : 0.0);
     const int max_gmres = o.max_gmres > 0 ? o.max_gmres : 200;
 
     const double *bb = b;
@@ -338,7 +341,7 @@ int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64
         for (int k = 0; k < restart && inner_total < max_gmres; ++k) {
             double *Vk = v.V + (size_t)k * npad;
             double *Vk1 = v.V + (size_t)(k + 1) * npad;
-            launch_zmv(s, X, n, m, t, Vk, v.u, nullptr, 0, partial, nullptr);
+            launch_zmv(s, X, n, m, t, Vk, v.u, nullptr, 0, partial, nullptr, f32_inner);
             prec(v.u, Vk1, v.ytmp);
             // classical Gram-Schmidt, twice
             launch_multidot(s, v.V, npad, k + 1, Vk1, npad, partial, v.hdev);
@@ -726,6 +729,7 @@ void mag_opts_default(mag_opts *o)
     o->oversample = 16;
     o->profile = 0;
     o->seed = 0x9E3779B97F4A7C15ull;
+    o->inner_prec = MAG_INNER_FP64;
 }
 
 int mag_create(mag_ctx **out, int device)

@@ -110,7 +110,7 @@ __device__ inline void tri_tile(int64_t idx, int64_t &I, int64_t &J)
 // sum_c Z(r0 + p, c) v_c over the tile's columns; part[tile * 2 TS + TS + p]:
 // column sums sum_r Z(r, c0 + p) v_r (off-diagonal tiles only; a diagonal
 // tile is summed over its full square as rows).  M > 0: compile-time m.
-template <int M>
+template <int M, bool F32 = false>
 __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64_t n, int m_rt, double t,
                                              const double *__restrict__ v, double *__restrict__ part,
                                              int64_t tile)
@@ -172,6 +172,7 @@ __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64
             double z;
             if (r >= nr || c >= nc) z = 0.0;
             else if (diag && r == c) z = 1.0;
+            else if (F32) z = (double)expf(-((float)t * sqrtf((float)s)));  // entry in FP32, sums in FP64
             else z = exp(-(t * sqrt(s)));
             rowacc[ii] = fma(z, vcj, rowacc[ii]);
             colacc = fma(z, vr[r], colacc);
@@ -214,12 +215,12 @@ __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64
 // Block I of y (rows r0 .. r0 + TS): sum of the row sums of tiles (I, 0..I)
 // and the column sums of tiles (I+1..T-1, I), in that order.  mode 0: y = Z v;
 // mode 1: y = b - Z v (b == NULL: ones) and blkmax[I] = max |y| over the block.
-template <int M>
+template <int M, bool F32 = false>
 __global__ void __launch_bounds__(256)
 k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const double *__restrict__ v,
           double *__restrict__ part)
 {
-    zmv_sym_body<M>(X, n, m_rt, t, v, part, blockIdx.x);
+    zmv_sym_body<M, F32>(X, n, m_rt, t, v, part, blockIdx.x);
 }
 
 __device__ __forceinline__ void zmv_sym_reduce_body(const double *__restrict__ part, int64_t T, int64_t n,
@@ -499,8 +500,22 @@ static void launch_zmv_split(hipStream_t s, const double *X, int64_t n, int m, d
         hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, blkmax, rb, out_norm);
 }
 
+template <bool F32>
+void launch_zmv_sym_tiles(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
+                          double *partial, const dim3 grid)
+{
+    switch (m) {
+    case 1: hipLaunchKernelGGL((k_zmv_sym<1, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 2: hipLaunchKernelGGL((k_zmv_sym<2, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 3: hipLaunchKernelGGL((k_zmv_sym<3, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 4: hipLaunchKernelGGL((k_zmv_sym<4, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 8: hipLaunchKernelGGL((k_zmv_sym<8, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    default: hipLaunchKernelGGL((k_zmv_sym<0, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    }
+}
+
 void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
-                double *y, const double *b, int mode, double *partial, double *out_norm)
+                double *y, const double *b, int mode, double *partial, double *out_norm, bool f32_entries)
 {
     if (m > MMAX_SYM) {
         launch_zmv_split(s, X, n, m, t, v, y, b, mode, partial, out_norm);
@@ -510,14 +525,8 @@ void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t, cons
     const int64_t T = npad / TS;
     const int64_t tiles = T * (T + 1) / 2;
     const dim3 grid((unsigned)tiles);
-    switch (m) {
-    case 1: hipLaunchKernelGGL(k_zmv_sym<1>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 2: hipLaunchKernelGGL(k_zmv_sym<2>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 3: hipLaunchKernelGGL(k_zmv_sym<3>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 4: hipLaunchKernelGGL(k_zmv_sym<4>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 8: hipLaunchKernelGGL(k_zmv_sym<8>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    default: hipLaunchKernelGGL(k_zmv_sym<0>, grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    }
+    if (f32_entries) launch_zmv_sym_tiles<true>(s, X, n, m, t, v, partial, grid);
+    else launch_zmv_sym_tiles<false>(s, X, n, m, t, v, partial, grid);
     double *blkmax = partial + tiles * 2 * TS;
     hipLaunchKernelGGL(k_zmv_sym_reduce, dim3((unsigned)T), dim3(TS), 0, s, partial, T, n, npad, y, b, mode,
                        blkmax);

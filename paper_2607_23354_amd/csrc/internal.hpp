@@ -206,9 +206,11 @@ void launch_potrf128(hipStream_t s, float *A, int64_t ld, int64_t k0, float *Lin
 // gemv64.hip: FP64 matrix-free products with Z regenerated from X.
 //   mode 0: y = Z v;  mode 1: y = b - Z v (b may be NULL meaning ones) and
 //   out_norm[0] = ||y||_inf (device scalar).
+//   f32_entries: each entry exp(-t d) evaluated in FP32 (sums stay FP64); the
+//   inner products of GMRES may take it, residuals never do (m <= 16 only).
 void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t,
                 const double *v, double *y, const double *b, int mode,
-                double *partial, double *out_norm);
+                double *partial, double *out_norm, bool f32_entries = false);
 size_t zmv_partial_doubles(int64_t n);
 
 // trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.

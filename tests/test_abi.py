@@ -50,17 +50,18 @@ def test_struct_layouts_match_c(tmp_path):
         '#include <stdio.h>\n#include <stddef.h>\n#include "mag.h"\n'
         "int main(void){\n"
         'printf("%zu %zu\\n", sizeof(mag_opts), sizeof(mag_info));\n'
-        'printf("%zu %zu %zu %zu\\n", offsetof(mag_opts, tol), offsetof(mag_opts, seed),'
-        " offsetof(mag_info, argmin_w), offsetof(mag_info, n_update));\n"
+        'printf("%zu %zu %zu %zu %zu\\n", offsetof(mag_opts, tol), offsetof(mag_opts, seed),'
+        " offsetof(mag_opts, inner_prec), offsetof(mag_info, argmin_w), offsetof(mag_info, n_update));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    so, si, o_tol, o_seed, o_arg, o_nu = map(int, out)
+    so, si, o_tol, o_seed, o_ip, o_arg, o_nu = map(int, out)
     assert so == ctypes.sizeof(L.MagOpts)
     assert si == ctypes.sizeof(L.MagInfo)
     assert o_tol == L.MagOpts.tol.offset
     assert o_seed == L.MagOpts.seed.offset
+    assert o_ip == L.MagOpts.inner_prec.offset
     assert o_arg == L.MagInfo.argmin_w.offset
     assert o_nu == L.MagInfo.n_update.offset
 
@@ -71,6 +72,7 @@ def test_host_only_entry_points():
     o = L.MagOpts()
     lib.mag_opts_default(ctypes.byref(o))
     assert o.tol == 1e-12 and o.gmres_restart == 30 and o.solver == L.MAG_AUTO
+    assert o.inner_prec == 0  # every product with Z in FP64 unless asked
     assert lib.mag_padded_size(1) == 256
     assert lib.mag_padded_size(256) == 256
     assert lib.mag_padded_size(257) == 512

@@ -117,3 +117,21 @@ def test_hodlr_full_size_torus(mag, t):
           f"outer={res.info['outer_iters']} gmres={res.info['gmres_iters']} M={res.info['magnitude']:.10g}")
     assert r <= 1e-12
     assert res.info["resid_inf"] <= 1e-12
+
+
+INNER32 = [c for c in CASES if c[0] in ("torus2000_t05", "torus2000_t8", "gauss3001_tstar",
+                                        "gauss1200_m8_t1", "torus2000_rank8", "mixture2500_t30")]
+
+
+@pytest.mark.parametrize("name,mkX,t,kw", INNER32, ids=[c[0] for c in INNER32])
+def test_hodlr_inner_fp32_products(mag, name, mkX, t, kw):
+    # FP32 entries inside GMRES only: the FP64 residual still decides, so the
+    # answer meets the same acceptance as with FP64 inner products
+    X = mkX()
+    kw = dict(kw)
+    kw.setdefault("max_outer", 30)
+    kw.setdefault("max_gmres", 600)
+    res = mag.weighting(dev(X), float(t), solver="hodlr", inner_prec="fp32", **kw)
+    w, ref, errM = check(X, float(t), res)
+    print(f"{name} (inner fp32): outer={res.info['outer_iters']} gmres={res.info['gmres_iters']} "
+          f"relerr_M={errM:.2e}")

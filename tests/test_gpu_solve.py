@@ -180,3 +180,19 @@ def test_autotune_panel_width_and_table_file(mag, tmp_path):
     print(f"autotune n=3000: picked {nb}, ms(256, 512) = {ms}")
     with pytest.raises(mag.MagError):
         mag.tune_panel(len(X), 384)
+
+
+@pytest.mark.parametrize("n,m,t", [(3000, 3, 2.0), (2048, 8, 1.0), (1500, 2, 20.0)])
+def test_fp32_ir_inner_fp32_products(mag, n, m, t):
+    # FP32 entries inside GMRES only; the FP64 residual decides convergence
+    X = W.gaussian(n, m, seed=31)
+    res = mag.weighting(dev(X), t, solver="fp32_ir", inner_prec="fp32", max_outer=20)
+    w = res.w.cpu().numpy()
+    assert np.abs(oracle.residual(X, t, w)).max() <= 1e-12
+    ref = mag.weighting(dev(X), t, solver="fp32_ir").w.cpu().numpy()
+    assert np.abs(w - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_inner_prec_rejected_value(mag):
+    with pytest.raises(ValueError):
+        mag.weighting(dev(W.gaussian(10, 2)), 1.0, inner_prec="fp16")
