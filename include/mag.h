@@ -52,7 +52,9 @@ typedef struct mag_ctx mag_ctx;
 int mag_create(mag_ctx **ctx, int device);
 void mag_destroy(mag_ctx *ctx);
 /* Enqueue subsequent work on `hip_stream` (a hipStream_t; NULL = the
- * context's own stream). */
+ * context's own stream, a blocking stream: it is ordered with the device's
+ * null stream, so work a caller enqueues there -- e.g. PyTorch's default
+ * stream, whose handle is NULL -- and the library's work do not overlap). */
 int mag_set_stream(mag_ctx *ctx, void *hip_stream);
 
 /* ---- options and diagnostics --------------------------------------------- */

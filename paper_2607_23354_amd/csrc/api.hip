@@ -741,7 +741,10 @@ int mag_create(mag_ctx **out, int device)
     HIPCHK(hipSetDevice(device));
     mag_ctx *c = new mag_ctx();
     c->device = device;
-    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    // a blocking stream: work on it is ordered with the device's null stream, which
+    // is where callers that pass NULL to mag_set_stream (PyTorch's default stream)
+    // put their allocations, fills and copies
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamDefault) != hipSuccess) {
         delete c;
         return MAG_EHIP;
     }
