@@ -202,7 +202,7 @@ def main():
                    "seed": args.seed, "solver": "fp32_ir", "parallelism": "single-gpu"},
         "roofline": {
             "bound": "mfma",
-            "kernel": "k_syrk_lower (trailing update A22 -= L21 L21^T, K = 512, FP32 MFMA 32x32x2)",
+            "kernel": "k_syrk_lower (trailing update A22 -= L21 L21^T of two 512-column panels, K = 1024, FP32 MFMA 32x32x2)",
             "achieved": achieved,
             "peak": FP32_MFMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",

@@ -206,7 +206,7 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
     }
 }
 
-template <int MODE>
+template <int MODE, bool LDS_EPI = false>
 __global__ void __launch_bounds__(NT, 2)
 k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
           const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K,
@@ -214,7 +214,7 @@ k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64
 {
     const int64_t ti = blockIdx.x % tilesM;
     const int64_t tj = blockIdx.x / tilesM;
-    gemm_tile_body<MODE>(C, ldc, P, ldp, Q, ldq, ti, tj, K, CT);
+    gemm_tile_body<MODE, LDS_EPI>(C, ldc, P, ldp, Q, ldq, ti, tj, K, CT);
 }
 
 // Trailing symmetric update C -= P P^T on the lower tiles of C only.
@@ -295,12 +295,14 @@ void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int6
 
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode,
-                    float *CT)
+                    float *CT, bool deep)
 {
     const int64_t tm = M / BT, tn = N / BT;
     if (tm <= 0 || tn <= 0 || K <= 0) return;
     const dim3 g((unsigned)(tm * tn));
-    if (mode == kGemmSub)
+    if (mode == kGemmSub && deep)
+        hipLaunchKernelGGL((k_gemm_nt<kGemmSub, true>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+    else if (mode == kGemmSub)
         hipLaunchKernelGGL(k_gemm_nt<kGemmSub>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
     else if (mode == kGemmSet)
         hipLaunchKernelGGL(k_gemm_nt<kGemmSet>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);

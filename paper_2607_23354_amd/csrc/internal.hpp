@@ -192,9 +192,10 @@ void launch_check_finite(hipStream_t s, const double *X, int64_t count, int *sta
 // P is M x K (P[p*ldp + i]), Q is N x K (Q[p*ldq + j]); M, N multiples of 128,
 // K multiple of 16.  kGemmSetT also writes C^T to CT (CT(j, i) at CT[i * ldc + j]).
 enum GemmMode { kGemmSub = 0, kGemmSet = 1, kGemmSetT = 2 };
+// deep: a kGemmSub with a deep K (takes the LDS-staged epilogue).
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K,
-                    GemmMode mode, float *CT = nullptr);
+                    GemmMode mode, float *CT = nullptr, bool deep = false);
 // C (N x N, lower 128-tiles only) -= P P^T with P N x K; N multiple of 128.
 void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                        int64_t N, int64_t K);
