@@ -219,20 +219,21 @@ k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64
 
 // Trailing symmetric update C -= P P^T on the lower tiles of C only.
 // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by id, so
-// id % 8 picks the XCD and consecutive ids of one XCD walk the 64 tiles of
-// one 8 x 8 super-tile of the lower triangle; the 16 operand panels of a
-// super-tile (2 MB at K = 256) stay in that XCD's L2 while its tiles run.
+// id % 8 picks the XCD and consecutive ids of one XCD walk the se x se tiles
+// of one super-tile of the lower triangle; the 2 se operand panels of a
+// super-tile (2 se x 128 rows x K floats: 4 MB at se = 8, K = 512, or at
+// se = 4, K = 1024) stay in that XCD's L2 while its tiles run.
 __global__ void __launch_bounds__(NT, 2)
 k_syrk_lower(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
-             int64_t tilesM, int64_t K)
+             int64_t tilesM, int64_t K, int se)
 {
     const int64_t b = blockIdx.x;
     const int64_t xcd = b % kXcds, slot = b / kXcds;
-    const int64_t sidx = (slot / 64) * kXcds + xcd, within = slot % 64;
+    const int64_t sidx = (slot / (se * se)) * kXcds + xcd, within = slot % (se * se);
     int64_t si, sj;
     tri_index(sidx, si, sj);
-    const int64_t ti = si * 8 + within / 8;
-    const int64_t tj = sj * 8 + within % 8;
+    const int64_t ti = si * se + within / se;
+    const int64_t tj = sj * se + within % se;
     if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
     gemm_tile_body<kGemmSub, true>(C, ldc, P, ldp, P, ldp, ti, tj, K, nullptr);
 }
@@ -315,11 +316,13 @@ void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int
 {
     const int64_t tm = N / BT;
     if (tm <= 0 || K <= 0) return;
-    // super-tiles of 8 x 8 tiles, in groups of kXcds (one per XCD)
-    const int64_t st = (tm + 7) / 8;
+    // super-tiles of se x se tiles, in groups of kXcds (one per XCD), sized so
+    // their operand panels fit an XCD's 4 MB L2
+    const int se = (K > 512) ? 4 : 8;
+    const int64_t st = (tm + se - 1) / se;
     const int64_t nsup = st * (st + 1) / 2;
-    const int64_t blocks = ((nsup + kXcds - 1) / kXcds) * kXcds * 64;
-    hipLaunchKernelGGL(k_syrk_lower, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P, ldp, tm, K);
+    const int64_t blocks = ((nsup + kXcds - 1) / kXcds) * kXcds * se * se;
+    hipLaunchKernelGGL(k_syrk_lower, dim3((unsigned)blocks), dim3(NT), 0, s, C, ldc, P, ldp, tm, K, se);
 }
 
 }  // namespace mag
