@@ -45,7 +45,7 @@ __device__ inline void tri_index(int64_t idx, int64_t &ti, int64_t &tj)
 
 constexpr int TLD = BT + 1;
 // operand stages (2 buffers x P, Q); the SetT epilogue's transposed half tile needs a
-// little more.  32 KB for the other modes lets five workgroups share a CU's LDS.
+// little more.  32 KB for the other modes lets four workgroups share a CU's LDS.
 constexpr int LDS_STAGES = 2 * 2 * KC * BT;
 constexpr int LDS_SETT = (LDS_STAGES > BT * (64 + 1)) ? LDS_STAGES : BT * (64 + 1);
 
