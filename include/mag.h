@@ -184,6 +184,47 @@ int mag_tplus(mag_ctx *ctx, const double *X, int64_t n, int32_t m, const mag_tpl
 int mag_dwdt(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, double *w,
              double *dwdt, const mag_opts *opts);
 
+/* ---- extreme eigenvalues of Z (positive-definiteness check) ---------------
+ * Section 4.2 checks that Z is positive definite, at little cost beside the
+ * solve, by estimating its smallest eigenvalue with symmetric Lanczos.  Here:
+ *   lambda_max: Lanczos on Z, with the matrix-free FP64 product Z v;
+ *   lambda_min: Lanczos on Z^{-1}, each product an FP32-factor + FP64
+ *               refinement solve (the factor is computed once, as for
+ *               mag_weighting; solver AUTO or FP32_IR, tol from opts);
+ * both with full reorthogonalisation (two classical Gram-Schmidt passes).
+ * The Ritz value of step j is the extreme eigenvalue of the j x j tridiagonal
+ * (bisection on Sturm counts), and r_j = beta_j |s_j| (s: the last entry of its
+ * unit eigenvector) bounds the residual of its Ritz vector, so some eigenvalue
+ * of the operator lies within r_j of it.  A side stops when r_j <= rtol times
+ * its Ritz value, when beta_j vanishes (an invariant subspace: exact), or after
+ * max_iter steps.  In exact arithmetic the Ritz values lie inside the spectrum:
+ * lambda_max is approached from below and lambda_min from above. */
+typedef struct {
+    int32_t max_iter;      /* Lanczos steps per side; 0 = 80; at most 256                */
+    int32_t pad_;
+    double rtol;           /* 0 = 1e-8                                                     */
+} mag_eig_opts;
+
+typedef struct {
+    double lambda_max, lambda_min, cond;  /* cond = lambda_max / lambda_min               */
+    double resid_max;      /* r of the lambda_max side (a bound on Z's residual)           */
+    double resid_min;      /* r of the lambda_min side (for Z^{-1}: |1/lambda - mu| <= r)  */
+    int32_t iters_max, iters_min;        /* Lanczos steps taken                           */
+    int32_t converged;     /* bit 0: the lambda_max side met rtol, bit 1: lambda_min side   */
+    int32_t solve_steps;   /* refinement steps over all solves with Z                       */
+} mag_eig_info;
+
+void mag_eig_opts_default(mag_eig_opts *opts);
+
+/* Extreme eigenvalues of Z(t) for the points X (device, n x m, distinct).
+ * v0 (device, n, may be NULL) starts both sides; NULL uses
+ * v0_j = 1/2 + frac((j + 1) g), g = (sqrt(5) - 1)/2, j = 0..n-1.  info (HOST) is
+ * required.  MAG_EINVAL for a zero v0 or bad arguments, MAG_ENOTPD for
+ * coincident points, MAG_ENOMEM when the FP32 factor does not fit, and the
+ * refinement's code when a solve fails (MAG_ENOCONV keeps the values so far). */
+int mag_eig_extremes(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, const double *v0,
+                     const mag_eig_opts *eopts, const mag_opts *opts, mag_eig_info *info);
+
 /* ---- adjoint of (w, Mag) with respect to (X, t) ----------------------------
  * Differentiating Z(t, X) w = 1: with lambda = Z^{-1}(gM 1 + gw),
  *   dL/dt   = lambda^T (D o Z) w,

@@ -22,7 +22,7 @@ from ._lib import MagError, MagInfo, MagOpts, MagTplusInfo, MagTplusOpts  # noqa
 __all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "tile32",
            "factor32", "prec_apply", "padded_size", "tplus", "dwdt", "dzmatvec",
            "MagnitudeFn", "weighting_and_magnitude", "weighting_batch", "tplus_batch",
-           "MagError", "SOLVERS"]
+           "eig_extremes", "MagError", "SOLVERS"]
 
 SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
            "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR}
@@ -250,6 +250,34 @@ def dwdt(X: torch.Tensor, t: float, *, ctx: Context | None = None, **opts):
     d = torch.empty(n, dtype=torch.float64, device=X.device)
     _lib.check(c.lib.mag_dwdt(c.handle, _ptr(X), n, m, float(t), _ptr(w), _ptr(d), ctypes.byref(o)), "mag_dwdt")
     return w, d
+
+
+def eig_extremes(X: torch.Tensor, t: float, *, v0: torch.Tensor | None = None, max_iter: int = 80,
+                 rtol: float = 1e-8, ctx: Context | None = None, **opts) -> dict:
+    """Extreme eigenvalues of Z(t) by symmetric Lanczos (Section 4.2's
+    positive-definiteness check): lambda_max from Z's matrix-free products,
+    lambda_min from Z^{-1} through the FP32 factor + refinement.  Returns the
+    info fields as a dict (status: MAG_OK, or MAG_ENOCONV when an inner solve
+    missed its tolerance)."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    o = make_opts(**opts)
+    eo = _lib.MagEigOpts()
+    c.lib.mag_eig_opts_default(ctypes.byref(eo))
+    eo.max_iter, eo.rtol = int(max_iter), float(rtol)
+    if v0 is not None:
+        if v0.device != X.device or v0.dtype != torch.float64 or v0.numel() != n:
+            raise ValueError("v0: float64 vector of n entries on the device of X")
+        v0 = v0.contiguous()
+    info = _lib.MagEigInfo()
+    rc = c.lib.mag_eig_extremes(c.handle, _ptr(X), n, m, float(t), _ptr(v0), ctypes.byref(eo), ctypes.byref(o),
+                                ctypes.byref(info))
+    if rc not in (_lib.MAG_OK, _lib.MAG_ENOCONV):
+        _lib.check(rc, "mag_eig_extremes")
+    d = info.as_dict()
+    d["status"] = rc
+    return d
 
 
 @dataclass

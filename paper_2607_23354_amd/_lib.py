@@ -100,6 +100,31 @@ class MagTplusInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class MagEigOpts(ctypes.Structure):
+    _fields_ = [
+        ("max_iter", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("rtol", ctypes.c_double),
+    ]
+
+
+class MagEigInfo(ctypes.Structure):
+    _fields_ = [
+        ("lambda_max", ctypes.c_double),
+        ("lambda_min", ctypes.c_double),
+        ("cond", ctypes.c_double),
+        ("resid_max", ctypes.c_double),
+        ("resid_min", ctypes.c_double),
+        ("iters_max", ctypes.c_int32),
+        ("iters_min", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+        ("solve_steps", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -133,6 +158,9 @@ SIGNATURES = {
     "mag_tplus": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(MagTplusOpts), ctypes.POINTER(MagOpts),
                                  ctypes.POINTER(_d), _vp, ctypes.POINTER(MagTplusInfo)]),
     "mag_dwdt": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp, ctypes.POINTER(MagOpts)]),
+    "mag_eig_opts_default": (None, [ctypes.POINTER(MagEigOpts)]),
+    "mag_eig_extremes": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, ctypes.POINTER(MagEigOpts),
+                                        ctypes.POINTER(MagOpts), ctypes.POINTER(MagEigInfo)]),
     "mag_weighting_fwd": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, ctypes.POINTER(_vp),
                                          ctypes.POINTER(MagOpts), ctypes.POINTER(MagInfo)]),
     "mag_weighting_vjp": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _d, _vp, _d, _vp, _vp,

@@ -16,6 +16,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -636,6 +637,154 @@ int ensure_aux(mag_ctx *ctx, int64_t npad)
     return ensure(ctx, ctx->aux, sizeof(double) * ((size_t)npad * 4 + 64));
 }
 
+// ---- symmetric tridiagonal helpers of the Lanczos estimator (host) ----------
+// T: diagonal a[0..k), off-diagonal b[0..k-1).
+
+// Number of eigenvalues of T below x: negative pivots of the LDL^T
+// factorisation of T - x I (Sylvester's law of inertia).
+int sturm_below(const std::vector<double> &a, const std::vector<double> &b, int k, double x, double tiny)
+{
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < k; ++i) {
+        q = (a[i] - x) - (i > 0 ? b[i - 1] * b[i - 1] / q : 0.0);
+        if (q == 0.0) q = -tiny;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Largest eigenvalue of T by bisection on the Sturm count, started from the
+// Gershgorin interval.
+double tridiag_top(const std::vector<double> &a, const std::vector<double> &b, int k)
+{
+    double lo = INFINITY, hi = -INFINITY, scale = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+        scale = std::max(scale, std::fabs(a[i]) + r);
+    }
+    const double tiny = std::max(scale, 1e-300) * 1e-300;
+    for (int it = 0; it < 2200 && hi - lo > 2.0 * DBL_EPSILON * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_below(a, b, k, mid, tiny) == k) hi = mid;  // every eigenvalue below mid
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Last entry of the unit eigenvector of T for the eigenvalue theta: inverse
+// iteration, (T - theta I) y = z solved by Gaussian elimination with partial
+// pivoting on the tridiagonal (row swaps fill a second superdiagonal).
+double tridiag_last(const std::vector<double> &a, const std::vector<double> &b, int k, double theta)
+{
+    if (k == 1) return 1.0;
+    double scale = 0.0;
+    for (int i = 0; i < k; ++i) scale = std::max(scale, std::fabs(a[i]) + (i + 1 < k ? std::fabs(b[i]) : 0.0));
+    const double tiny = DBL_EPSILON * std::max(scale, 1e-300);
+    std::vector<double> d(k), dl(k - 1), du(k - 1), du2(k, 0.0);
+    std::vector<char> swp(k - 1, 0);
+    for (int i = 0; i < k; ++i) d[i] = a[i] - theta;
+    for (int i = 0; i + 1 < k; ++i) dl[i] = du[i] = b[i];
+    for (int i = 0; i + 1 < k; ++i) {
+        if (std::fabs(d[i]) >= std::fabs(dl[i])) {
+            if (d[i] == 0.0) d[i] = tiny;
+            const double l = dl[i] / d[i];
+            dl[i] = l;
+            d[i + 1] -= l * du[i];
+        } else {
+            // rows i and i+1 trade places; the pivot row brings its superdiagonal along
+            const double l = d[i] / dl[i];
+            d[i] = dl[i];
+            dl[i] = l;
+            const double u0 = du[i];
+            du[i] = d[i + 1];
+            d[i + 1] = u0 - l * d[i + 1];
+            if (i + 2 < k) {
+                du2[i] = du[i + 1];
+                du[i + 1] = -l * du[i + 1];
+            }
+            swp[i] = 1;
+        }
+    }
+    if (d[k - 1] == 0.0) d[k - 1] = tiny;
+    std::vector<double> y(k, 1.0 / std::sqrt((double)k));
+    for (int it = 0; it < 3; ++it) {
+        for (int i = 0; i + 1 < k; ++i) {
+            if (swp[i]) {
+                const double y0 = y[i];
+                y[i] = y[i + 1];
+                y[i + 1] = y0 - dl[i] * y[i];
+            } else {
+                y[i + 1] -= dl[i] * y[i];
+            }
+        }
+        y[k - 1] /= d[k - 1];
+        y[k - 2] = (y[k - 2] - du[k - 2] * y[k - 1]) / d[k - 2];
+        for (int i = k - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / d[i];
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm = std::max(nrm, std::fabs(y[i]));
+        for (int i = 0; i < k; ++i) y[i] /= nrm;  // keep the scale bounded between steps
+    }
+    double nrm2 = 0.0;
+    for (int i = 0; i < k; ++i) nrm2 += y[i] * y[i];
+    return y[k - 1] / std::sqrt(nrm2);
+}
+
+struct LanczosResult {
+    double theta = 0.0, resid = 0.0;
+    int iters = 0;
+    bool converged = false;
+};
+
+// Symmetric Lanczos for the largest eigenvalue of the operator applied by
+// op(in, out) (device npad vectors, zero on the padding), from q0 (device npad,
+// unit 2-norm).  Q holds max_iter + 1 basis vectors of npad doubles; u is a
+// work vector; dev: 2 * (max_iter + 2) device doubles.  Every new vector is
+// orthogonalised against the whole basis twice (classical Gram-Schmidt).
+int lanczos_top(mag_ctx *ctx, int64_t npad, const std::function<int(const double *, double *)> &op,
+                double *Q, double *u, double *dev, int max_iter, double rtol, LanczosResult &res)
+{
+    hipStream_t s = ctx->stream;
+    double *partial = (double *)ctx->partial.p;
+    // the dot products of step j write partial sums for j + 1 vectors
+    if (ctx->partial.bytes < sizeof(double) * blas1_partial_doubles(max_iter + 1)) return MAG_EINTERNAL;
+    std::vector<double> a, b, hbuf(2 * (max_iter + 2) + 1);
+    for (int j = 0; j < max_iter; ++j) {
+        double *qj = Q + (size_t)j * npad;
+        double *qj1 = Q + (size_t)(j + 1) * npad;
+        CHK(op(qj, u));
+        launch_multidot(s, Q, npad, j + 1, u, npad, partial, dev);
+        launch_multi_axpy(s, Q, npad, j + 1, dev, u, npad, -1.0);
+        launch_multidot(s, Q, npad, j + 1, u, npad, partial, dev + (j + 1));
+        launch_multi_axpy(s, Q, npad, j + 1, dev + (j + 1), u, npad, -1.0);
+        launch_nrm2(s, u, npad, partial, dev + 2 * (j + 1));
+        HIPCHK(hipMemcpyAsync(hbuf.data(), dev, sizeof(double) * (2 * (j + 1) + 1), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        a.push_back(hbuf[j] + hbuf[2 * j + 1]);  // q_j . A q_j over both passes
+        const double beta = hbuf[2 * (j + 1)];
+        const int k = j + 1;
+        res.theta = tridiag_top(a, b, k);
+        res.iters = k;
+        if (!std::isfinite(res.theta) || !std::isfinite(beta)) return MAG_EINTERNAL;
+        if (!(beta > 1e-14 * std::fabs(res.theta))) {  // invariant subspace: T's eigenvalues are exact
+            res.resid = std::fabs(beta);
+            res.converged = true;
+            return MAG_OK;
+        }
+        res.resid = beta * std::fabs(tridiag_last(a, b, k, res.theta));
+        if (res.resid <= rtol * std::fabs(res.theta)) {
+            res.converged = true;
+            return MAG_OK;
+        }
+        b.push_back(beta);
+        if (k < max_iter) launch_scale_inv(s, u, qj1, npad, dev + 2 * (j + 1));
+    }
+    return MAG_OK;
+}
+
 }  // namespace
 
 struct mag_factor {
@@ -772,7 +921,7 @@ void mag_destroy(mag_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints, &c->aux, &c->bfactor,
                       &c->bdinv, &c->bvec, &c->bscal, &c->bpartial, &c->bints, &c->bdesc, &c->barena,
-                      &c->bstage, &c->hodlr})
+                      &c->bstage, &c->hodlr, &c->eig})
         if (b->p) hipFree(b->p);
     if (c->bhost) hipHostFree(c->bhost);
     if (c->blas) rocblas_destroy_handle((rocblas_handle)c->blas);
@@ -1258,6 +1407,98 @@ int mag_dwdt(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, double
     HIPCHK(hipMemcpyAsync(dwdt, d, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return MAG_OK;
+}
+
+// ---- extreme eigenvalues (Section 4.2 positive-definiteness check) -----------
+
+void mag_eig_opts_default(mag_eig_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->max_iter = 80;
+    o->rtol = 1e-8;
+}
+
+int mag_eig_extremes(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, const double *v0,
+                     const mag_eig_opts *eopts, const mag_opts *opts, mag_eig_info *info)
+{
+    if (!c || !info || !valid_args(X, n, m, t)) return MAG_EINVAL;
+    mag_eig_opts eo;
+    if (eopts) eo = *eopts;
+    else mag_eig_opts_default(&eo);
+    const int max_iter = eo.max_iter > 0 ? eo.max_iter : 80;
+    const double rtol = eo.rtol > 0 ? eo.rtol : 1e-8;
+    if (max_iter > 256) return MAG_EINVAL;
+    mag_opts o;
+    if (opts) o = *opts;
+    else mag_opts_default(&o);
+    if (o.solver != MAG_AUTO && o.solver != MAG_FP32_IR) return MAG_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    HIPCHK(hipSetDevice(c->device));
+    const int restart = std::max(1, o.gmres_restart);
+    CHK(ensure_solver(c, n, m, restart));
+    // the orthogonalisation's dot products against up to max_iter + 1 vectors
+    CHK(ensure(c, c->partial, sizeof(double) * (blas1_partial_doubles(max_iter + 2) + 64)));
+    CHK(check_points(c, X, n, m, false));
+    if (o.solver == MAG_AUTO && !auto_dense(c, n)) return MAG_ENOMEM;
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure_ctx_factor(c, n));
+    // basis (max_iter + 1 vectors), the work vector, start vector and device scalars
+    CHK(ensure(c, c->eig, sizeof(double) * ((size_t)(max_iter + 3) * npad + 2 * (max_iter + 2) + 64)));
+    hipStream_t s = c->stream;
+    double *Q = (double *)c->eig.p;
+    double *u = Q + (size_t)(max_iter + 1) * npad;
+    double *q0 = u + npad;
+    double *dev = q0 + npad;
+    double *partial = (double *)c->partial.p;
+    if (v0) {
+        launch_scale(s, v0, 1.0, q0, n, npad);
+    } else {
+        launch_golden(s, q0, n, npad);
+    }
+    launch_nrm2(s, q0, npad, partial, dev);
+    HIPCHK(hipMemcpyAsync(c->host_scalars, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (!(c->host_scalars[0] > 0.0) || !std::isfinite(c->host_scalars[0])) return MAG_EINVAL;
+    const double q0norm = c->host_scalars[0];
+
+    // lambda_max: Lanczos on Z (matrix-free FP64 products)
+    LanczosResult top;
+    const auto zop = [&](const double *in, double *out) -> int {
+        launch_zmv(s, X, n, m, t, in, out, nullptr, 0, partial, nullptr);
+        return MAG_OK;
+    };
+    launch_scale(s, q0, 1.0 / q0norm, Q, npad, npad);
+    CHK(lanczos_top(c, npad, zop, Q, u, dev, max_iter, rtol, top));
+
+    // lambda_min: Lanczos on Z^{-1} through the FP32 factor + refinement
+    Factor32 F = ctx_factor(c, n);
+    CHK(factor_fp32(c, X, n, m, t, F, nullptr, nullptr));
+    int solve_steps = 0, solve_rc = MAG_OK;
+    const auto iop = [&](const double *in, double *out) -> int {
+        RefineStats st;
+        const int rc = refine_solve(c, X, n, m, t, F, in, 1.0, out, o, st);
+        solve_steps += st.outer;
+        if (rc == MAG_ENOCONV) {
+            solve_rc = rc;
+            return MAG_OK;
+        }
+        return rc;
+    };
+    LanczosResult bot;
+    launch_scale(s, q0, 1.0 / q0norm, Q, npad, npad);
+    CHK(lanczos_top(c, npad, iop, Q, u, dev, max_iter, rtol, bot));
+
+    info->lambda_max = top.theta;
+    info->resid_max = top.resid;
+    info->iters_max = top.iters;
+    info->lambda_min = (bot.theta > 0.0) ? 1.0 / bot.theta : 0.0;
+    info->resid_min = bot.resid;
+    info->iters_min = bot.iters;
+    info->cond = (bot.theta > 0.0) ? top.theta * bot.theta : INFINITY;
+    info->converged = (top.converged ? 1 : 0) | (bot.converged ? 2 : 0);
+    info->solve_steps = solve_steps;
+    return solve_rc;
 }
 
 // ---- adjoint ----------------------------------------------------------------

@@ -207,6 +207,22 @@ __global__ void k_affine_ones(const double *x, double a, double *y, int64_t n, i
         y[i] = (i < n) ? a + (x ? x[i] : 0.0) : 0.0;
 }
 
+// Deterministic start vector with no special structure: the Weyl sequence of
+// the golden ratio, shifted to (1/2, 3/2).
+__global__ void k_golden(double *y, int64_t n, int64_t len)
+{
+    const double g = 0.6180339887498949;  // (sqrt 5 - 1) / 2
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (i < n) {
+            const double p = (double)(i + 1) * g;
+            v = 0.5 + (p - floor(p));
+        }
+        y[i] = v;
+    }
+}
+
 __global__ void k_scale(const double *x, double a, double *y, int64_t n, int64_t len)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len;
@@ -483,6 +499,10 @@ void launch_amax(hipStream_t s, const double *x, int64_t len, double *partial, d
 void launch_affine_ones(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len)
 {
     hipLaunchKernelGGL(k_affine_ones, dim3(grid_for(len)), dim3(256), 0, s, x, a, y, n, len);
+}
+void launch_golden(hipStream_t s, double *y, int64_t n, int64_t len)
+{
+    hipLaunchKernelGGL(k_golden, dim3(grid_for(len)), dim3(256), 0, s, y, n, len);
 }
 void launch_scale(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len)
 {

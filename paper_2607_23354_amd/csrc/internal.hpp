@@ -133,6 +133,7 @@ struct mag_ctx {
     // batched solves
     mag::DevBuf bfactor, bdinv, bvec, bscal, bpartial, bints, bdesc, barena, bstage;
     mag::DevBuf hodlr;     // HODLR preconditioner workspace
+    mag::DevBuf eig;       // Lanczos bases of the eigenvalue estimator
     void *bhost = nullptr;   // pinned host staging for work lists and descriptors
     size_t bhost_bytes = 0;
     double *host_scalars = nullptr;  // pinned host staging (64 doubles)
@@ -244,6 +245,8 @@ void launch_amax(hipStream_t s, const double *x, int64_t len, double *partial, d
 void launch_affine_ones(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len);
 // y = a*x on [0, n), zero on [n, len)
 void launch_scale(hipStream_t s, const double *x, double a, double *y, int64_t n, int64_t len);
+// y_j = 1/2 + frac((j + 1) g), g = (sqrt 5 - 1)/2, on [0, n); zero on [n, len)
+void launch_golden(hipStream_t s, double *y, int64_t n, int64_t len);
 
 // ---- hodlr.hip: HODLR preconditioner ---------------------------------------------
 // Device pointers into ctx->hodlr (valid until the next HODLR factorisation on

@@ -52,11 +52,16 @@ def test_struct_layouts_match_c(tmp_path):
         'printf("%zu %zu\\n", sizeof(mag_opts), sizeof(mag_info));\n'
         'printf("%zu %zu %zu %zu %zu\\n", offsetof(mag_opts, tol), offsetof(mag_opts, seed),'
         " offsetof(mag_opts, inner_prec), offsetof(mag_info, argmin_w), offsetof(mag_info, n_update));\n"
+        'printf("%zu %zu %zu %zu %zu\\n", sizeof(mag_eig_opts), sizeof(mag_eig_info), offsetof(mag_eig_opts, rtol),'
+        " offsetof(mag_eig_info, iters_max), offsetof(mag_eig_info, solve_steps));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    so, si, o_tol, o_seed, o_ip, o_arg, o_nu = map(int, out)
+    so, si, o_tol, o_seed, o_ip, o_arg, o_nu, seo, sei, o_rt, o_im, o_ss = map(int, out)
+    assert seo == ctypes.sizeof(L.MagEigOpts) and sei == ctypes.sizeof(L.MagEigInfo)
+    assert o_rt == L.MagEigOpts.rtol.offset
+    assert o_im == L.MagEigInfo.iters_max.offset and o_ss == L.MagEigInfo.solve_steps.offset
     assert so == ctypes.sizeof(L.MagOpts)
     assert si == ctypes.sizeof(L.MagInfo)
     assert o_tol == L.MagOpts.tol.offset
@@ -84,6 +89,11 @@ def test_host_only_entry_points():
     assert lib.mag_weighting(None, None, 10, 3, 1.0, None, None, None) == L.MAG_EINVAL
     assert lib.mag_dmin(None, None, 10, 3, None) == L.MAG_EINVAL
     assert lib.mag_set_stream(None, None) == L.MAG_EINVAL
+    eo = L.MagEigOpts()
+    lib.mag_eig_opts_default(ctypes.byref(eo))
+    assert eo.max_iter == 80 and eo.rtol == 1e-8
+    ei = L.MagEigInfo()
+    assert lib.mag_eig_extremes(None, None, 10, 3, 1.0, None, None, None, ctypes.byref(ei)) == L.MAG_EINVAL
 
 
 def test_no_fallback_without_library(monkeypatch, tmp_path):

@@ -154,6 +154,16 @@ def centre_kgon(k: int, m: int = 2) -> np.ndarray:
     return X
 
 
+def regular_polygon(k: int, m: int = 2) -> np.ndarray:
+    """The vertices of a regular k-gon of unit circumradius in the first two
+    coordinates (remaining coordinates zero), in angular order."""
+    X = np.zeros((k, m), dtype=np.float64)
+    ang = 2.0 * np.pi * np.arange(k) / k
+    X[:, 0] = np.cos(ang)
+    X[:, 1] = np.sin(ang)
+    return X
+
+
 def gaussian_cutoff_estimate(n: int, m: int) -> float:
     """Empirical law for the cutoff of Gaussian clouds, E t_+ ~ gamma m^(-2/3)
     n^(1/4) with gamma = 2^(7/8) (Appendix C.2, eq. gaussianCutoff).  Used only
