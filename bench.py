@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--check-rows", type=int, default=512)
+    ap.add_argument("--eig-steps", type=int, default=1,
+                    help="timed runs of the extreme-eigenvalue estimator on the same workload (0: skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the solves, so a "
                          "hardware-counter run can scale FETCH_SIZE / WRITE_SIZE by a kernel "
@@ -166,6 +168,22 @@ def main():
         except Exception as e:  # report, do not hide
             dense = {"error": repr(e)}
 
+    # the positive-definiteness check of the same workload (Lanczos on Z and Z^{-1});
+    # reported beside the metric, never part of it
+    eig = None
+    if args.eig_steps > 0:
+        mag.eig_extremes(Xd, t, ctx=ctx)
+        torch.cuda.synchronize()
+        e0 = time.perf_counter()
+        einfo = None
+        for _ in range(args.eig_steps):
+            einfo = mag.eig_extremes(Xd, t, ctx=ctx)
+        torch.cuda.synchronize()
+        e1 = time.perf_counter()
+        eig = dict(einfo)
+        eig["ms"] = (e1 - e0) * 1e3 / args.eig_steps
+        print(f"[bench] eig_extremes {eig['ms']:.2f} ms", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         ns = args.cpu_sample_n
@@ -219,6 +237,7 @@ def main():
                   "min_w": last["min_w"], "shifted": last["shifted"]},
         "fp64_dense": dense,
         "speedup_vs_fp64_dense": (dense["ms_per_solve"] / ms_per_step) if dense and "ms_per_solve" in dense else None,
+        "eig_extremes": eig,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
