@@ -150,12 +150,21 @@ typedef struct {
     int32_t grid;          /* grid points, default 32                                     */
     int32_t max_extend;    /* downward grid extensions, default 2                          */
     int32_t newton;        /* 1: safeguarded Newton inside bisection, default 1            */
-    int32_t pad_;
+    int32_t method;        /* bracket refinement: MAG_TPLUS_BISECT (default) or RIDDERS    */
     double lo_factor;      /* grid spans [t_b*lo_factor, t_b], default 1e-3                */
     double rtol;           /* relative bracket width, default 1e-6                         */
     double eps;            /* early halt when 0 <= min w < eps; 0 = n * 2^-53              */
     double t_lo, t_hi;     /* optional starting bracket (0 = none)                          */
 } mag_tplus_opts;
+
+/* Ridders' method (Section 2 names it for t_+): in s = log t, with the bracket
+ * s_a < s_b (g(s) = min w(e^s), g_a < 0 <= g_b) and g_m at the midpoint s_m, the
+ * next point is s_m + (s_m - s_a) sign(g_a - g_b) g_m / sqrt(g_m^2 - g_a g_b),
+ * which lies inside the bracket; each step evaluates the midpoint and that point
+ * (two solves) and keeps the uppermost sign change among the four.  No
+ * derivative is used (newton is ignored). */
+#define MAG_TPLUS_BISECT 0
+#define MAG_TPLUS_RIDDERS 1
 
 typedef struct {
     double t_plus;         /* = *t_plus                                                     */
@@ -164,7 +173,7 @@ typedef struct {
     double min_w;          /* min w at t_plus                                               */
     double t_bracket_lo, t_bracket_hi;
     int32_t solves;        /* weighting solves (factorisations)                             */
-    int32_t newton_steps;
+    int32_t newton_steps;  /* interpolated points: Newton (bisection method) or Ridders     */
     int32_t no_sign_change;/* 1: w >= 0 on the whole (extended) grid; t_plus = 0            */
     int32_t status;
 } mag_tplus_info;

@@ -287,11 +287,22 @@ class TplusResult:
     info: dict
 
 
+TPLUS_METHODS = {"bisection": 0, "ridders": 1}
+
+
+def _tplus_method(method: str) -> int:
+    if method not in TPLUS_METHODS:
+        raise ValueError(f"method must be one of {sorted(TPLUS_METHODS)}")
+    return TPLUS_METHODS[method]
+
+
 def tplus(X: torch.Tensor, *, ctx: Context | None = None, grid: int = 32, lo_factor: float = 1e-3,
           rtol: float = 1e-6, newton: bool = True, max_extend: int = 2, eps: float = 0.0,
-          t_lo: float = 0.0, t_hi: float = 0.0, want_w: bool = True, **opts) -> TplusResult:
+          t_lo: float = 0.0, t_hi: float = 0.0, want_w: bool = True, method: str = "bisection",
+          **opts) -> TplusResult:
     """Cutoff t_+ (least t from which w >= 0) by a downward log-grid scan from
-    log(n-1)/d_min and safeguarded Newton/bisection in log t."""
+    log(n-1)/d_min, then the bracket refined in log t by safeguarded
+    Newton/bisection (method "bisection") or Ridders' method ("ridders")."""
     X = _points(X)
     n, m = X.shape
     c = _ctx(ctx, X)
@@ -299,6 +310,7 @@ def tplus(X: torch.Tensor, *, ctx: Context | None = None, grid: int = 32, lo_fac
     c.lib.mag_tplus_opts_default(ctypes.byref(to))
     to.grid, to.lo_factor, to.rtol, to.newton = grid, lo_factor, rtol, 1 if newton else 0
     to.max_extend, to.eps, to.t_lo, to.t_hi = max_extend, eps, t_lo, t_hi
+    to.method = _tplus_method(method)
     o = make_opts(**opts)
     w = torch.empty(n, dtype=torch.float64, device=X.device) if want_w else None
     tp = ctypes.c_double()
@@ -405,7 +417,7 @@ def weighting_batch(X: torch.Tensor, offs, t, *, ctx: Context | None = None, rai
 
 def tplus_batch(X: torch.Tensor, offs, *, ctx: Context | None = None, grid: int = 32, lo_factor: float = 1e-3,
                 rtol: float = 1e-6, newton: bool = True, max_extend: int = 2, eps: float = 0.0,
-                want_w: bool = False, **opts):
+                want_w: bool = False, method: str = "bisection", **opts):
     """Batched cutoff search over the clouds rows [offs[b], offs[b+1]) of X.
     Returns (t_plus list, w packed or None, info list)."""
     X, offs, arr = _pack(X, offs)
@@ -416,6 +428,7 @@ def tplus_batch(X: torch.Tensor, offs, *, ctx: Context | None = None, grid: int 
     c.lib.mag_tplus_opts_default(ctypes.byref(to))
     to.grid, to.lo_factor, to.rtol, to.newton = grid, lo_factor, rtol, 1 if newton else 0
     to.max_extend, to.eps = max_extend, eps
+    to.method = _tplus_method(method)
     o = make_opts(**opts)
     tp = (ctypes.c_double * B)()
     infos = (MagTplusInfo * B)()

@@ -73,7 +73,7 @@ class MagTplusOpts(ctypes.Structure):
         ("grid", ctypes.c_int32),
         ("max_extend", ctypes.c_int32),
         ("newton", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("method", ctypes.c_int32),
         ("lo_factor", ctypes.c_double),
         ("rtol", ctypes.c_double),
         ("eps", ctypes.c_double),

@@ -1233,6 +1233,7 @@ int mag_tplus(mag_ctx *c, const double *X, int64_t n, int32_t m, const mag_tplus
     if (sopts) o = *sopts;
     else mag_opts_default(&o);
     if (to.grid < 2 || !(to.lo_factor > 0.0 && to.lo_factor < 1.0) || !(to.rtol > 0.0)) return MAG_EINVAL;
+    if (to.method != MAG_TPLUS_BISECT && to.method != MAG_TPLUS_RIDDERS) return MAG_EINVAL;
     const int restart = std::max(1, o.gmres_restart);
     CHK(ensure_solver(c, n, m, restart));
     int rc = check_points(c, X, n, m);
@@ -1259,7 +1260,8 @@ int mag_tplus(mag_ctx *c, const double *X, int64_t n, int32_t m, const mag_tplus
     int solves = 0, newton_steps = 0;
     TEval lo, hi, cur;
     bool have_lo = false, have_hi = false;
-    const bool newton = to.newton != 0;
+    const bool ridders = to.method == MAG_TPLUS_RIDDERS;
+    const bool newton = to.newton != 0 && !ridders;
 
     auto accept_hi = [&](const TEval &e) -> int {
         hi = e;
@@ -1313,9 +1315,38 @@ int mag_tplus(mag_ctx *c, const double *X, int64_t n, int32_t m, const mag_tplus
         }
         return MAG_OK;
     }
-    // refine the bracket [lo, hi]: safeguarded Newton in log t inside bisection.
-    // The last evaluated point is lo, whose factor is still in the context, so
-    // its derivative costs one refinement solve rather than a factorisation.
+    // Ridders' method in log t: each step evaluates the midpoint and then the
+    // Ridders point from the bracket values at the step's start; both lie inside
+    // the bracket on the root's side, and each update keeps lo < 0 <= hi, the
+    // uppermost sign change.
+    int guard = 0;
+    bool halted = false;
+    auto take = [&](const TEval &e) -> int {
+        if (e.minw < 0.0) {
+            lo = e;
+        } else {
+            CHK(accept_hi(e));
+            if (e.minw < eps) halted = true;  // halting rule: 0 <= min w < eps
+        }
+        return MAG_OK;
+    };
+    while (ridders && !halted && (hi.t - lo.t) / hi.t > to.rtol && guard++ < 200) {
+        const double sa = std::log(lo.t), sb = std::log(hi.t), ga = lo.minw, gb = hi.minw;
+        const double tm = std::exp(0.5 * (sa + sb));
+        if (!(tm > lo.t && tm < hi.t)) break;
+        CHK(tplus_eval(c, X, n, m, tm, o, false, w_cur, cur, solves));
+        CHK(take(cur));
+        if (halted || (hi.t - lo.t) / hi.t <= to.rtol) break;
+        const double tx = std::exp(ridders_point(sa, ga, sb, gb, cur.minw));
+        if (!(tx > lo.t && tx < hi.t)) continue;
+        CHK(tplus_eval(c, X, n, m, tx, o, false, w_cur, cur, solves));
+        ++newton_steps;
+        CHK(take(cur));
+    }
+    // otherwise refine the bracket [lo, hi]: safeguarded Newton in log t inside
+    // bisection.  The last evaluated point is lo, whose factor is still in the
+    // context, so its derivative costs one refinement solve rather than a
+    // factorisation.
     TEval last = lo;
     if (newton) {
         CHK(tplus_deriv(c, X, n, m, o, w_cur, last));
@@ -1323,8 +1354,7 @@ int mag_tplus(mag_ctx *c, const double *X, int64_t n, int32_t m, const mag_tplus
     }
     bool prev_newton = false;
     double prev_step = INFINITY;
-    int guard = 0;
-    while ((hi.t - lo.t) / hi.t > to.rtol && guard++ < 200) {
+    while (!ridders && (hi.t - lo.t) / hi.t > to.rtol && guard++ < 200) {
         const double slo = std::log(lo.t), shi = std::log(hi.t);
         const double mid = 0.5 * (slo + shi);
         double sc = mid;

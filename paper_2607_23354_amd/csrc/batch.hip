@@ -643,6 +643,7 @@ int mag_tplus_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs,
     if (sopts) o = *sopts;
     else mag_opts_default(&o);
     if (to.grid < 2 || !(to.lo_factor > 0.0 && to.lo_factor < 1.0) || !(to.rtol > 0.0)) return MAG_EINVAL;
+    if (to.method != MAG_TPLUS_BISECT && to.method != MAG_TPLUS_RIDDERS) return MAG_EINVAL;
     std::vector<const double *> Xs(B);
     std::vector<int64_t> ns(B);
     for (int b = 0; b < B; ++b) {
@@ -652,6 +653,8 @@ int mag_tplus_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs,
     }
     BRC(validate_batch(c, Xs, ns, m));
     if (m > pair_max_dim() && to.newton) to.newton = 0;
+    const bool ridders = to.method == MAG_TPLUS_RIDDERS;
+    if (ridders) to.newton = 0;
 
     // per-cloud state of the search (same rules as mag_tplus)
     struct Cloud {
@@ -666,6 +669,12 @@ int mag_tplus_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs,
         int solves = 0, newton_steps = 0, no_sign = 0;
         double cur = 0;
         bool cur_newton = false;
+        // Ridders: the bracket (log t, min w) at the start of a step, whether its
+        // midpoint has been evaluated (then the Ridders point is next), and what
+        // the current evaluation is (0 other, 1 midpoint, 2 Ridders point)
+        double ra = 0, rga = 0, rb = 0, rgb = 0, rgm = 0;
+        bool rid_pending = false;
+        int cur_kind = 0;
     };
     std::vector<Cloud> cl(B);
     std::vector<double> ts(B, 1.0);
@@ -728,6 +737,24 @@ int mag_tplus_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs,
                 }
                 const double slo = std::log(q.lo), shi = std::log(q.hi), mid = 0.5 * (slo + shi);
                 double sc = mid;
+                q.cur_kind = 0;
+                if (ridders) {
+                    // the same steps as mag_tplus, one evaluation per batched solve
+                    if (q.rid_pending) {
+                        const double sx = ridders_point(q.ra, q.rga, q.rb, q.rgb, q.rgm);
+                        if (sx > slo && sx < shi) {
+                            sc = sx;
+                            q.cur_kind = 2;
+                        }
+                    }
+                    if (q.cur_kind == 0) {
+                        q.ra = slo;
+                        q.rga = q.lo_min;
+                        q.rb = shi;
+                        q.rgb = q.hi_min;
+                        q.cur_kind = 1;
+                    }
+                }
                 if (newton && q.last_has_d && q.last_d != 0.0) {
                     const double sl = std::log(q.last_t);
                     const double sn = sl - q.last_min / (q.last_t * q.last_d);
@@ -744,6 +771,15 @@ int mag_tplus_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs,
                 q.prev_newton = q.cur_newton;
                 if (!q.cur_newton) q.prev_step = INFINITY;
                 tc = std::exp(sc);
+                if (q.cur_kind == 2 && !(tc > q.lo && tc < q.hi)) {
+                    // the Ridders point rounds onto a bracket end: take the midpoint
+                    q.ra = slo;
+                    q.rga = q.lo_min;
+                    q.rb = shi;
+                    q.rgb = q.hi_min;
+                    q.cur_kind = 1;
+                    tc = std::exp(mid);
+                }
                 if (!(tc > q.lo && tc < q.hi)) {
                     q.phase = 2;
                     continue;
@@ -783,6 +819,11 @@ int mag_tplus_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs,
             const double mw = mins[3 * i + 1];
             ++q.solves;
             if (q.cur_newton) ++q.newton_steps;
+            if (ridders && q.phase == 1) {
+                if (q.cur_kind == 2) ++q.newton_steps;
+                q.rid_pending = q.cur_kind == 1;
+                q.rgm = mw;
+            }
             q.last_t = q.cur;
             q.last_min = mw;
             q.last_has_d = false;

@@ -14,6 +14,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <vector>
@@ -264,6 +266,19 @@ struct HodlrFactor {
     std::vector<int64_t> bnd_host, poff, woff, csz;
     std::vector<int> k, crows, cmax;
 };
+// Ridders' point for the bracket s_a < s_b with g_a < 0 <= g_b, from g_m at the
+// midpoint: s_m + (s_m - s_a) sign(g_a - g_b) g_m / sqrt(g_m^2 - g_a g_b).  It lies
+// in [s_a, s_b] since g_m^2 - g_a g_b >= g_m^2; the midpoint when undefined.
+inline double ridders_point(double sa, double ga, double sb, double gb, double gm)
+{
+    const double sm = 0.5 * (sa + sb);
+    const double den = std::sqrt(gm * gm - ga * gb);
+    if (!(den > 0.0) || !std::isfinite(den)) return sm;
+    const double sgn = (ga - gb) < 0.0 ? -1.0 : 1.0;
+    const double sx = sm + (sm - sa) * sgn * gm / den;
+    return std::min(std::max(sx, sa), sb);
+}
+
 int hodlr_max_leaf();
 int hodlr_max_cols();
 int hodlr_levels(int64_t n, int leaf);

@@ -54,11 +54,15 @@ def test_struct_layouts_match_c(tmp_path):
         " offsetof(mag_opts, inner_prec), offsetof(mag_info, argmin_w), offsetof(mag_info, n_update));\n"
         'printf("%zu %zu %zu %zu %zu\\n", sizeof(mag_eig_opts), sizeof(mag_eig_info), offsetof(mag_eig_opts, rtol),'
         " offsetof(mag_eig_info, iters_max), offsetof(mag_eig_info, solve_steps));\n"
+        'printf("%zu %zu %zu\\n", sizeof(mag_tplus_opts), offsetof(mag_tplus_opts, method),'
+        " offsetof(mag_tplus_opts, lo_factor));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
-    so, si, o_tol, o_seed, o_ip, o_arg, o_nu, seo, sei, o_rt, o_im, o_ss = map(int, out)
+    so, si, o_tol, o_seed, o_ip, o_arg, o_nu, seo, sei, o_rt, o_im, o_ss, sto, o_me, o_lf = map(int, out)
+    assert sto == ctypes.sizeof(L.MagTplusOpts) and o_me == L.MagTplusOpts.method.offset
+    assert o_lf == L.MagTplusOpts.lo_factor.offset
     assert seo == ctypes.sizeof(L.MagEigOpts) and sei == ctypes.sizeof(L.MagEigInfo)
     assert o_rt == L.MagEigOpts.rtol.offset
     assert o_im == L.MagEigInfo.iters_max.offset and o_ss == L.MagEigInfo.solve_steps.offset
@@ -89,6 +93,9 @@ def test_host_only_entry_points():
     assert lib.mag_weighting(None, None, 10, 3, 1.0, None, None, None) == L.MAG_EINVAL
     assert lib.mag_dmin(None, None, 10, 3, None) == L.MAG_EINVAL
     assert lib.mag_set_stream(None, None) == L.MAG_EINVAL
+    to = L.MagTplusOpts()
+    lib.mag_tplus_opts_default(ctypes.byref(to))
+    assert to.method == 0 and to.newton == 1  # bisection with safeguarded Newton unless asked
     eo = L.MagEigOpts()
     lib.mag_eig_opts_default(ctypes.byref(eo))
     assert eo.max_iter == 80 and eo.rtol == 1e-8

@@ -75,6 +75,24 @@ def test_tplus_batch_vs_single_and_oracle(mag):
         print(b, len(Xb), tps[b], infos[b]["solves"], infos[b]["newton_steps"])
 
 
+def test_tplus_batch_ridders_vs_single(mag):
+    clouds = W.mixture_clouds(B=5, m=3, seed=12, n_lo=300, n_hi=800)
+    clouds.append(W.centre_kgon(12, m=3))
+    X, offs = W.pack_clouds(clouds)
+    tps, w, infos = mag.tplus_batch(dev(X), offs, want_w=True, method="ridders")
+    w = w.cpu().numpy()
+    for b, Xb in enumerate(clouds):
+        single = mag.tplus(dev(Xb), method="ridders")
+        assert infos[b]["no_sign_change"] == 0
+        # the same rules, one evaluation per batched solve (the batched products sum in
+        # another order, so a decision next to the root can differ)
+        assert abs(tps[b] - single.t_plus) / single.t_plus <= 2.5e-6
+        wb = w[offs[b]:offs[b + 1]]
+        assert wb.min() >= 0
+        assert np.abs(oracle.residual(Xb, tps[b], wb)).max() <= 1e-12
+        print(b, len(Xb), tps[b], single.t_plus, infos[b]["solves"], single.info["solves"])
+
+
 def test_tplus_batch_no_sign_change_items(mag):
     rng = np.random.default_rng(4)
     s_pos = np.linspace(0.0, 1.0, 200) + rng.random(200) * (0.1 / 200)

@@ -26,10 +26,10 @@ def kgon_root(k):
 # ------------------------------------------------------------------ t_+
 
 @pytest.mark.parametrize("k", [6, 8, 12, 24])
-@pytest.mark.parametrize("newton", [True, False])
-def test_tplus_kgon_closed_form(mag, k, newton):
+@pytest.mark.parametrize("newton,method", [(True, "bisection"), (False, "bisection"), (False, "ridders")])
+def test_tplus_kgon_closed_form(mag, k, newton, method):
     root = kgon_root(k)
-    r = mag.tplus(dev(W.centre_kgon(k)), rtol=1e-7, newton=newton)
+    r = mag.tplus(dev(W.centre_kgon(k)), rtol=1e-7, newton=newton, method=method)
     assert r.info["no_sign_change"] == 0
     assert root <= r.t_plus * (1 + 1e-12)
     assert (r.t_plus - root) / root <= 2e-7, (r.t_plus, root, r.info)
@@ -54,10 +54,11 @@ def test_tplus_collinear_and_tiny(mag):
         assert r.info["no_sign_change"] == 1 and r.t_plus == 0.0
 
 
+@pytest.mark.parametrize("method", ["bisection", "ridders"])
 @pytest.mark.parametrize("n,seed", [(300, 0), (777, 1), (1100, 2)])
-def test_tplus_vs_oracle_mixture(mag, n, seed):
+def test_tplus_vs_oracle_mixture(mag, n, seed, method):
     X = W.gaussian_mixture(n, 3, seed=seed)
-    r = mag.tplus(dev(X))
+    r = mag.tplus(dev(X), method=method)
     ref = oracle.tplus(X)
     assert r.info["no_sign_change"] == 0 and not ref.no_sign_change
     # both are upper ends of brackets of relative width <= 1e-6 around the same root
@@ -76,6 +77,21 @@ def test_tplus_newton_saves_solves(mag):
     b = mag.tplus(dev(X), newton=False)
     assert abs(a.t_plus - b.t_plus) / b.t_plus <= 2.5e-6
     assert a.info["solves"] < b.info["solves"]
+
+
+def test_tplus_ridders_vs_bisection(mag):
+    # Ridders' interpolation (no derivative) against plain bisection: the same
+    # cutoff, in fewer solves on a smooth min w(t)
+    for seed in (7, 9):
+        X = W.gaussian_mixture(600, 3, seed=seed)
+        a = mag.tplus(dev(X), method="ridders")
+        b = mag.tplus(dev(X), newton=False)
+        print(seed, a.t_plus, a.info["solves"], a.info["newton_steps"], b.t_plus, b.info["solves"])
+        assert abs(a.t_plus - b.t_plus) / b.t_plus <= 2.5e-6
+        assert a.info["newton_steps"] > 0
+        assert a.info["solves"] <= b.info["solves"]
+    with pytest.raises(ValueError):
+        mag.tplus(dev(X), method="brent")
 
 
 def test_tplus_scaling(mag):
