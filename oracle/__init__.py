@@ -20,6 +20,9 @@ magnitude"):
   * Appendix A: the cutoff computed by binary search.
   * Section 4.2: positive definiteness checked by a Cholesky attempt and an
     extreme-eigenvalue estimate.
+  * Appendix C.1, eq. scaleZero: the weighting at scale zero,
+    lim_{t -> 0} Z(t)^{-1} 1 = d^{-1} 1 / (1^T d^{-1} 1); d is indefinite, so
+    d u = 1 is solved by Gaussian elimination with partial pivoting.
 
 Readings where the paper is silent (each listed in the design notes):
   * t_+ := inf{t > 0 : w(s) >= 0 for all s >= t}; located as the largest
@@ -84,6 +87,9 @@ def lib():
                                       ctypes.c_int64, _D]
         L.orc_sum.restype = ctypes.c_double
         L.orc_sum.argtypes = [_D, ctypes.c_int64]
+        L.orc_dist_residual.argtypes = [_D, ctypes.c_int64, ctypes.c_int, _D, _I64, ctypes.c_int64, _D]
+        L.orc_dist_solve_ones.restype = ctypes.c_int
+        L.orc_dist_solve_ones.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _D, _D]
         L.orc_weighting.restype = ctypes.c_int
         L.orc_weighting.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                     _D, _D, _D]
@@ -249,6 +255,44 @@ def weighting(X, t: float, refine: int = 3) -> Weighting:
 def magnitude(X, t: float) -> float:
     """Mag = 1^T w (Section 2)."""
     return weighting(X, t).M
+
+
+# --------------------------------------------------------------------------
+# Weighting at scale zero (Appendix C.1, eq. scaleZero)
+# --------------------------------------------------------------------------
+
+def weighting_zero(X, refine: int = 2):
+    """(w0, sum_dinv): w0 = d^{-1} 1 / (1^T d^{-1} 1), the limit of the
+    weighting as t -> 0, and 1^T d^{-1} 1.  d u = 1 by LU with partial
+    pivoting and ``refine`` Dot2-residual refinement steps; the sum is
+    compensated.  One point: w0 = 1 (the limit of Z(t)^{-1} 1 = 1) and
+    sum_dinv = inf (d = 0)."""
+    X = _pts(X)
+    n, m = X.shape
+    if n == 1:
+        return np.ones(1), float("inf")
+    u = np.empty(n)
+    work = np.empty((n, n))
+    st = lib().orc_dist_solve_ones(_p(X), n, m, int(refine), _p(u), _p(work))
+    if st != 0:
+        raise NotPositiveDefinite(f"d singular (column {st - 1}): coincident points")
+    s = msum(u)
+    return u / s, s
+
+
+def dist_residual(X, u, rows=None) -> np.ndarray:
+    """r = 1 - d u (Dot2), on all rows or the given ones."""
+    X = _pts(X)
+    n, m = X.shape
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if rows is None:
+        r = np.empty(n)
+        lib().orc_dist_residual(_p(X), n, m, _p(u), None, 0, _p(r))
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        r = np.empty(len(rows))
+        lib().orc_dist_residual(_p(X), n, m, _p(u), rows.ctypes.data_as(_I64), len(rows), _p(r))
+    return r
 
 
 # --------------------------------------------------------------------------

@@ -310,3 +310,124 @@ int orc_weighting(const double *X, int64_t n, int m, double t, int refine,
     free(dw);
     return ORC_OK;
 }
+
+/* ---- weighting at scale zero (Appendix C.1, eq. scaleZero) ---------------
+ * As t -> 0, Z(t)^{-1} 1 tends to d^{-1} 1 / (1^T d^{-1} 1).  The distance
+ * matrix d is symmetric but indefinite, so the plain solver is Gaussian
+ * elimination with partial pivoting. */
+
+/* LU factorisation with row interchanges, in place: P A = L U with unit lower
+ * L (strictly below the diagonal) and U (on and above it).  A is n x n
+ * row-major; piv[j] is the row swapped with row j at step j.  Returns 0, or
+ * j+1 when column j has no nonzero pivot (A singular). */
+int orc_lu(double *A, int64_t n, int64_t *piv)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t p = j;
+        double best = fabs(A[j * n + j]);
+        for (int64_t i = j + 1; i < n; ++i) {
+            double a = fabs(A[i * n + j]);
+            if (a > best) {
+                best = a;
+                p = i;
+            }
+        }
+        piv[j] = p;
+        if (!(best > 0.0))
+            return (int)(j + 1);
+        if (p != j) {
+            for (int64_t k = 0; k < n; ++k) {
+                double tmp = A[j * n + k];
+                A[j * n + k] = A[p * n + k];
+                A[p * n + k] = tmp;
+            }
+        }
+        const double ujj = A[j * n + j];
+#pragma omp parallel for schedule(static)
+        for (int64_t i = j + 1; i < n; ++i) {
+            double l = A[i * n + j] / ujj;
+            A[i * n + j] = l;
+            for (int64_t k = j + 1; k < n; ++k)
+                A[i * n + k] = A[i * n + k] - l * A[j * n + k];
+        }
+    }
+    return ORC_OK;
+}
+
+/* Solve A x = b with the factors of orc_lu: apply the row interchanges to b,
+ * forward substitution with unit L, back substitution with U. */
+void orc_lu_solve(const double *LU, int64_t n, const int64_t *piv, const double *b, double *x)
+{
+    for (int64_t i = 0; i < n; ++i)
+        x[i] = b[i];
+    for (int64_t j = 0; j < n; ++j) {
+        if (piv[j] != j) {
+            double tmp = x[j];
+            x[j] = x[piv[j]];
+            x[piv[j]] = tmp;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double a = x[i];
+        for (int64_t k = 0; k < i; ++k)
+            a = a - LU[i * n + k] * x[k];
+        x[i] = a;
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double a = x[i];
+        for (int64_t k = i + 1; k < n; ++k)
+            a = a - LU[i * n + k] * x[k];
+        x[i] = a / LU[i * n + i];
+    }
+}
+
+/* Residual r_j = 1 - sum_k d_jk u_k by Dot2 (as orc_residual, with the
+ * distances as entries).  rows == NULL means all n rows. */
+void orc_dist_residual(const double *X, int64_t n, int m, const double *u, const int64_t *rows, int64_t nrows,
+                       double *r)
+{
+    int64_t cnt = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < cnt; ++i) {
+        int64_t j = rows ? rows[i] : i;
+        double s = 1.0, c = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            double p, ep, q;
+            two_prod(dist(X, m, j, k), -u[k], &p, &ep);
+            two_sum(s, p, &s, &q);
+            c = c + (q + ep);
+        }
+        r[i] = s + c;
+    }
+}
+
+/* u = d^{-1} 1 for n >= 2 distinct points: d from X (work, n x n row-major),
+ * LU with partial pivoting, one solve, then `refine` steps u <- u + d^{-1} r with
+ * the Dot2 residual r = 1 - d u.  Returns 0, or the failing pivot (1-based). */
+int orc_dist_solve_ones(const double *X, int64_t n, int m, int refine, double *u, double *work)
+{
+    orc_distance_matrix(X, n, m, work);
+    int64_t *piv = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int st = orc_lu(work, n, piv);
+    if (st != ORC_OK) {
+        free(piv);
+        return st;
+    }
+    double *ones = (double *)malloc((size_t)n * sizeof(double));
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *du = (double *)malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        ones[i] = 1.0;
+    orc_lu_solve(work, n, piv, ones, u);
+    for (int it = 0; it < refine; ++it) {
+        orc_dist_residual(X, n, m, u, NULL, 0, r);
+        orc_lu_solve(work, n, piv, r, du);
+        for (int64_t i = 0; i < n; ++i)
+            u[i] = u[i] + du[i];
+    }
+    free(piv);
+    free(ones);
+    free(r);
+    free(du);
+    return ORC_OK;
+}

@@ -383,3 +383,72 @@ def test_grad_x_rows_matches_full():
     rows = np.array([0, 33, 69])
     got = oracle.grad_x_rows(X, t, s.w, s.w, rows)
     assert np.array_equal(got, dX[rows])
+
+
+# ---------------------------------------------------------------- scale zero (eq. scaleZero)
+
+def test_scale_zero_tiny_cases():
+    w0, s = oracle.weighting_zero(np.array([[0.5, -1.0]]))
+    assert w0.tolist() == [1.0] and s == float("inf")
+    # two points at distance D: d^{-1} 1 = (1/D, 1/D)
+    X = np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 2.0]])
+    w0, s = oracle.weighting_zero(X)
+    assert np.allclose(w0, [0.5, 0.5], rtol=0, atol=1e-15) and s == pytest.approx(2.0 / 3.0, rel=1e-15)
+
+
+@pytest.mark.parametrize("n,m", [(7, 1), (40, 3), (150, 2)])
+def test_scale_zero_collinear_closed_form(n, m):
+    # on a line, d w = c 1 holds for w = (e_first + e_last) / 2 with c = L / 2, since
+    # d_j,first + d_j,last = L for every point j between the ends
+    X = W.collinear(n, m, seed=n)
+    proj = X @ (X[1] - X[0])
+    lo, hi = int(np.argmin(proj)), int(np.argmax(proj))
+    L = float(np.linalg.norm(X[hi] - X[lo]))
+    w0, s = oracle.weighting_zero(X)
+    ref = np.zeros(n)
+    ref[lo] = ref[hi] = 0.5
+    assert np.abs(w0 - ref).max() <= 1e-10
+    assert s == pytest.approx(2.0 / L, rel=1e-10)
+
+
+@pytest.mark.parametrize("k", [5, 12, 31])
+def test_scale_zero_polygon_closed_form(k):
+    # regular k-gon: every row of d sums to sum_l 2 sin(pi l / k), so d^{-1} 1 is uniform
+    X = W.regular_polygon(k, m=3)
+    r = sum(2.0 * np.sin(np.pi * l / k) for l in range(1, k))
+    w0, s = oracle.weighting_zero(X)
+    assert np.abs(w0 - 1.0 / k).max() <= 1e-14
+    assert s == pytest.approx(k / r, rel=1e-13)
+
+
+@pytest.mark.parametrize("n,m,seed", [(60, 2, 0), (300, 3, 1), (500, 8, 2)])
+def test_scale_zero_vs_lapack_and_limit(n, m, seed):
+    X = W.gaussian(n, m, seed=seed)
+    w0, s = oracle.weighting_zero(X)
+    D = scipy.spatial.distance.cdist(X, X)
+    u = scipy.linalg.solve(D, np.ones(n))
+    assert np.abs(w0 - u / u.sum()).max() <= 1e-9 * np.abs(w0).max()
+    assert s == pytest.approx(u.sum(), rel=1e-9)
+    # the limit of the finite-scale weighting, with O(t) error
+    e1 = np.abs(oracle.weighting(X, 1e-3).w - w0).max()
+    e2 = np.abs(oracle.weighting(X, 1e-4).w - w0).max()
+    assert e2 < e1 / 5
+    # scale invariance of w0; 1^T d^{-1} 1 scales as 1/lambda; permutation equivariance
+    w0s, ss = oracle.weighting_zero(2.5 * X)
+    assert np.abs(w0s - w0).max() <= 1e-12 * np.abs(w0).max() and ss == pytest.approx(s / 2.5, rel=1e-12)
+    perm = np.random.default_rng(seed).permutation(n)
+    w0p, _ = oracle.weighting_zero(X[perm])
+    assert np.abs(w0p - w0[perm]).max() <= 1e-12 * np.abs(w0).max()
+
+
+def test_scale_zero_dist_residual_exact_rational():
+    # Dot2 residual against exact rationals on a tiny set with integer distances
+    X = np.array([[0.0, 0.0], [3.0, 4.0], [6.0, 8.0], [0.0, 5.0]])
+    u = np.array([0.1, -0.7, 1.0 / 3.0, 2.5])
+    D = [[Fraction(0)] * 4 for _ in range(4)]
+    for j in range(4):
+        for k in range(4):
+            dd = float(np.sqrt(((X[j] - X[k]) ** 2).sum()))
+            D[j][k] = Fraction(dd)
+    exact = [float(1 - sum(D[j][k] * Fraction(u[k]) for k in range(4))) for j in range(4)]
+    assert oracle.dist_residual(X, u).tolist() == exact
