@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--check-rows", type=int, default=512)
     ap.add_argument("--eig-steps", type=int, default=1,
                     help="timed runs of the extreme-eigenvalue estimator on the same workload (0: skip)")
+    ap.add_argument("--zero-steps", type=int, default=3,
+                    help="timed solves of the scale-zero weighting of the same cloud (0: skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB before the solves, so a "
                          "hardware-counter run can scale FETCH_SIZE / WRITE_SIZE by a kernel "
@@ -184,6 +186,26 @@ def main():
         eig["ms"] = (e1 - e0) * 1e3 / args.eig_steps
         print(f"[bench] eig_extremes {eig['ms']:.2f} ms", file=sys.stderr, flush=True)
 
+    # the weighting at scale zero of the same cloud (d w = 1 through c 1 1^T - d)
+    zero = None
+    if args.zero_steps > 0:
+        wz = torch.empty(n, dtype=torch.float64, device=dev)
+        mag.weighting_zero(Xd, ctx=ctx, out=wz)
+        torch.cuda.synchronize()
+        z0 = time.perf_counter()
+        zr = None
+        for _ in range(args.zero_steps):
+            zr = mag.weighting_zero(Xd, ctx=ctx, out=wz)
+        torch.cuda.synchronize()
+        z1 = time.perf_counter()
+        zrows = rows[:128]
+        zres = oracle.dist_residual(X, wz.cpu().numpy() * zr.info["sum_dinv"], zrows)
+        zero = {"ms_per_solve": (z1 - z0) * 1e3 / args.zero_steps,
+                "outer_iters": zr.info["outer_iters"], "gmres_iters": zr.info["gmres_iters"],
+                "c": zr.info["c"], "sum_dinv": zr.info["sum_dinv"], "min_w": zr.info["min_w"],
+                "resid_rel_sampled_oracle": float(np.abs(zres).max()), "sampled_rows": int(len(zrows))}
+        print(f"[bench] weighting_zero {zero['ms_per_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu:
         ns = args.cpu_sample_n
@@ -238,6 +260,7 @@ def main():
         "fp64_dense": dense,
         "speedup_vs_fp64_dense": (dense["ms_per_solve"] / ms_per_step) if dense and "ms_per_solve" in dense else None,
         "eig_extremes": eig,
+        "weighting_zero": zero,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -193,6 +193,28 @@ int mag_tplus(mag_ctx *ctx, const double *X, int64_t n, int32_t m, const mag_tpl
 int mag_dwdt(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, double *w,
              double *dwdt, const mag_opts *opts);
 
+/* ---- weighting at scale zero -------------------------------------------------
+ * Appendix C.1 (eq. scaleZero): as t -> 0, Z(t)^{-1} 1 tends to
+ *   w0 = d^{-1} 1 / (1^T d^{-1} 1),
+ * the solution of d w = 1 scaled to sum 1.  d is indefinite (one positive
+ * eigenvalue; -d is positive definite on the complement of 1), so the solve
+ * works on B = c 1 1^T - d.  For every c that keeps B nonsingular, B^{-1} 1 =
+ * d^{-1} 1 / (c 1^T d^{-1} 1 - 1) (Sherman-Morrison), hence w0 = B^{-1} 1 / (1^T
+ * B^{-1} 1) and 1^T d^{-1} 1 = beta / (c beta - 1) with beta = 1^T B^{-1} 1; B is
+ * positive definite once c exceeds 1 / (1^T d^{-1} 1).  c starts at twice the
+ * largest distance from the centroid (at least the diameter) and is doubled
+ * once if the FP32 factor meets a non-positive pivot; the factor's diagonal
+ * shift then takes over.  The solve is the FP32_IR path with B in the place of
+ * Z (FP32 MFMA Cholesky of B, FP64 refinement with matrix-free products of B,
+ * entries c - d_jk).  X: device n x m, distinct points, m <= 16; w: device n.
+ * n = 1 gives w0 = 1 (the limit) and 1^T d^{-1} 1 = +inf.  info (may be NULL):
+ * iterations, resid_inf = ||1 - B u||_inf of the unscaled solve u, magnitude =
+ * the sum of w0, min_w and argmin_w of w0, shifted/shift of the factor.
+ * sum_dinv (HOST, may be NULL) receives 1^T d^{-1} 1; c_used (HOST, may be
+ * NULL) the c of the solve. */
+int mag_weighting_zero(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double *w,
+                       const mag_opts *opts, mag_info *info, double *sum_dinv, double *c_used);
+
 /* ---- extreme eigenvalues of Z (positive-definiteness check) ---------------
  * Section 4.2 checks that Z is positive definite, at little cost beside the
  * solve, by estimating its smallest eigenvalue with symmetric Lanczos.  Here:

@@ -22,7 +22,7 @@ from ._lib import MagError, MagInfo, MagOpts, MagTplusInfo, MagTplusOpts  # noqa
 __all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "tile32",
            "factor32", "prec_apply", "padded_size", "tplus", "dwdt", "dzmatvec",
            "MagnitudeFn", "weighting_and_magnitude", "weighting_batch", "tplus_batch",
-           "eig_extremes", "MagError", "SOLVERS"]
+           "eig_extremes", "weighting_zero", "MagError", "SOLVERS"]
 
 SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
            "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR}
@@ -143,6 +143,27 @@ def weighting(X: torch.Tensor, t: float, *, ctx: Context | None = None, out: tor
     if rc != _lib.MAG_OK and not (rc == _lib.MAG_ENOCONV and not raise_on_noconv):
         raise MagError(rc, "mag_weighting")
     return Result(w, info.as_dict())
+
+
+def weighting_zero(X: torch.Tensor, *, ctx: Context | None = None, out: torch.Tensor | None = None,
+                   raise_on_noconv: bool = True, **opts) -> Result:
+    """Weighting at scale zero (eq. scaleZero): w0 = d^{-1} 1 / (1^T d^{-1} 1),
+    the limit of w as t -> 0, from the positive definite c 1 1^T - d.  info also
+    holds sum_dinv = 1^T d^{-1} 1 and c."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    w = out if out is not None else torch.empty(n, dtype=torch.float64, device=X.device)
+    o = make_opts(**opts)
+    info = MagInfo()
+    sd, cu = ctypes.c_double(), ctypes.c_double()
+    rc = c.lib.mag_weighting_zero(c.handle, _ptr(X), n, m, _ptr(w), ctypes.byref(o), ctypes.byref(info),
+                                  ctypes.byref(sd), ctypes.byref(cu))
+    if rc != _lib.MAG_OK and not (rc == _lib.MAG_ENOCONV and not raise_on_noconv):
+        raise MagError(rc, "mag_weighting_zero")
+    d = info.as_dict()
+    d["sum_dinv"], d["c"], d["status"] = sd.value, cu.value, rc
+    return Result(w, d)
 
 
 def magnitude(X: torch.Tensor, t: float, *, ctx: Context | None = None, **opts) -> float:

@@ -159,6 +159,8 @@ SIGNATURES = {
                                  ctypes.POINTER(_d), _vp, ctypes.POINTER(MagTplusInfo)]),
     "mag_dwdt": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp, ctypes.POINTER(MagOpts)]),
     "mag_eig_opts_default": (None, [ctypes.POINTER(MagEigOpts)]),
+    "mag_weighting_zero": (ctypes.c_int, [_vp, _vp, _i64, _i32, _vp, ctypes.POINTER(MagOpts),
+                                          ctypes.POINTER(MagInfo), ctypes.POINTER(_d), ctypes.POINTER(_d)]),
     "mag_eig_extremes": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, ctypes.POINTER(MagEigOpts),
                                         ctypes.POINTER(MagOpts), ctypes.POINTER(MagEigInfo)]),
     "mag_weighting_fwd": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, ctypes.POINTER(_vp),

@@ -201,7 +201,7 @@ int ensure_solver(mag_ctx *ctx, int64_t n, int m, int restart)
 // Tile generation + blocked FP32 Cholesky, retried with a growing diagonal
 // shift when the FP32 factorisation meets a non-positive pivot.
 int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Factor32 &F,
-                FactorTimer *ft, Timer *tm)
+                FactorTimer *ft, Timer *tm, int kernel = kKernExp)
 {
     hipStream_t s = ctx->stream;
     int *status = (int *)ctx->ints.p + kIntStatus;
@@ -211,7 +211,7 @@ int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Facto
     for (int attempt = 0;; ++attempt) {
         launch_fill_ints(s, status, 8, 0);
         // the tile generator also flags coincident points (Z singular)
-        launch_tilegen32(s, X, n, m, t, F.A, F.npad, (float)F.shift, status);
+        launch_tilegen32(s, X, n, m, t, F.A, F.npad, (float)F.shift, status, kernel);
         if (tm && attempt == 0) tm->mark(1);
         if (ft) {
             ft->used = 0;
@@ -245,7 +245,7 @@ using PrecFn = std::function<void(const double *, double *, double *)>;
 
 int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64_t npad,
                 const PrecFn &prec, const double *b, double bnorm, double *xout, const mag_opts &o,
-                RefineStats &st)
+                RefineStats &st, int kernel = kKernExp)
 {
     hipStream_t s = ctx->stream;
     const int restart = std::max(1, o.gmres_restart);
@@ -258,7 +258,7 @@ int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64
     const double tol = (o.tol > 0 ? o.tol : 1e-12) * std::max(1.0, bnorm);
     // FP32 entries in the inner products: the correction equation is then solved
     // for an operator within ~1e-7 of Z, so asking GMRES for more than 1e-6 is wasted
-    const bool f32_inner = o.inner_prec == MAG_INNER_FP32 && m <= 16;
+    const bool f32_inner = o.inner_prec == MAG_INNER_FP32 && m <= 16 && kernel == kKernExp;
     const double inner_tol = std::max(o.inner_tol > 0 ? o.inner_tol : 1e-10, f32_inner ? 1e-6 : 0.0);
     const int max_gmres = o.max_gmres > 0 ? o.max_gmres : 200;
 
@@ -287,7 +287,7 @@ int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64
     // iteration restarts from the best iterate with GMRES corrections.
     bool plain = true, last_plain = false;
     auto residual = [&]() -> int {
-        launch_zmv(s, X, n, m, t, v.x, v.r, bb, 1, partial, v.dsc);
+        launch_zmv(s, X, n, m, t, v.x, v.r, bb, 1, partial, v.dsc, false, kernel);
         HIPCHK(hipMemcpyAsync(hs, v.dsc, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(hs + 8, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -342,7 +342,7 @@ int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64
         for (int k = 0; k < restart && inner_total < max_gmres; ++k) {
             double *Vk = v.V + (size_t)k * npad;
             double *Vk1 = v.V + (size_t)(k + 1) * npad;
-            launch_zmv(s, X, n, m, t, Vk, v.u, nullptr, 0, partial, nullptr, f32_inner);
+            launch_zmv(s, X, n, m, t, Vk, v.u, nullptr, 0, partial, nullptr, f32_inner, kernel);
             prec(v.u, Vk1, v.ytmp);
             // classical Gram-Schmidt, twice
             launch_multidot(s, v.V, npad, k + 1, Vk1, npad, partial, v.hdev);
@@ -393,7 +393,8 @@ int refine_core(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int64
 
 // GMRES-IR with the FP32 Cholesky factor F as the preconditioner (L L^T)^{-1}.
 int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const Factor32 &F,
-                 const double *b, double bnorm, double *xout, const mag_opts &o, RefineStats &st)
+                 const double *b, double bnorm, double *xout, const mag_opts &o, RefineStats &st,
+                 int kernel = kKernExp)
 {
     int *ints = (int *)ctx->ints.p;
     int *status = ints + kIntStatus;
@@ -402,7 +403,7 @@ int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, cons
     const PrecFn prec = [&](const double *in, double *out, double *tmp) {
         launch_prec_apply(s, F.A, F.npad, F.dinv, in, tmp, out, counters, status);
     };
-    return refine_core(ctx, X, n, m, t, F.npad, prec, b, bnorm, xout, o, st);
+    return refine_core(ctx, X, n, m, t, F.npad, prec, b, bnorm, xout, o, st, kernel);
 }
 
 // sum, min, argmin of w[0..n) -> host
@@ -1437,6 +1438,87 @@ int mag_dwdt(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, double
     HIPCHK(hipMemcpyAsync(dwdt, d, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return MAG_OK;
+}
+
+// ---- weighting at scale zero (Appendix C.1, eq. scaleZero) ---------------------
+
+int mag_weighting_zero(mag_ctx *c, const double *X, int64_t n, int32_t m, double *w, const mag_opts *opts,
+                       mag_info *info, double *sum_dinv, double *c_used)
+{
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (!c || !X || !w || n < 1 || m < 1 || m > 16) return MAG_EINVAL;
+    mag_opts o;
+    if (opts) o = *opts;
+    else mag_opts_default(&o);
+    if (o.solver != MAG_AUTO && o.solver != MAG_FP32_IR) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    const int restart = std::max(1, o.gmres_restart);
+    CHK(ensure_solver(c, n, m, restart));
+    CHK(check_points(c, X, n, m, false));
+    hipStream_t s = c->stream;
+    if (n == 1) {
+        launch_fill(s, w, 1, 1.0);
+        HIPCHK(hipStreamSynchronize(s));
+        if (info) {
+            info->magnitude = 1.0;
+            info->min_w = 1.0;
+        }
+        if (sum_dinv) *sum_dinv = INFINITY;
+        if (c_used) *c_used = 0.0;
+        return MAG_OK;
+    }
+    if (o.solver == MAG_AUTO && !auto_dense(c, n)) return MAG_ENOMEM;
+    // c: twice the largest distance from the centroid, an upper bound of the diameter
+    std::vector<double> hx((size_t)n * m);
+    HIPCHK(hipMemcpyAsync(hx.data(), X, sizeof(double) * hx.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> cen(m, 0.0);
+    for (int64_t j = 0; j < n; ++j)
+        for (int l = 0; l < m; ++l) cen[l] += hx[(size_t)j * m + l];
+    for (int l = 0; l < m; ++l) cen[l] /= (double)n;
+    double rad2 = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        double q = 0.0;
+        for (int l = 0; l < m; ++l) {
+            const double e = hx[(size_t)j * m + l] - cen[l];
+            q += e * e;
+        }
+        rad2 = std::max(rad2, q);
+    }
+    double cs = 2.0 * std::sqrt(rad2);
+    if (!(cs > 0.0) || !std::isfinite(cs)) return MAG_ENOTPD;  // every point coincides
+    CHK(ensure_ctx_factor(c, n));
+    Factor32 F = ctx_factor(c, n);
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        CHK(factor_fp32(c, X, n, m, cs, F, nullptr, nullptr, kKernShiftDist));
+        if (!F.shifted || attempt == 1) break;
+        cs *= 2.0;  // c may be below 1 / (1^T d^{-1} 1): B indefinite
+    }
+    Vecs v;
+    CHK(carve_vecs(c, F.npad, restart, v));
+    RefineStats st;
+    const int rc = refine_solve(c, X, n, m, cs, F, nullptr, 1.0, v.best, o, st, kKernShiftDist);
+    if (rc != MAG_OK && rc != MAG_ENOCONV) return rc;
+    double beta, mn;
+    int64_t am;
+    CHK(summarize(c, v.best, n, beta, mn, am));
+    if (!(beta != 0.0) || !std::isfinite(beta)) return MAG_EINTERNAL;
+    launch_scale(s, v.best, 1.0 / beta, w, n, n);
+    double sw;
+    CHK(summarize(c, w, n, sw, mn, am));
+    if (info) {
+        info->outer_iters = st.outer;
+        info->gmres_iters = st.inner;
+        info->shifted = F.shifted;
+        info->shift = F.shift;
+        info->resid_inf = st.resid;
+        info->magnitude = sw;
+        info->min_w = mn;
+        info->argmin_w = am;
+    }
+    if (sum_dinv) *sum_dinv = beta / (cs * beta - 1.0);
+    if (c_used) *c_used = cs;
+    return rc;
 }
 
 // ---- extreme eigenvalues (Section 4.2 positive-definiteness check) -----------

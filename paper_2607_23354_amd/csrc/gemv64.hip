@@ -93,6 +93,7 @@ __device__ __forceinline__ void zmv_partial_body(const double *__restrict__ X, i
 }
 
 constexpr int TS = 128;       // symmetric tile edge
+constexpr int kEntExp = 0, kEntExp32 = 1, kEntShiftDist = 2;
 constexpr int MMAX_SYM = 16;  // largest dimension of the symmetric product
 
 // Lower tile index -> (I, J), J <= I, idx = I (I + 1) / 2 + J.
@@ -110,7 +111,10 @@ __device__ inline void tri_tile(int64_t idx, int64_t &I, int64_t &J)
 // sum_c Z(r0 + p, c) v_c over the tile's columns; part[tile * 2 TS + TS + p]:
 // column sums sum_r Z(r, c0 + p) v_r (off-diagonal tiles only; a diagonal
 // tile is summed over its full square as rows).  M > 0: compile-time m.
-template <int M, bool F32 = false>
+// ENT: the entry, kEntExp exp(-t d) in FP64, kEntExp32 the same in FP32 (sums in
+// FP64), kEntShiftDist t - d in FP64 (t carries the shift c of the scale-zero
+// system, diagonal c).
+template <int M, int ENT = kEntExp>
 __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64_t n, int m_rt, double t,
                                              const double *__restrict__ v, double *__restrict__ part,
                                              int64_t tile)
@@ -171,8 +175,9 @@ __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64
             }
             double z;
             if (r >= nr || c >= nc) z = 0.0;
-            else if (diag && r == c) z = 1.0;
-            else if (F32) z = (double)expf(-((float)t * sqrtf((float)s)));  // entry in FP32, sums in FP64
+            else if (diag && r == c) z = (ENT == kEntShiftDist) ? t : 1.0;
+            else if (ENT == kEntExp32) z = (double)expf(-((float)t * sqrtf((float)s)));  // entry in FP32, sums in FP64
+            else if (ENT == kEntShiftDist) z = t - sqrt(s);
             else z = exp(-(t * sqrt(s)));
             rowacc[ii] = fma(z, vcj, rowacc[ii]);
             colacc = fma(z, vr[r], colacc);
@@ -215,12 +220,12 @@ __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64
 // Block I of y (rows r0 .. r0 + TS): sum of the row sums of tiles (I, 0..I)
 // and the column sums of tiles (I+1..T-1, I), in that order.  mode 0: y = Z v;
 // mode 1: y = b - Z v (b == NULL: ones) and blkmax[I] = max |y| over the block.
-template <int M, bool F32 = false>
+template <int M, int ENT = kEntExp>
 __global__ void __launch_bounds__(256)
 k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const double *__restrict__ v,
           double *__restrict__ part)
 {
-    zmv_sym_body<M, F32>(X, n, m_rt, t, v, part, blockIdx.x);
+    zmv_sym_body<M, ENT>(X, n, m_rt, t, v, part, blockIdx.x);
 }
 
 __device__ __forceinline__ void zmv_sym_reduce_body(const double *__restrict__ part, int64_t T, int64_t n,
@@ -500,23 +505,37 @@ static void launch_zmv_split(hipStream_t s, const double *X, int64_t n, int m, d
         hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, blkmax, rb, out_norm);
 }
 
-template <bool F32>
+template <int ENT>
 void launch_zmv_sym_tiles(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
                           double *partial, const dim3 grid)
 {
     switch (m) {
-    case 1: hipLaunchKernelGGL((k_zmv_sym<1, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 2: hipLaunchKernelGGL((k_zmv_sym<2, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 3: hipLaunchKernelGGL((k_zmv_sym<3, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 4: hipLaunchKernelGGL((k_zmv_sym<4, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    case 8: hipLaunchKernelGGL((k_zmv_sym<8, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
-    default: hipLaunchKernelGGL((k_zmv_sym<0, F32>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 1: hipLaunchKernelGGL((k_zmv_sym<1, ENT>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 2: hipLaunchKernelGGL((k_zmv_sym<2, ENT>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 3: hipLaunchKernelGGL((k_zmv_sym<3, ENT>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 4: hipLaunchKernelGGL((k_zmv_sym<4, ENT>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    case 8: hipLaunchKernelGGL((k_zmv_sym<8, ENT>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
+    default: hipLaunchKernelGGL((k_zmv_sym<0, ENT>), grid, dim3(256), 0, s, X, n, m, t, v, partial); break;
     }
 }
 
 void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
-                double *y, const double *b, int mode, double *partial, double *out_norm, bool f32_entries)
+                double *y, const double *b, int mode, double *partial, double *out_norm, bool f32_entries,
+                int kernel)
 {
+    if (kernel == kKernShiftDist) {
+        // the scale-zero system (m <= 16 only, checked by the caller)
+        const int64_t npad = (n + kPad - 1) / kPad * kPad;
+        const int64_t T = npad / TS;
+        const int64_t tiles = T * (T + 1) / 2;
+        launch_zmv_sym_tiles<kEntShiftDist>(s, X, n, m, t, v, partial, dim3((unsigned)tiles));
+        double *blkmax = partial + tiles * 2 * TS;
+        hipLaunchKernelGGL(k_zmv_sym_reduce, dim3((unsigned)T), dim3(TS), 0, s, partial, T, n, npad, y, b, mode,
+                           blkmax);
+        if (mode == 1 && out_norm)
+            hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, s, blkmax, T, out_norm);
+        return;
+    }
     if (m > MMAX_SYM) {
         launch_zmv_split(s, X, n, m, t, v, y, b, mode, partial, out_norm);
         return;
@@ -525,8 +544,8 @@ void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t, cons
     const int64_t T = npad / TS;
     const int64_t tiles = T * (T + 1) / 2;
     const dim3 grid((unsigned)tiles);
-    if (f32_entries) launch_zmv_sym_tiles<true>(s, X, n, m, t, v, partial, grid);
-    else launch_zmv_sym_tiles<false>(s, X, n, m, t, v, partial, grid);
+    if (f32_entries) launch_zmv_sym_tiles<kEntExp32>(s, X, n, m, t, v, partial, grid);
+    else launch_zmv_sym_tiles<kEntExp>(s, X, n, m, t, v, partial, grid);
     double *blkmax = partial + tiles * 2 * TS;
     hipLaunchKernelGGL(k_zmv_sym_reduce, dim3((unsigned)T), dim3(TS), 0, s, partial, T, n, npad, y, b, mode,
                        blkmax);

@@ -36,6 +36,11 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// The kernel matrix a factor or product is built from: Z = exp[-t d] (Section
+// 2), or c 1 1^T - d for the weighting at scale zero (eq. scaleZero), with c in
+// the place of t.
+constexpr int kKernExp = 0, kKernShiftDist = 1;
+
 // Status words written by kernels (device memory, zeroed per call).
 enum StatusWord : int {
     kStBreakdown = 0,    // FP32 Cholesky met a non-positive pivot (index+1)
@@ -182,9 +187,10 @@ void launch_gradx(hipStream_t s, const double *X, int64_t n, int m, double t, co
 
 // ---- launchers (all enqueue on ctx->stream) --------------------------------
 // tilegen.hip
-// status (optional): status[kStDuplicate] = 1 if some pair j != k < n has d_jk = 0
+// status (optional): status[kStDuplicate] = 1 if some pair j != k < n has d_jk = 0.
+// kernel kKernShiftDist writes t - d_jk (diagonal t + shift) instead of exp(-t d_jk).
 void launch_tilegen32(hipStream_t s, const double *X, int64_t n, int m, double t,
-                      float *A, int64_t npad, float shift, int *status = nullptr);
+                      float *A, int64_t npad, float shift, int *status = nullptr, int kernel = kKernExp);
 void launch_tilegen64(hipStream_t s, const double *X, int64_t n, int m, double t, double *A);
 // Writes min squared distance partials; returns number of partials in *np.
 void launch_dmin2(hipStream_t s, const double *X, int64_t n, int m, double *partial,
@@ -212,9 +218,11 @@ void launch_potrf128(hipStream_t s, float *A, int64_t ld, int64_t k0, float *Lin
 //   out_norm[0] = ||y||_inf (device scalar).
 //   f32_entries: each entry exp(-t d) evaluated in FP32 (sums stay FP64); the
 //   inner products of GMRES may take it, residuals never do (m <= 16 only).
+//   kernel: kKernExp the entries exp(-t d) of Z; kKernShiftDist the entries
+//   t - d of the scale-zero system c 1 1^T - d with c passed as t (m <= 16).
 void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t,
                 const double *v, double *y, const double *b, int mode,
-                double *partial, double *out_norm, bool f32_entries = false);
+                double *partial, double *out_norm, bool f32_entries = false, int kernel = kKernExp);
 size_t zmv_partial_doubles(int64_t n);
 
 // trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.

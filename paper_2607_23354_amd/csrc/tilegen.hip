@@ -77,6 +77,7 @@ __device__ inline void block_sqdist(double (&s)[kPerThread], const double *X, in
     }
 }
 
+template <int KERN = kKernExp>
 __device__ __forceinline__ void tilegen32_body(const double *__restrict__ X, int64_t n, int m,
                                                double t, float *__restrict__ A, int64_t npad,
                                                float shift, int64_t blk, int *__restrict__ status)
@@ -97,22 +98,26 @@ __device__ __forceinline__ void tilegen32_body(const double *__restrict__ X, int
         const int64_t k = col0 + 2 * c + h;
         float v;
         if (j == k)
-            v = 1.0f + shift;
+            v = ((KERN == kKernShiftDist) ? tf : 1.0f) + shift;
         else if (j >= n || k >= n)
             v = 0.0f;
         else {
             if (status && s[c] == 0.0) status[kStDuplicate] = 1;  // Z singular
-            v = expf(-(tf * sqrtf((float)s[c])));
+            if (KERN == kKernShiftDist)
+                v = (float)(t - sqrt(s[c]));  // c - d_jk, formed in FP64
+            else
+                v = expf(-(tf * sqrtf((float)s[c])));
         }
         A[k * npad + j] = v;
     }
 }
 
+template <int KERN>
 __global__ void __launch_bounds__(kThreads)
 k_tilegen32(const double *__restrict__ X, int64_t n, int m, double t, float *__restrict__ A,
             int64_t npad, float shift, int *__restrict__ status)
 {
-    tilegen32_body(X, n, m, t, A, npad, shift, blockIdx.x, status);
+    tilegen32_body<KERN>(X, n, m, t, A, npad, shift, blockIdx.x, status);
 }
 
 // Batched: one launch for every active problem of a batch.
@@ -214,10 +219,14 @@ int64_t lower_blocks(int64_t rows)
 }  // namespace
 
 void launch_tilegen32(hipStream_t s, const double *X, int64_t n, int m, double t, float *A,
-                      int64_t npad, float shift, int *status)
+                      int64_t npad, float shift, int *status, int kernel)
 {
-    hipLaunchKernelGGL(k_tilegen32, dim3((unsigned)lower_blocks(npad)), dim3(kThreads), 0, s, X, n,
-                       m, t, A, npad, shift, status);
+    if (kernel == kKernShiftDist)
+        hipLaunchKernelGGL(k_tilegen32<kKernShiftDist>, dim3((unsigned)lower_blocks(npad)), dim3(kThreads), 0, s, X,
+                           n, m, t, A, npad, shift, status);
+    else
+        hipLaunchKernelGGL(k_tilegen32<kKernExp>, dim3((unsigned)lower_blocks(npad)), dim3(kThreads), 0, s, X, n,
+                           m, t, A, npad, shift, status);
 }
 
 void launch_tilegen64(hipStream_t s, const double *X, int64_t n, int m, double t, double *A)
