@@ -63,10 +63,17 @@ enum {
                           * device memory, else MAG_HODLR                                */
     MAG_FP64_DENSE = 1,  /* FP64 Z in HBM + rocSOLVER dpotrf/dpotrs (dense comparator)   */
     MAG_FP32_IR = 2,     /* FP32 MFMA Cholesky + FP64 GMRES iterative refinement         */
-    MAG_HODLR = 3        /* HODLR preconditioner + FP64 GMRES (largest sizes, Sec. 3.2): *
+    MAG_HODLR = 3,       /* HODLR preconditioner + FP64 GMRES (largest sizes, Sec. 3.2): *
                           * points reordered by recursive coordinate bisection, leaf    *
                           * blocks exact, sibling blocks Z(I,J) ~ U_I V_J^T sampled     *
                           * with a Gaussian test matrix; m <= 16                        */
+    MAG_HSS = 4          /* HSS preconditioner with nested bases, factored by ULV, + FP64 *
+                          * GMRES (Sec. 3.2's hierarchical solver): the same tree; each *
+                          * node's basis spans its whole off-diagonal block row (one    *
+                          * Gaussian sample, projected up the tree); level l keeps      *
+                          * max_rank 2^{-l/2} + oversample columns rounded up to 64     *
+                          * (64..512, at most twice its children's); leaves of at least *
+                          * 64 points (n > leaf); m <= 16                               */
 };
 
 typedef struct {

@@ -25,7 +25,7 @@ __all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "
            "eig_extremes", "weighting_zero", "MagError", "SOLVERS"]
 
 SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
-           "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR}
+           "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR, "hss": _lib.MAG_HSS}
 
 
 def _ptr(t: torch.Tensor | None):

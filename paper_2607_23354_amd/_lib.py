@@ -24,6 +24,7 @@ MAG_AUTO = 0
 MAG_FP64_DENSE = 1
 MAG_FP32_IR = 2
 MAG_HODLR = 3
+MAG_HSS = 4
 
 
 class MagOpts(ctypes.Structure):

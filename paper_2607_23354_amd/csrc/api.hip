@@ -606,6 +606,60 @@ int solve_hodlr(mag_ctx *ctx, const double *X, int64_t n, int m, double t, doubl
     return rc;
 }
 
+// HSS preconditioner with nested bases + ULV (hodlr.hip) + FP64 GMRES-IR.
+int solve_hss(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double *w, const mag_opts &o,
+              mag_info *info)
+{
+    hipStream_t s = ctx->stream;
+    const int restart = std::max(1, o.gmres_restart);
+    const int leaf = o.leaf > 0 ? o.leaf : hodlr_max_leaf();
+    if (leaf < 2 || leaf > hodlr_max_leaf() || m > 16) return MAG_EINVAL;
+    CHK(ensure_solver(ctx, n, m, restart));
+    Timer tm;
+    tm.start(o.profile != 0, s);
+    tm.mark(0);
+    HssFactor H;
+    CHK(hss_factor(ctx, X, n, m, t, leaf, std::max(0, o.max_rank), std::max(0, o.oversample), o.seed, H));
+    if (info) {
+        info->shifted = H.shift > 0.0 ? 1 : 0;
+        info->shift = H.shift;
+    }
+    tm.mark(1);
+    tm.mark(2);
+    Vecs v;
+    CHK(carve_vecs(ctx, H.npad, restart, v));
+    int prc = MAG_OK;
+    const PrecFn prec = [&](const double *in, double *out, double *) {
+        const int e = hss_apply(s, H, in, out);
+        if (e != MAG_OK) prc = e;
+    };
+    RefineStats st;
+    int rc = refine_core(ctx, X, n, m, t, H.npad, prec, nullptr, 1.0, v.best, o, st);
+    if (prc != MAG_OK) return prc;
+    if (rc != MAG_OK && rc != MAG_ENOCONV) return rc;
+    tm.mark(3);
+    launch_copy(s, v.best, w, n);
+    double sum, mn;
+    int64_t am;
+    CHK(summarize(ctx, v.best, n, sum, mn, am));
+    tm.mark(4);
+    if (info) {
+        info->outer_iters = st.outer;
+        info->gmres_iters = st.inner;
+        info->resid_inf = st.resid;
+        info->magnitude = sum;
+        info->min_w = mn;
+        info->argmin_w = am;
+        if (o.profile) {
+            info->ms_tilegen = 0.0;
+            info->ms_factor = tm.ms(0, 1);
+            info->ms_refine = tm.ms(2, 3);
+            info->ms_total = tm.ms(0, 4);
+        }
+    }
+    return rc;
+}
+
 // MAG_AUTO: the dense FP32 factor when its npad^2 floats fit in three quarters
 // of the device memory (counting what this context already holds for it),
 // else the HODLR preconditioner.
@@ -922,7 +976,7 @@ void mag_destroy(mag_ctx *c)
     if (c->stream) hipStreamSynchronize(c->stream);
     for (DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints, &c->aux, &c->bfactor,
                       &c->bdinv, &c->bvec, &c->bscal, &c->bpartial, &c->bints, &c->bdesc, &c->barena,
-                      &c->bstage, &c->hodlr, &c->eig})
+                      &c->bstage, &c->hodlr, &c->eig, &c->hss})
         if (b->p) hipFree(b->p);
     if (c->bhost) hipHostFree(c->bhost);
     if (c->blas) rocblas_destroy_handle((rocblas_handle)c->blas);
@@ -1087,6 +1141,7 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
         switch (o.solver) {
         case MAG_FP64_DENSE: rc = solve_fp64_dense(c, X, n, m, t, w, o, info); break;
         case MAG_HODLR: rc = solve_hodlr(c, X, n, m, t, w, o, info); break;
+        case MAG_HSS: rc = solve_hss(c, X, n, m, t, w, o, info); break;
         case MAG_AUTO: rc = fp32 ? solve_fp32_ir(c, X, n, m, t, w, o, info)
                                  : solve_hodlr(c, X, n, m, t, w, o, info);
             break;

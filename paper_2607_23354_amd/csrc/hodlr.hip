@@ -949,4 +949,608 @@ void hodlr_apply(hipStream_t s, const HodlrFactor &H, const double *r, double *z
     hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(256), 0, s, H.xp, H.perm, n, H.npad, z);
 }
 
+
+// ==== HSS with nested bases and its ULV factorisation ==========================
+// The hierarchically semiseparable form behind Section 3.2's solver: on the
+// same cluster tree, every node tau below the root has a basis U_tau of the
+// off-diagonal block row Z(I_tau, rest), nested: U_tau = diag(U_a, U_b) R_tau
+// for its children a, b (so only the leaves' bases and the small R_tau are
+// stored), and sibling blocks are Z(I_a, I_b) ~ U_a B_ab U_b^T.
+//
+// Construction (randomized, projected samples).  S = (Z - leaf blocks) Omega for
+// one Gaussian Omega (n x r), summed from the sibling-pair products of every
+// level.  A leaf's basis spans the leading eigenvectors of T T^T, T = S(leaf);
+// with S~ = U^T T and O~ = U^T Omega(leaf) kept per node, a parent's sample of
+// its own off-diagonal block row, in its children's basis coordinates, is
+//   T_tau = [S~_a - B_ab O~_b ; S~_b - B_ab^T O~_a]
+// (the sibling block is removed), and R_tau spans the leading eigenvectors of
+// T_tau T_tau^T.  B_ab = U_a^T Z(I_a, I_b) U_b with the explicit bases.  The
+// full eigenvector matrix Q_tau = [Q_e | R_tau] (ascending eigenvalues) is kept:
+// it is the orthogonal transform of the ULV step.
+//
+// ULV (bottom-up).  A node's block D (the leaf block of Z, or the children's
+// Schur complements coupled by B) becomes Q^T D Q; the first e = a - k
+// unknowns touch nothing outside the node, so they are eliminated by a
+// Cholesky factor L_e, and the Schur complement of the k basis unknowns
+// D_ss - W W^T (W = D_se L_e^{-T}) is passed to the parent.  The root's block
+// is factored whole.  The apply runs the same steps on a vector: up the tree
+// b~ = Q^T b, y_e = L_e^{-1} b~_e, b^ = b~_s - W y_e; the root solve; down the
+// tree x_e = L_e^{-T} (y_e - W^T x_s), x = Q [x_e; x_s].
+namespace {
+
+// T[leaf] (ell x r, column-major) = S(rows of the leaf, :) (S: n x r row-major); zero padding rows.
+__global__ void k_hss_gather_rows(const double *__restrict__ S, int r, const int64_t *__restrict__ bndL, int ell,
+                                  int64_t leaves, double *__restrict__ T)
+{
+    const int64_t blk = (int64_t)ell * r, total = leaves * blk;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t leaf = e / blk, w = e % blk;
+        const int j = (int)(w / ell), i = (int)(w % ell);
+        const int64_t lo = bndL[leaf], hi = bndL[leaf + 1];
+        T[e] = (lo + i < hi) ? S[(lo + i) * r + j] : 0.0;
+    }
+}
+
+// U (n x k, row-major) from the last k columns of each leaf's Q (ell x ell).
+__global__ void k_hss_scatter_basis(const double *__restrict__ Q, int ell, int k, const int64_t *__restrict__ bndL,
+                                    int64_t leaves, double *__restrict__ U)
+{
+    const int64_t blk = (int64_t)ell * k, total = leaves * blk;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t leaf = e / blk, w = e % blk;
+        const int i = (int)(w / k), c = (int)(w % k);
+        const int64_t lo = bndL[leaf], hi = bndL[leaf + 1];
+        if (lo + i < hi) U[(lo + i) * k + c] = Q[leaf * (int64_t)ell * ell + (int64_t)(ell - k + c) * ell + i];
+    }
+}
+
+// Nested basis of the next level: out[p, j] = sum_i A[p, i] R_c[i, j] for the
+// rows p of child c (A: n x kc, out: n x kl, both row-major; R_c = Q-block
+// rows c%2 kc .. of the parent's last kl columns).  16 rows per workgroup.
+__global__ void __launch_bounds__(NT)
+k_hss_rowmul(const double *__restrict__ A, int kc, const double *__restrict__ Q, int a, int kl,
+             const int64_t *__restrict__ bnd, int rbmax, double *__restrict__ out)
+{
+    const int64_t c = blockIdx.x / rbmax;
+    const int rb = blockIdx.x % rbmax;
+    const int64_t lo = bnd[c], hi = bnd[c + 1];
+    const int64_t p = lo + (int64_t)rb * 16 + (threadIdx.x >> 4);
+    const int cg = threadIdx.x & 15;
+    if (p >= hi) return;
+    const double *R = Q + (c / 2) * (int64_t)a * a + (int64_t)(a - kl) * a + (c % 2) * kc;
+    const double *ar = A + p * kc;
+    for (int j = cg; j < kl; j += 16) {
+        const double *rc = R + (int64_t)j * a;
+        double acc = 0.0;
+        for (int i = 0; i < kc; ++i) acc = fma(ar[i], rc[i], acc);
+        out[p * kl + j] = acc;
+    }
+}
+
+// dst[p] (2 kc x cols, column-major) = [child 2p; child 2p+1], child c's block
+// at src + c * sstride + soff with leading dimension lds.
+__global__ void k_hss_stack(const double *__restrict__ src, int64_t sstride, int lds, int soff, int kc, int cols,
+                            int64_t parents, double *__restrict__ dst)
+{
+    const int a = 2 * kc;
+    const int64_t blk = (int64_t)a * cols, total = parents * blk;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / blk, w = e % blk;
+        const int j = (int)(w / a), i = (int)(w % a);
+        const int h = i >= kc ? 1 : 0;
+        dst[e] = src[(2 * p + h) * sstride + (int64_t)j * lds + soff + (i - h * kc)];
+    }
+}
+
+// D[leaf] (ell x ell, column-major): Z on the leaf's points (FP64, the entry of
+// the matrix-free product), identity on the padding.
+__global__ void k_hss_leaf_block(const double *__restrict__ Xp, int m, double t, const int64_t *__restrict__ bndL,
+                                 int ell, int64_t leaves, double *__restrict__ D)
+{
+    const int64_t blk = (int64_t)ell * ell, total = leaves * blk;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t leaf = e / blk, w = e % blk;
+        const int j = (int)(w / ell), i = (int)(w % ell);
+        const int64_t lo = bndL[leaf];
+        const int sz = (int)(bndL[leaf + 1] - lo);
+        double v;
+        if (i == j) {
+            v = 1.0;
+        } else if (i < sz && j < sz) {
+            double q = 0.0;
+            for (int l = 0; l < m; ++l) q = sq_acc(q, Xp[(lo + i) * m + l] - Xp[(lo + j) * m + l]);
+            v = exp(-(t * sqrt(q)));
+        } else {
+            v = 0.0;
+        }
+        D[e] = v;
+    }
+}
+
+// D[p] (2 kc x 2 kc) = [[S_a, B], [B^T, S_b]] with S_c the trailing kc x kc
+// block (rows and columns e .. e + kc) of child c's Dt (ac x ac) and B = Bc[p]
+// (kc x kc, column-major).
+__global__ void k_hss_assemble(const double *__restrict__ Dtc, int ac, int kc, const double *__restrict__ Bc,
+                               int64_t parents, double *__restrict__ D)
+{
+    const int a = 2 * kc, ec = ac - kc;
+    const int64_t blk = (int64_t)a * a, total = parents * blk;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / blk, w = e % blk;
+        const int j = (int)(w / a), i = (int)(w % a);
+        const int hi = i >= kc ? 1 : 0, hj = j >= kc ? 1 : 0;
+        const int ii = i - hi * kc, jj = j - hj * kc;
+        double v;
+        if (hi == hj) v = Dtc[(2 * p + hi) * (int64_t)ac * ac + (int64_t)(ec + jj) * ac + (ec + ii)];
+        else if (hj) v = Bc[p * (int64_t)kc * kc + (int64_t)jj * kc + ii];
+        else v = Bc[p * (int64_t)kc * kc + (int64_t)ii * kc + jj];
+        D[e] = v;
+    }
+}
+
+// xl[leaf] (ell) = r at the leaf's points (tree order through perm), zero padding.
+__global__ void k_hss_gather_vec(const double *__restrict__ r, const int64_t *__restrict__ perm,
+                                 const int64_t *__restrict__ bndL, int ell, int64_t leaves, double *__restrict__ xl)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < leaves * ell; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t leaf = e / ell;
+        const int i = (int)(e % ell);
+        const int64_t lo = bndL[leaf], hi = bndL[leaf + 1];
+        xl[e] = (lo + i < hi) ? r[perm[lo + i]] : 0.0;
+    }
+}
+
+// z[perm[p]] = x at tree position p (leaf-padded layout), zero on [n, npad).
+__global__ void k_hss_scatter_vec(const double *__restrict__ xl, const int64_t *__restrict__ perm,
+                                  const int64_t *__restrict__ bndL, int ell, int64_t leaves, int64_t n, int64_t npad,
+                                  double *__restrict__ z)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < leaves * ell; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t leaf = e / ell;
+        const int i = (int)(e % ell);
+        const int64_t lo = bndL[leaf], hi = bndL[leaf + 1];
+        if (lo + i < hi) z[perm[lo + i]] = xl[e];
+    }
+    for (int64_t e = n + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npad; e += (int64_t)gridDim.x * blockDim.x)
+        z[e] = 0.0;
+}
+
+// v[tau] (a) = [ub[tau][0 .. e); x of the parent, half tau % 2 (k entries)].
+__global__ void k_hss_down_vec(const double *__restrict__ ub, const double *__restrict__ xpar, int apar, int a, int k,
+                               int64_t count, double *__restrict__ v)
+{
+    const int e0 = a - k;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count * a; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t tau = e / a;
+        const int i = (int)(e % a);
+        v[e] = (i < e0) ? ub[e] : xpar[(tau / 2) * apar + (tau % 2) * k + (i - e0)];
+    }
+}
+
+// D[node][i][i] += sigma for i < e (the block to eliminate), every node.
+__global__ void k_hss_shift(double *__restrict__ D, int a, int e, int64_t nodes, double sigma)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nodes * e; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t node = q / e;
+        const int i = (int)(q % e);
+        D[node * (int64_t)a * a + (int64_t)i * a + i] += sigma;
+    }
+}
+
+// largest |entry| of the diagonal of each node's first e x e block, into out[0]
+__global__ void k_hss_diagmax(const double *__restrict__ D, int a, int e, int64_t nodes, double *__restrict__ out)
+{
+    __shared__ double red[NT];
+    double v = 0.0;
+    for (int64_t q = threadIdx.x; q < nodes * e; q += NT) {
+        const int64_t node = q / e;
+        const int i = (int)(q % e);
+        v = fmax(v, fabs(D[node * (int64_t)a * a + (int64_t)i * a + i]));
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+inline unsigned hss_grid(int64_t total)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + NT - 1) / NT, 4096));
+}
+
+}  // namespace
+
+#define HSSCHK(x)                                                                                  \
+    do {                                                                                           \
+        const int rc_ = (x);                                                                       \
+        if (rc_ != MAG_OK) return rc_;                                                             \
+    } while (0)
+
+int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int leaf, int rank0, int oversample,
+               uint64_t seed, HssFactor &H)
+{
+    hipStream_t s = ctx->stream;
+    if (m > MMAXH || leaf < 2 || leaf > LMAX || rank0 < 0 || oversample < 0 || n < 2) return MAG_EINVAL;
+    const int L = hodlr_levels(n, leaf);
+    const int64_t npad = round_up(n, kPad);
+    rocblas_handle bh = nullptr;
+    if (blas_handle(ctx, bh) != MAG_OK) return MAG_EHIP;
+
+    std::vector<double> Xh((size_t)n * m);
+    if (hipMemcpyAsync(Xh.data(), X, sizeof(double) * n * m, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return MAG_EHIP;
+    std::vector<int64_t> perm, bnd;
+    build_tree(Xh, n, m, L, perm, bnd);
+    const int64_t leaves = (int64_t)1 << L;
+    int64_t minleaf = INT64_MAX, maxleaf = 0;
+    for (int64_t i = 0; i < leaves; ++i) {
+        const int64_t sz = bnd[boff(L) + i + 1] - bnd[boff(L) + i];
+        minleaf = std::min(minleaf, sz);
+        maxleaf = std::max(maxleaf, sz);
+    }
+    if (maxleaf > LMAX || minleaf < 1) return MAG_EINTERNAL;
+    // bases are stored in 64-column slabs: every leaf needs at least 64 points
+    if (L > 0 && minleaf < SL) return MAG_EINVAL;
+    std::vector<double> Xp((size_t)n * m);
+    for (int64_t i = 0; i < n; ++i)
+        for (int l = 0; l < m; ++l) Xp[i * m + l] = Xh[perm[i] * m + l];
+
+    // ranks: level l >= 1 keeps k[l] columns, a multiple of 64 within [64, 512]
+    // from rank0 2^{-l/2} + oversample, at most its active size a[l] (at the
+    // leaves, the smallest leaf, so no basis vector lives on padding)
+    const int ell = (int)maxleaf;
+    std::vector<int> k(L + 1, 0), a(L + 1, 0);
+    auto cap = [&](int l) {
+        const double want = rank0 * std::pow(2.0, -0.5 * l) + oversample;
+        return SL * std::max(1, std::min((int)std::ceil(want / SL), KMAXC));
+    };
+    if (L == 0) {
+        a[0] = ell;
+    } else {
+        a[L] = ell;
+        k[L] = std::min<int>(cap(L), (int)(minleaf / SL) * SL);
+        for (int l = L - 1; l >= 1; --l) {
+            a[l] = 2 * k[l + 1];
+            k[l] = std::min(a[l], cap(l));
+        }
+        a[0] = 2 * k[1];
+    }
+    int kmax = SL;
+    for (int l = 1; l <= L; ++l) kmax = std::max(kmax, k[l]);
+    const int r = std::min(KMAXC * SL, ((kmax + oversample + SL - 1) / SL) * SL);
+    std::vector<int64_t> off(L + 2, 0), voff(L + 2, 0);
+    for (int l = 1; l <= L; ++l) {
+        off[l + 1] = off[l] + ((int64_t)1 << l) * a[l] * a[l];
+        voff[l + 1] = voff[l] + ((int64_t)1 << l) * a[l];
+    }
+    const int64_t qtot = off[L + 1], vtot = voff[L + 1];
+    // per-level buffer needs; gram chunking per level (children of level l)
+    int64_t maxT = 1, maxQ = 1, maxSt = 1, maxB = 1, maxEig = 1, gpart = 1, amax = std::max(1, a[0]);
+    std::vector<int> crows(L + 1, 256), cmx(L + 1, 1), rbl(L + 1, 1), rb16(L + 1, 1);
+    for (int l = 1; l <= L; ++l) {
+        const int64_t nodes = (int64_t)1 << l;
+        maxT = std::max(maxT, nodes * a[l] * r);
+        maxQ = std::max(maxQ, nodes * a[l] * a[l]);
+        maxSt = std::max(maxSt, nodes * k[l] * r);
+        maxB = std::max(maxB, (nodes / 2) * (int64_t)k[l] * k[l]);
+        maxEig = std::max(maxEig, 2 * nodes * a[l]);
+        amax = std::max(amax, (int64_t)a[l]);
+        int64_t csz = 0;
+        for (int64_t c = 0; c < nodes; ++c) csz = std::max(csz, bnd[boff(l) + c + 1] - bnd[boff(l) + c]);
+        crows[l] = (int)std::max<int64_t>(256, cdiv(cdiv(csz, 64), 32) * 32);
+        cmx[l] = (int)cdiv(csz, crows[l]);
+        rbl[l] = (int)cdiv(csz, 64);
+        rb16[l] = (int)cdiv(csz, 16);
+        gpart = std::max(gpart, (nodes / 2) * cmx[l] * (int64_t)(k[l] / SL) * (k[l] / SL) * SL * SL);
+    }
+    maxEig = std::max(maxEig, 2 * amax);
+    maxQ = std::max(maxQ, amax * amax);  // the root block passes through Dn too
+
+    // device workspace (doubles, then int64, then int)
+    const size_t nd = (size_t)n * m + 3 * (size_t)n * r + 3 * (size_t)n * kmax + 2 * (size_t)qtot +
+                      (size_t)amax * amax + (size_t)maxT + 2 * (size_t)maxQ + 4 * (size_t)maxSt +
+                      (size_t)(L + 1) * maxB + (size_t)gpart + 2 * (size_t)vtot + (size_t)leaves * ell +
+                      2 * (size_t)amax + (size_t)maxEig + 256;
+    const size_t nint = (size_t)n + bnd.size() + 16;
+    const size_t nsmall = (size_t)std::max<int64_t>(leaves, 2) + 64;
+    if (ensure(ctx, ctx->hss, sizeof(double) * nd + sizeof(int64_t) * nint + sizeof(int) * nsmall + 4096) != MAG_OK)
+        return MAG_ENOMEM;
+    double *p = (double *)ctx->hss.p;
+    H.Xp = p; p += (size_t)n * m;
+    double *Om = p; p += (size_t)n * r;
+    double *S = p; p += (size_t)n * r;
+    double *Tmp = p; p += (size_t)n * r;
+    double *Ucur = p; p += (size_t)n * kmax;
+    double *Unext = p; p += (size_t)n * kmax;
+    double *Wz = p; p += (size_t)n * kmax;
+    H.Q = p; p += qtot;
+    H.Dt = p; p += qtot;
+    H.Droot = p; p += (size_t)amax * amax;
+    double *T = p; p += maxT;
+    double *Dn = p; p += maxQ;
+    double *T2 = p; p += maxQ;
+    double *St[2] = {p, p + maxSt}; p += 2 * maxSt;
+    double *Ot[2] = {p, p + maxSt}; p += 2 * maxSt;
+    std::vector<double *> Bc(L + 1, nullptr);
+    for (int l = 0; l <= L; ++l) { Bc[l] = p; p += maxB; }
+    double *gp = p; p += gpart;
+    H.ub = p; p += vtot;
+    H.xb = p; p += vtot;
+    H.xl = p; p += (size_t)leaves * ell;
+    H.rr = p; p += 2 * (size_t)amax;
+    double *eigw = p; p += maxEig;
+    p += 256;
+    int64_t *ip = (int64_t *)p;
+    H.perm = ip; ip += n;
+    H.bnd = ip; ip += bnd.size();
+    int *info = (int *)(ip + 8);
+    H.n = n; H.npad = npad; H.m = m; H.L = L; H.ell = ell; H.t = t;
+    H.k = k; H.a = a; H.off = off; H.voff = voff; H.blas = bh;
+
+    if (hipMemcpyAsync(H.Xp, Xp.data(), sizeof(double) * n * m, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(H.perm, perm.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(H.bnd, bnd.data(), sizeof(int64_t) * bnd.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return MAG_EHIP;
+    const int64_t *bL = H.bnd + boff(L);
+    const double one = 1.0, mone = -1.0, zero = 0.0;
+    auto check_info = [&](int count) -> int {
+        std::vector<int> hi(count);
+        if (hipMemcpyAsync(hi.data(), info, sizeof(int) * count, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return MAG_EHIP;
+        for (int v : hi)
+            if (v != 0) return MAG_ENOTPD;
+        return MAG_OK;
+    };
+    // Cholesky of each node's leading e x e block of D (ld a), retaken from the
+    // copy in `src` with a growing diagonal shift when the compressed block is
+    // not positive definite (it approximates a Schur complement of Z; the shift
+    // only changes the preconditioner, GMRES keeps the exact products)
+    H.shift = 0.0;
+    auto potrf_shifted = [&](double *D, const double *src, int a, int e, int64_t nodes) -> int {
+        for (int attempt = 0;; ++attempt) {
+            RBCHK(rocsolver_dpotrf_strided_batched(bh, rocblas_fill_lower, e, D, a, (rocblas_stride)a * a, info,
+                                                   (rocblas_int)nodes));
+            const int rc = check_info((int)nodes);
+            if (rc != MAG_ENOTPD) return rc;
+            if (attempt >= 8) return MAG_ENOTPD;
+            if (hipMemcpyAsync(D, src, sizeof(double) * nodes * a * a, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return MAG_EHIP;
+            double *dmax = eigw;
+            hipLaunchKernelGGL(k_hss_diagmax, dim3(1), dim3(NT), 0, s, D, a, e, nodes, dmax);
+            double hmax = 0.0;
+            if (hipMemcpyAsync(&hmax, dmax, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return MAG_EHIP;
+            const double sigma = hmax * std::pow(10.0, -8.0 + attempt);
+            hipLaunchKernelGGL(k_hss_shift, dim3(hss_grid(nodes * (int64_t)e)), dim3(NT), 0, s, D, a, e, nodes, sigma);
+            H.shift = std::max(H.shift, sigma);
+        }
+    };
+
+    if (L == 0) {
+        // one leaf: the root block is Z itself
+        hipLaunchKernelGGL(k_hss_leaf_block, dim3(hss_grid((int64_t)ell * ell)), dim3(NT), 0, s, H.Xp, m, t, bL, ell,
+                           (int64_t)1, H.Droot);
+        RBCHK(rocsolver_dpotrf(bh, rocblas_fill_lower, ell, H.Droot, ell, info));
+        return check_info(1);  // exact Z: not positive definite only for coincident points
+    }
+
+    // 1. S = (Z - leaf blocks) Omega, from the sibling-pair products of every level
+    hipLaunchKernelGGL(k_omega, dim3(2048), dim3(NT), 0, s, Om, n, r, r, mix64(seed + 0x2545f4914f6cdd1dull));
+    launch_fill(s, S, (int64_t)n * r, 0.0);
+    for (int l = 1; l <= L; ++l) {
+        const int64_t tasks = (int64_t)1 << (l - 1);
+        for (int mode = 0; mode < 2; ++mode)
+            hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rbl[l]), (unsigned)(r / SL)), dim3(NT), 0, s, H.Xp, m,
+                               t, H.bnd + boff(l), mode, rbl[l], Om, Tmp, r);
+        launch_axpy1(s, Tmp, S, (int64_t)n * r);
+    }
+    // Bc[l][pair] = U(I_a)^T Z(I_a, I_b) U(I_b) for level l's sibling pairs, U: n x k[l]
+    auto couplings = [&](const double *U, int l) {
+        const int kl = k[l], nt = (kl / SL) * (kl / SL);
+        const int64_t tasks = (int64_t)1 << (l - 1);
+        hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rbl[l]), (unsigned)(kl / SL)), dim3(NT), 0, s, H.Xp, m,
+                           t, H.bnd + boff(l), 0, rbl[l], U, Wz, kl);
+        hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)(tasks * cmx[l]), (unsigned)nt), dim3(NT), 0, s, U, kl, Wz,
+                           kl, H.bnd + boff(l), 2, 0, crows[l], cmx[l], gp);
+        hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(tasks * nt), SL * SL / NT), dim3(NT), 0, s, gp, cmx[l], kl,
+                           kl, Bc[l]);
+    };
+
+    // 2. leaves: bases from the eigenvectors of T T^T
+    {
+        const int kl = k[L];
+        double *QL = H.Q + off[L];
+        hipLaunchKernelGGL(k_hss_gather_rows, dim3(hss_grid(leaves * ell * (int64_t)r)), dim3(NT), 0, s, S, r, bL, ell,
+                           leaves, T);
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_transpose, ell, ell, r, &one,
+                                            T, ell, (rocblas_stride)ell * r, T, ell, (rocblas_stride)ell * r, &zero, QL,
+                                            ell, (rocblas_stride)ell * ell, (rocblas_int)leaves));
+        RBCHK(rocsolver_dsyevd_strided_batched(bh, rocblas_evect_original, rocblas_fill_lower, ell, QL, ell,
+                                               (rocblas_stride)ell * ell, eigw, ell, eigw + leaves * ell, ell, info,
+                                               (rocblas_int)leaves));
+        HSSCHK(check_info((int)leaves));
+        const double *V = QL + (int64_t)(ell - kl) * ell;
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, kl, r, ell, &one,
+                                            V, ell, (rocblas_stride)ell * ell, T, ell, (rocblas_stride)ell * r, &zero,
+                                            St[0], kl, (rocblas_stride)kl * r, (rocblas_int)leaves));
+        hipLaunchKernelGGL(k_hss_gather_rows, dim3(hss_grid(leaves * ell * (int64_t)r)), dim3(NT), 0, s, Om, r, bL, ell,
+                           leaves, T);
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, kl, r, ell, &one,
+                                            V, ell, (rocblas_stride)ell * ell, T, ell, (rocblas_stride)ell * r, &zero,
+                                            Ot[0], kl, (rocblas_stride)kl * r, (rocblas_int)leaves));
+        hipLaunchKernelGGL(k_hss_scatter_basis, dim3(hss_grid(leaves * ell * (int64_t)kl)), dim3(NT), 0, s, QL, ell, kl,
+                           bL, leaves, Ucur);
+    }
+    // 3. levels L-1 .. 1: couplings of the children, projected samples, nested bases
+    int cur = 0;
+    for (int l = L - 1; l >= 1; --l) {
+        const int kc = k[l + 1], al = a[l], kl = k[l];
+        const int64_t nodes = (int64_t)1 << l;
+        couplings(Ucur, l + 1);
+        // T = [S~_a - B O~_b ; S~_b - B^T O~_a]
+        hipLaunchKernelGGL(k_hss_stack, dim3(hss_grid(nodes * al * (int64_t)r)), dim3(NT), 0, s, St[cur],
+                           (int64_t)kc * r, kc, 0, kc, r, nodes, T);
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_none, kc, r, kc, &mone,
+                                            Bc[l + 1], kc, (rocblas_stride)kc * kc, Ot[cur] + (int64_t)kc * r, kc,
+                                            (rocblas_stride)2 * kc * r, &one, T, al, (rocblas_stride)al * r,
+                                            (rocblas_int)nodes));
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, kc, r, kc, &mone,
+                                            Bc[l + 1], kc, (rocblas_stride)kc * kc, Ot[cur], kc,
+                                            (rocblas_stride)2 * kc * r, &one, T + kc, al, (rocblas_stride)al * r,
+                                            (rocblas_int)nodes));
+        double *Ql = H.Q + off[l];
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_transpose, al, al, r, &one,
+                                            T, al, (rocblas_stride)al * r, T, al, (rocblas_stride)al * r, &zero, Ql, al,
+                                            (rocblas_stride)al * al, (rocblas_int)nodes));
+        RBCHK(rocsolver_dsyevd_strided_batched(bh, rocblas_evect_original, rocblas_fill_lower, al, Ql, al,
+                                               (rocblas_stride)al * al, eigw, al, eigw + nodes * al, al, info,
+                                               (rocblas_int)nodes));
+        HSSCHK(check_info((int)nodes));
+        const double *R = Ql + (int64_t)(al - kl) * al;
+        const int nx = cur ^ 1;
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, kl, r, al, &one,
+                                            R, al, (rocblas_stride)al * al, T, al, (rocblas_stride)al * r, &zero,
+                                            St[nx], kl, (rocblas_stride)kl * r, (rocblas_int)nodes));
+        hipLaunchKernelGGL(k_hss_stack, dim3(hss_grid(nodes * al * (int64_t)r)), dim3(NT), 0, s, Ot[cur],
+                           (int64_t)kc * r, kc, 0, kc, r, nodes, T);
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, kl, r, al, &one,
+                                            R, al, (rocblas_stride)al * al, T, al, (rocblas_stride)al * r, &zero,
+                                            Ot[nx], kl, (rocblas_stride)kl * r, (rocblas_int)nodes));
+        // explicit bases of level l: U_l(I_c) = U_{l+1}(I_c) R_c for each child c
+        hipLaunchKernelGGL(k_hss_rowmul, dim3((unsigned)(2 * nodes * rb16[l + 1])), dim3(NT), 0, s, Ucur, kc, Ql, al,
+                           kl, H.bnd + boff(l + 1), rb16[l + 1], Unext);
+        std::swap(Ucur, Unext);
+        cur = nx;
+    }
+    couplings(Ucur, 1);
+
+    // 4. ULV, bottom-up
+    for (int l = L; l >= 1; --l) {
+        const int al = a[l], kl = k[l], el = al - kl;
+        const int64_t nodes = (int64_t)1 << l;
+        double *Ql = H.Q + off[l], *Dl = H.Dt + off[l];
+        if (l == L)
+            hipLaunchKernelGGL(k_hss_leaf_block, dim3(hss_grid(nodes * (int64_t)al * al)), dim3(NT), 0, s, H.Xp, m, t,
+                               bL, ell, nodes, Dn);
+        else
+            hipLaunchKernelGGL(k_hss_assemble, dim3(hss_grid(nodes * (int64_t)al * al)), dim3(NT), 0, s,
+                               H.Dt + off[l + 1], a[l + 1], k[l + 1], Bc[l + 1], nodes, Dn);
+        // Dt = Q^T D Q
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_none, al, al, al, &one, Dn,
+                                            al, (rocblas_stride)al * al, Ql, al, (rocblas_stride)al * al, &zero, T2, al,
+                                            (rocblas_stride)al * al, (rocblas_int)nodes));
+        RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_transpose, rocblas_operation_none, al, al, al, &one,
+                                            Ql, al, (rocblas_stride)al * al, T2, al, (rocblas_stride)al * al, &zero, Dl,
+                                            al, (rocblas_stride)al * al, (rocblas_int)nodes));
+        if (el > 0) {
+            // keep Q^T D Q for a retake with a shift (Dn is free after the transform)
+            if (hipMemcpyAsync(Dn, Dl, sizeof(double) * nodes * al * al, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return MAG_EHIP;
+            HSSCHK(potrf_shifted(Dl, Dn, al, el, nodes));
+            RBCHK(rocblas_dtrsm_strided_batched(bh, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                                                rocblas_diagonal_non_unit, kl, el, &one, Dl, al,
+                                                (rocblas_stride)al * al, Dl + el, al, (rocblas_stride)al * al,
+                                                (rocblas_int)nodes));
+            RBCHK(rocblas_dgemm_strided_batched(bh, rocblas_operation_none, rocblas_operation_transpose, kl, kl, el,
+                                                &mone, Dl + el, al, (rocblas_stride)al * al, Dl + el, al,
+                                                (rocblas_stride)al * al, &one, Dl + el + (int64_t)el * al, al,
+                                                (rocblas_stride)al * al, (rocblas_int)nodes));
+        }
+    }
+    hipLaunchKernelGGL(k_hss_assemble, dim3(hss_grid((int64_t)a[0] * a[0])), dim3(NT), 0, s, H.Dt + off[1], a[1], k[1],
+                       Bc[1], (int64_t)1, Dn);
+    if (hipMemcpyAsync(H.Droot, Dn, sizeof(double) * a[0] * a[0], hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return MAG_EHIP;
+    HSSCHK(potrf_shifted(H.Droot, Dn, a[0], a[0], 1));
+    if (hipGetLastError() != hipSuccess) return MAG_EHIP;
+    return MAG_OK;
+}
+
+int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z)
+{
+    rocblas_handle bh = (rocblas_handle)H.blas;
+    if (rocblas_set_stream(bh, s) != rocblas_status_success) return MAG_EHIP;
+    const int L = H.L, ell = H.ell;
+    const int64_t leaves = (int64_t)1 << L;
+    const int64_t *bL = H.bnd + boff(L);
+    const double one = 1.0, mone = -1.0, zero = 0.0;
+    hipLaunchKernelGGL(k_hss_gather_vec, dim3(hss_grid(leaves * ell)), dim3(NT), 0, s, r, H.perm, bL, ell, leaves,
+                       H.xl);
+    if (L == 0) {
+        RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, ell, H.Droot,
+                            ell, H.xl, 1));
+        RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, ell,
+                            H.Droot, ell, H.xl, 1));
+        hipLaunchKernelGGL(k_hss_scatter_vec, dim3(hss_grid(std::max<int64_t>(leaves * ell, H.npad))), dim3(NT), 0, s,
+                           H.xl, H.perm, bL, ell, leaves, H.n, H.npad, z);
+        return MAG_OK;
+    }
+    // up: ub_l[tau] = Q^T (node rhs), then y_e = L_e^{-1} b~_e, b^ = b~_s - W y_e
+    for (int l = L; l >= 1; --l) {
+        const int al = H.a[l], kl = H.k[l], el = al - kl;
+        const int64_t nodes = (int64_t)1 << l;
+        const double *rin;
+        if (l == L) {
+            rin = H.xl;
+        } else {
+            const int ac = H.a[l + 1];
+            hipLaunchKernelGGL(k_hss_stack, dim3(hss_grid(nodes * al)), dim3(NT), 0, s, H.ub + H.voff[l + 1], (int64_t)ac,
+                               ac, ac - H.k[l + 1], H.k[l + 1], 1, nodes, H.xb + H.voff[l]);
+            rin = H.xb + H.voff[l];
+        }
+        double *u = H.ub + H.voff[l];
+        const double *Ql = H.Q + H.off[l], *Dl = H.Dt + H.off[l];
+        RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_transpose, al, al, &one, Ql, al,
+                                            (rocblas_stride)al * al, rin, 1, al, &zero, u, 1, al, (rocblas_int)nodes));
+        if (el > 0) {
+            RBCHK(rocblas_dtrsv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_none,
+                                                rocblas_diagonal_non_unit, el, Dl, al, (rocblas_stride)al * al, u, 1, al,
+                                                (rocblas_int)nodes));
+            RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_none, kl, el, &mone, Dl + el, al,
+                                                (rocblas_stride)al * al, u, 1, al, &one, u + el, 1, al,
+                                                (rocblas_int)nodes));
+        }
+    }
+    // root
+    const int a0 = H.a[0];
+    hipLaunchKernelGGL(k_hss_stack, dim3(hss_grid(a0)), dim3(NT), 0, s, H.ub + H.voff[1], (int64_t)H.a[1], H.a[1],
+                       H.a[1] - H.k[1], H.k[1], 1, (int64_t)1, H.rr);
+    RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, a0, H.Droot, a0,
+                        H.rr, 1));
+    RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, a0, H.Droot, a0,
+                        H.rr, 1));
+    // down: v = [y_e; x_s], x_e = L_e^{-T} (y_e - W^T x_s), x = Q v
+    for (int l = 1; l <= L; ++l) {
+        const int al = H.a[l], kl = H.k[l], el = al - kl;
+        const int64_t nodes = (int64_t)1 << l;
+        const double *xpar = (l == 1) ? H.rr : H.xb + H.voff[l - 1];
+        const int apar = (l == 1) ? a0 : H.a[l - 1];
+        double *v = H.ub + H.voff[l];  // y_e stays in place, x_s is written after it
+        hipLaunchKernelGGL(k_hss_down_vec, dim3(hss_grid(nodes * al)), dim3(NT), 0, s, H.ub + H.voff[l], xpar, apar, al,
+                           kl, nodes, v);
+        const double *Ql = H.Q + H.off[l], *Dl = H.Dt + H.off[l];
+        if (el > 0) {
+            RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_transpose, kl, el, &mone, Dl + el, al,
+                                                (rocblas_stride)al * al, v + el, 1, al, &one, v, 1, al,
+                                                (rocblas_int)nodes));
+            RBCHK(rocblas_dtrsv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_transpose,
+                                                rocblas_diagonal_non_unit, el, Dl, al, (rocblas_stride)al * al, v, 1, al,
+                                                (rocblas_int)nodes));
+        }
+        double *xo = (l == L) ? H.xl : H.xb + H.voff[l];
+        RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_none, al, al, &one, Ql, al, (rocblas_stride)al * al,
+                                            v, 1, al, &zero, xo, 1, al, (rocblas_int)nodes));
+    }
+    hipLaunchKernelGGL(k_hss_scatter_vec, dim3(hss_grid(std::max<int64_t>(leaves * ell, H.npad))), dim3(NT), 0, s, H.xl,
+                       H.perm, bL, ell, leaves, H.n, H.npad, z);
+    return MAG_OK;
+}
+
 }  // namespace mag

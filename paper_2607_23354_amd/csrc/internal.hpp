@@ -141,6 +141,7 @@ struct mag_ctx {
     mag::DevBuf bfactor, bdinv, bvec, bscal, bpartial, bints, bdesc, barena, bstage;
     mag::DevBuf hodlr;     // HODLR preconditioner workspace
     mag::DevBuf eig;       // Lanczos bases of the eigenvalue estimator
+    mag::DevBuf hss;       // HSS approximation and ULV factor
     void *bhost = nullptr;   // pinned host staging for work lists and descriptors
     size_t bhost_bytes = 0;
     double *host_scalars = nullptr;  // pinned host staging (64 doubles)
@@ -298,5 +299,36 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
                  int oversample, uint64_t seed, HodlrFactor &H);
 // z = H^{-1} r; r, z device vectors of length npad (z zero on [n, npad)).
 void hodlr_apply(hipStream_t s, const HodlrFactor &H, const double *r, double *z);
+
+// ---- hodlr.hip: HSS approximation with nested bases and its ULV factor --------
+// Same cluster tree as the HODLR (points in tree order, perfect tree of L
+// levels).  Level l (1 <= l <= L) has 2^l nodes with a[l] active unknowns each
+// (the leaf size ell at l = L, else the two children's k[l+1]) and orthogonal
+// Q (a x a, column-major) whose last k[l] columns are the node's basis; level
+// 0 is the root, a dense block of a[0] = 2 k[1] unknowns.  Dt holds, per node,
+// the transformed block Q^T D Q after elimination: L_e (the Cholesky factor of
+// the first e = a - k unknowns) top-left, W = D_se L_e^{-T} bottom-left and the
+// Schur complement passed to the parent bottom-right.  Root: Cholesky of its
+// block.  ub/xb: per-level work vectors of the apply.
+struct HssFactor {
+    int64_t n = 0, npad = 0;
+    int m = 0, L = 0, ell = 0;
+    double t = 0.0;
+    double *Xp = nullptr, *Q = nullptr, *Dt = nullptr, *Droot = nullptr, *ub = nullptr, *xb = nullptr;
+    double *xl = nullptr, *rr = nullptr;
+    int64_t *perm = nullptr, *bnd = nullptr;
+    std::vector<int> k, a;
+    std::vector<int64_t> off;  // per level: offset of its Q / Dt blocks (doubles)
+    std::vector<int64_t> voff; // per level: offset of its ub / xb vectors (doubles)
+    void *blas = nullptr;      // rocblas_handle of the context
+    double shift = 0.0;        // largest diagonal shift a compressed block needed (0: none)
+};
+// Build the HSS approximation of Z(t) (ranks from rank0 and oversample as
+// documented for mag_opts.max_rank) and its ULV factor.  MAG_ENOTPD when a
+// block to be eliminated is not positive definite.
+int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int leaf, int rank0, int oversample,
+               uint64_t seed, HssFactor &H);
+// z = H^{-1} r (npad vectors, caller's point order; z zero on [n, npad)).
+int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z);
 
 }  // namespace mag
