@@ -71,9 +71,10 @@ enum {
                           * GMRES (Sec. 3.2's hierarchical solver): the same tree; each *
                           * node's basis spans its whole off-diagonal block row (one    *
                           * Gaussian sample, projected up the tree); level l keeps      *
-                          * max_rank 2^{-l/2} + oversample columns rounded up to 64     *
-                          * (64..512, at most twice its children's); leaves of at least *
-                          * 64 points (n > leaf); m <= 16                               */
+                          * 8 max_rank 2^{-l/2} + oversample columns rounded up to 64   *
+                          * (64..512, at most twice its children's: a block row sees    *
+                          * the near field on every side); leaves of at least 64 points *
+                          * (n > leaf); m <= 16                                         */
 };
 
 typedef struct {

@@ -1200,12 +1200,16 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
         for (int l = 0; l < m; ++l) Xp[i * m + l] = Xh[perm[i] * m + l];
 
     // ranks: level l >= 1 keeps k[l] columns, a multiple of 64 within [64, 512]
-    // from rank0 2^{-l/2} + oversample, at most its active size a[l] (at the
-    // leaves, the smallest leaf, so no basis vector lives on padding)
+    // from 8 rank0 2^{-l/2} + oversample, at most its active size a[l] (at the
+    // leaves, the smallest leaf, so no basis vector lives on padding).  A node's
+    // basis covers its whole off-diagonal block row (the near field on every
+    // side), not one sibling block as in the HODLR, hence the factor 8: on the
+    // noisy torus at n = 131072 the factor 1 schedule needed diagonal shifts and
+    // 400 GMRES iterations, the factor 8 one none and 80-95.
     const int ell = (int)maxleaf;
     std::vector<int> k(L + 1, 0), a(L + 1, 0);
     auto cap = [&](int l) {
-        const double want = rank0 * std::pow(2.0, -0.5 * l) + oversample;
+        const double want = 8.0 * rank0 * std::pow(2.0, -0.5 * l) + oversample;
         return SL * std::max(1, std::min((int)std::ceil(want / SL), KMAXC));
     };
     if (L == 0) {
