@@ -97,21 +97,25 @@ __global__ void __launch_bounds__(NT) k_omega(double *__restrict__ Om, int64_t n
     }
 }
 
-// Sampling product over the sibling pairs of one level, 64-column slab
-// blockIdx.y of B and out (both n x ld, row-major):
+// Sampling product over the sibling pairs of one level, NS 64-column slabs
+// (blockIdx.y) of B and out (both n x ld, row-major):
 //   out[r, slab] = sum_{c in C} Z(r, c) B[c, slab]   for r in R,
 // mode 0: R = left child, C = right child;  mode 1: R = right, C = left.
 // bnd: bounds of the children level (2 * tasks + 1 entries).  One workgroup
-// per 64-row block of R and slab; Z is formed 64 x 64 at a time in LDS.
+// per 64-row block of R and NS slabs; Z is formed 64 x (64 / NS) at a time in
+// LDS and applied to all NS slabs, so each entry's exp is evaluated once per
+// NS slabs.  Every output sums over c in ascending order whatever NS is.
+template <int NS>
 __global__ void __launch_bounds__(NT)
 k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restrict__ bnd, int mode,
          int rbmax, const double *B, double *out, int ld)
 {
-    __shared__ double Bs[ZC][SL];
-    __shared__ double Zs[ZR][ZC + 1];
-    __shared__ double Xc[MMAXH][ZC];
+    constexpr int CC = ZC / NS;  // points per chunk
+    __shared__ double Bs[CC][NS * SL];
+    __shared__ double Zs[ZR][CC + 1];
+    __shared__ double Xc[MMAXH][CC];
     const int task = blockIdx.x / rbmax, rb = blockIdx.x % rbmax;
-    const int col0 = blockIdx.y * SL;
+    const int col0 = blockIdx.y * NS * SL;
     const int64_t a = bnd[2 * task], b = bnd[2 * task + 1], c = bnd[2 * task + 2];
     const int64_t rlo = mode ? b : a, rhi = mode ? c : b;
     const int64_t clo = mode ? a : b, chi = mode ? b : c;
@@ -119,31 +123,33 @@ k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restri
     if (r0 >= rhi) return;  // uniform per workgroup
     const int nr = (int)min((int64_t)ZR, rhi - r0);
     const int tid = threadIdx.x;
-    const int gr = tid & 63, gp = tid >> 6;  // Z-tile generation: row, 16-point group
-    const int ty = tid >> 4, tx = tid & 15;  // accumulation: rows 4ty.., columns 4tx..
+    const int gr = tid & 63, gp = tid >> 6;  // Z-tile generation: row, group of CC / 4 points
+    const int ty = tid >> 4, tx = tid & 15;  // accumulation: rows 4ty.., columns 4tx.. of each slab
     double xr[MMAXH];
 #pragma unroll
     for (int l = 0; l < MMAXH; ++l) xr[l] = (l < m && gr < nr) ? Xp[(r0 + gr) * m + l] : 0.0;
-    double acc[4][4];
+    double acc[NS][4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int u = 0; u < NS; ++u)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[u][i][j] = 0.0;
 
-    for (int64_t c0 = clo; c0 < chi; c0 += ZC) {
-        const int cnt = (int)min((int64_t)ZC, chi - c0);
+    for (int64_t c0 = clo; c0 < chi; c0 += CC) {
+        const int cnt = (int)min((int64_t)CC, chi - c0);
         __syncthreads();
-        for (int e = tid; e < ZC * SL; e += NT) {
-            const int p = e / SL, q = e % SL;
+        for (int e = tid; e < CC * NS * SL; e += NT) {
+            const int p = e / (NS * SL), q = e % (NS * SL);
             Bs[p][q] = (p < cnt) ? B[(c0 + p) * ld + col0 + q] : 0.0;
         }
-        for (int e = tid; e < m * ZC; e += NT) {
-            const int l = e / ZC, p = e % ZC;
+        for (int e = tid; e < m * CC; e += NT) {
+            const int l = e / CC, p = e % CC;
             Xc[l][p] = (p < cnt) ? Xp[(c0 + p) * m + l] : 0.0;
         }
         __syncthreads();
-        for (int q = 0; q < 16; ++q) {
-            const int p = gp * 16 + q;
+        for (int q = 0; q < CC / 4; ++q) {
+            const int p = gp * (CC / 4) + q;
             double s = 0.0;
 #pragma unroll
             for (int l = 0; l < MMAXH; ++l)
@@ -152,16 +158,20 @@ k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restri
         }
         __syncthreads();
 #pragma unroll 4
-        for (int p = 0; p < ZC; ++p) {
-            double av[4], bv[4];
+        for (int p = 0; p < CC; ++p) {
+            double av[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) av[i] = Zs[4 * ty + i][p];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bs[p][4 * tx + j];
+            for (int u = 0; u < NS; ++u) {
+                double bv[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) bv[j] = Bs[p][u * SL + 4 * tx + j];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[u][i][j] = fma(av[i], bv[j], acc[u][i][j]);
+            }
         }
     }
 #pragma unroll
@@ -169,9 +179,29 @@ k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restri
         const int r = 4 * ty + i;
         if (r < nr) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) out[(r0 + r) * ld + col0 + 4 * tx + j] = acc[i][j];
+            for (int u = 0; u < NS; ++u)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) out[(r0 + r) * ld + col0 + u * SL + 4 * tx + j] = acc[u][i][j];
         }
     }
+}
+
+// Launch k_zblock over `tasks` sibling pairs, `cols` columns (a multiple of 64)
+// of B and out, with as many slabs per workgroup as divide them (up to 4).
+void launch_zblock(hipStream_t s, const double *Xp, int m, double t, const int64_t *bnd, int mode, int64_t tasks,
+                   int rbmax, const double *B, double *out, int ld, int cols)
+{
+    const int slabs = cols / SL;
+    const unsigned gx = (unsigned)(tasks * rbmax);
+    if (slabs % 4 == 0)
+        hipLaunchKernelGGL(k_zblock<4>, dim3(gx, (unsigned)(slabs / 4)), dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax,
+                           B, out, ld);
+    else if (slabs % 2 == 0)
+        hipLaunchKernelGGL(k_zblock<2>, dim3(gx, (unsigned)(slabs / 2)), dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax,
+                           B, out, ld);
+    else
+        hipLaunchKernelGGL(k_zblock<1>, dim3(gx, (unsigned)slabs), dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B,
+                           out, ld);
 }
 
 // Row range of task i: [bnd[ts*i + to], bnd[ts*i + to + 1]).
@@ -844,8 +874,7 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
         double *Pl = H.P + pl.poff[l];
         hipLaunchKernelGGL(k_omega, dim3(2048), dim3(NT), 0, s, Om, n, k, k,
                            mix64(seed + 0x51ed2701ull * (uint64_t)(l + 1)));
-        hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rb), (unsigned)(k / SL)), dim3(NT), 0, s, H.Xp, m, t,
-                           bch, 0, rb, Om, Pl, k);
+        launch_zblock(s, H.Xp, m, t, bch, 0, tasks, rb, Om, Pl, k, k);
         double *src = Pl, *dst = W2;
         for (int pass = 0; pass < 3; ++pass) {
             gram(src, k, src, k, bch, 2, 0, tasks, l, G);
@@ -861,8 +890,7 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
         }
         // three passes end in W2: copy the left children's rows back
         hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)(tasks * rb)), dim3(NT), 0, s, src, Pl, k, bch, 2, 0, rb);
-        hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rb), (unsigned)(k / SL)), dim3(NT), 0, s, H.Xp, m, t,
-                           bch, 1, rb, Pl, Pl, k);
+        launch_zblock(s, H.Xp, m, t, bch, 1, tasks, rb, Pl, Pl, k, k);
     }
 
     // 2. leaves: exact inverses, applied to every level's basis
@@ -1004,26 +1032,17 @@ __global__ void k_hss_scatter_basis(const double *__restrict__ Q, int ell, int k
     }
 }
 
-// Nested basis of the next level: out[p, j] = sum_i A[p, i] R_c[i, j] for the
-// rows p of child c (A: n x kc, out: n x kl, both row-major; R_c = Q-block
-// rows c%2 kc .. of the parent's last kl columns).  16 rows per workgroup.
-__global__ void __launch_bounds__(NT)
-k_hss_rowmul(const double *__restrict__ A, int kc, const double *__restrict__ Q, int a, int kl,
-             const int64_t *__restrict__ bnd, int rbmax, double *__restrict__ out)
+// Rs[2p + h] (kc x k, column-major) = rows h kc .. of the last k columns of
+// Q[p] (a x a): the blocks R_c of the nested basis, for the row products.
+__global__ void k_hss_split_R(const double *__restrict__ Q, int a, int k, int kc, int64_t parents,
+                              double *__restrict__ Rs)
 {
-    const int64_t c = blockIdx.x / rbmax;
-    const int rb = blockIdx.x % rbmax;
-    const int64_t lo = bnd[c], hi = bnd[c + 1];
-    const int64_t p = lo + (int64_t)rb * 16 + (threadIdx.x >> 4);
-    const int cg = threadIdx.x & 15;
-    if (p >= hi) return;
-    const double *R = Q + (c / 2) * (int64_t)a * a + (int64_t)(a - kl) * a + (c % 2) * kc;
-    const double *ar = A + p * kc;
-    for (int j = cg; j < kl; j += 16) {
-        const double *rc = R + (int64_t)j * a;
-        double acc = 0.0;
-        for (int i = 0; i < kc; ++i) acc = fma(ar[i], rc[i], acc);
-        out[p * kl + j] = acc;
+    const int64_t blk = (int64_t)kc * k, total = 2 * parents * blk;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t ch = e / blk, w = e % blk;
+        const int c = (int)(w / kc), i = (int)(w % kc);
+        const int64_t p = ch / 2, h = ch % 2;
+        Rs[e] = Q[p * (int64_t)a * a + (int64_t)(a - k + c) * a + h * kc + i];
     }
 }
 
@@ -1234,7 +1253,7 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
     const int64_t qtot = off[L + 1], vtot = voff[L + 1];
     // per-level buffer needs; gram chunking per level (children of level l)
     int64_t maxT = 1, maxQ = 1, maxSt = 1, maxB = 1, maxEig = 1, gpart = 1, amax = std::max(1, a[0]);
-    std::vector<int> crows(L + 1, 256), cmx(L + 1, 1), rbl(L + 1, 1), rb16(L + 1, 1);
+    std::vector<int> crows(L + 1, 256), cmx(L + 1, 1), rbl(L + 1, 1);
     for (int l = 1; l <= L; ++l) {
         const int64_t nodes = (int64_t)1 << l;
         maxT = std::max(maxT, nodes * a[l] * r);
@@ -1248,7 +1267,6 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
         crows[l] = (int)std::max<int64_t>(256, cdiv(cdiv(csz, 64), 32) * 32);
         cmx[l] = (int)cdiv(csz, crows[l]);
         rbl[l] = (int)cdiv(csz, 64);
-        rb16[l] = (int)cdiv(csz, 16);
         gpart = std::max(gpart, (nodes / 2) * cmx[l] * (int64_t)(k[l] / SL) * (k[l] / SL) * SL * SL);
     }
     maxEig = std::max(maxEig, 2 * amax);
@@ -1351,16 +1369,14 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
     for (int l = 1; l <= L; ++l) {
         const int64_t tasks = (int64_t)1 << (l - 1);
         for (int mode = 0; mode < 2; ++mode)
-            hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rbl[l]), (unsigned)(r / SL)), dim3(NT), 0, s, H.Xp, m,
-                               t, H.bnd + boff(l), mode, rbl[l], Om, Tmp, r);
+            launch_zblock(s, H.Xp, m, t, H.bnd + boff(l), mode, tasks, rbl[l], Om, Tmp, r, r);
         launch_axpy1(s, Tmp, S, (int64_t)n * r);
     }
     // Bc[l][pair] = U(I_a)^T Z(I_a, I_b) U(I_b) for level l's sibling pairs, U: n x k[l]
     auto couplings = [&](const double *U, int l) {
         const int kl = k[l], nt = (kl / SL) * (kl / SL);
         const int64_t tasks = (int64_t)1 << (l - 1);
-        hipLaunchKernelGGL(k_zblock, dim3((unsigned)(tasks * rbl[l]), (unsigned)(kl / SL)), dim3(NT), 0, s, H.Xp, m,
-                           t, H.bnd + boff(l), 0, rbl[l], U, Wz, kl);
+        launch_zblock(s, H.Xp, m, t, H.bnd + boff(l), 0, tasks, rbl[l], U, Wz, kl, kl);
         hipLaunchKernelGGL(k_gram_partial, dim3((unsigned)(tasks * cmx[l]), (unsigned)nt), dim3(NT), 0, s, U, kl, Wz,
                            kl, H.bnd + boff(l), 2, 0, crows[l], cmx[l], gp);
         hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)(tasks * nt), SL * SL / NT), dim3(NT), 0, s, gp, cmx[l], kl,
@@ -1428,8 +1444,11 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
                                             R, al, (rocblas_stride)al * al, T, al, (rocblas_stride)al * r, &zero,
                                             Ot[nx], kl, (rocblas_stride)kl * r, (rocblas_int)nodes));
         // explicit bases of level l: U_l(I_c) = U_{l+1}(I_c) R_c for each child c
-        hipLaunchKernelGGL(k_hss_rowmul, dim3((unsigned)(2 * nodes * rb16[l + 1])), dim3(NT), 0, s, Ucur, kc, Ql, al,
-                           kl, H.bnd + boff(l + 1), rb16[l + 1], Unext);
+        // (R_c copied out to kc x kl blocks in T2, then the row-block products)
+        hipLaunchKernelGGL(k_hss_split_R, dim3(hss_grid(2 * nodes * (int64_t)kc * kl)), dim3(NT), 0, s, Ql, al, kl, kc,
+                           nodes, T2);
+        hipLaunchKernelGGL(k_rowmul, dim3((unsigned)(2 * nodes * rbl[l + 1]), (unsigned)(kl / SL)), dim3(NT), 0, s,
+                           Ucur, kc, Unext, kl, T2, (int64_t)kc * kl, H.bnd + boff(l + 1), 1, 0, rbl[l + 1], 0);
         std::swap(Ucur, Unext);
         cur = nx;
     }
