@@ -241,7 +241,7 @@ int batch_build_graph(Batch &bt)
     for (int b = 0; b < bt.B; ++b) all[b] = b;
     // work lists (persistent arena), built before capture
     struct Launch {
-        int kind;  // 0 trsm, 1 subupdate, 2 syrk, 3 potrf, 4 tilegen, 5 zero status
+        int kind;  // 0 trsm, 1 subupdate, 2 syrk, 3 potrf, 4 tilegen, 5 zero status, 6 strip
         int64_t kk;
         BWork w;
     };
@@ -252,19 +252,29 @@ int batch_build_graph(Batch &bt)
     BWork wt;
     BRC(bt.make_work(all, [&](int p) { return tilegen32_blocks(bt.h[p].npad); }, true, wt));
     seq.push_back({4, 0, wt});
-    for (int64_t k = 0; k < bt.maxpad; k += kPanel) {
-        for (int sub = 0; sub < kPanel / kTile; ++sub) {
-            const int64_t kk = k + sub * kTile;
-            BWork wp;
-            BRC(bt.make_work(all, [&](int p) { return (int64_t)(kk < bt.h[p].npad ? 1 : 0); }, true, wp));
-            seq.push_back({3, kk, wp});
-            BWork w0;
-            BRC(bt.make_work(all, [&](int p) { return kk < bt.h[p].npad ? gemm_b_units(0, bt.h[p].npad, kk) : 0; }, true, w0));
-            seq.push_back({0, kk, w0});
-            if (sub == 0) {
-                BWork w1;
-                BRC(bt.make_work(all, [&](int p) { return kk < bt.h[p].npad ? gemm_b_units(1, bt.h[p].npad, kk) : 0; }, true, w1));
-                seq.push_back({1, kk, w1});
+    // panels of kPanel columns in pairs: first panel, strip update of the second
+    // panel by the first, second panel, then one trailing update by both
+    for (int64_t k = 0; k < bt.maxpad; k += 2 * kPanel) {
+        for (int half = 0; half < 2; ++half) {
+            const int64_t kp = k + half * kPanel;
+            if (half == 1) {
+                BWork ws;
+                BRC(bt.make_work(all, [&](int p) { return kp < bt.h[p].npad ? gemm_b_units(3, bt.h[p].npad, k) : 0; }, true, ws));
+                seq.push_back({6, k, ws});
+            }
+            for (int sub = 0; sub < kPanel / kTile; ++sub) {
+                const int64_t kk = kp + sub * kTile;
+                BWork wp;
+                BRC(bt.make_work(all, [&](int p) { return (int64_t)(kk < bt.h[p].npad ? 1 : 0); }, true, wp));
+                seq.push_back({3, kk, wp});
+                BWork w0;
+                BRC(bt.make_work(all, [&](int p) { return kk < bt.h[p].npad ? gemm_b_units(0, bt.h[p].npad, kk) : 0; }, true, w0));
+                seq.push_back({0, kk, w0});
+                if (sub == 0) {
+                    BWork w1;
+                    BRC(bt.make_work(all, [&](int p) { return kk < bt.h[p].npad ? gemm_b_units(1, bt.h[p].npad, kk) : 0; }, true, w1));
+                    seq.push_back({1, kk, w1});
+                }
             }
         }
         BWork w2;
@@ -278,6 +288,7 @@ int batch_build_graph(Batch &bt)
         case 5: launch_zero_status_b(bt.s, bt.d, L.w.plist, L.w.na); break;
         case 4: launch_tilegen32_b(bt.s, bt.d, L.w); break;
         case 3: launch_potrf128_b(bt.s, bt.d, L.w, L.kk); break;
+        case 6: launch_gemm_b(bt.s, 3, bt.d, L.w, L.kk); break;
         default: launch_gemm_b(bt.s, L.kind, bt.d, L.w, L.kk); break;
         }
     }

@@ -239,9 +239,15 @@ k_syrk_lower(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, in
 }
 
 // Batched factorisation updates at panel offset kk of every active problem.
+// Panels are 256 columns wide and go in pairs (kk, kk + 256), as in the
+// single-problem factorisation.
 //   KIND 0: panel TRSM (SetT) of the 128-column sub-panel at kk, in place
 //   KIND 1: update of the next sub-panel's 128 columns by the one at kk
-//   KIND 2: trailing SYRK (lower tiles) by the 256-column panel at kk
+//   KIND 2: trailing SYRK (lower tiles) by the pair of panels at kk (K = 512)
+//   KIND 3: strip update of the second panel's columns (every row from
+//           kk + 256) by the first panel of the pair at kk (K = 256); the
+//           tile above the strip's 128-diagonal is rewritten by the second
+//           panel's own TRSM
 template <int KIND>
 __global__ void __launch_bounds__(NT, 2)
 k_gemm_b(const BProb *__restrict__ Pr, BWork w, int64_t kk)
@@ -260,11 +266,16 @@ k_gemm_b(const BProb *__restrict__ Pr, BWork w, int64_t kk)
         const float *Pp = A + kk * np + kk + BT;
         gemm_tile_body<kGemmSub>(A + (kk + BT) * np + kk + BT, np, Pp, np, Pp, np, u, 0, BT,
                                  nullptr);
-    } else {
+    } else if (KIND == 2) {
         int64_t ti, tj;
         tri_index(u, ti, tj);
+        const float *Pp = A + kk * np + kk + 4 * BT;
+        gemm_tile_body<kGemmSub, true>(A + (kk + 4 * BT) * np + kk + 4 * BT, np, Pp, np, Pp, np, ti, tj,
+                                       4 * BT, nullptr);
+    } else {
+        const int64_t T = (np - kk - 2 * BT) / BT;
         const float *Pp = A + kk * np + kk + 2 * BT;
-        gemm_tile_body<kGemmSub, true>(A + (kk + 2 * BT) * np + kk + 2 * BT, np, Pp, np, Pp, np, ti, tj,
+        gemm_tile_body<kGemmSub, true>(A + (kk + 2 * BT) * np + kk + 2 * BT, np, Pp, np, Pp, np, u % T, u / T,
                                        2 * BT, nullptr);
     }
 }
@@ -278,7 +289,11 @@ int64_t gemm_b_units(int kind, int64_t npad, int64_t kk)
         const int64_t rows = npad - kk - BT;
         return rows > 0 ? rows / BT : 0;
     }
-    const int64_t rows = npad - kk - 2 * BT;
+    if (kind == 3) {
+        const int64_t rows = npad - kk - 2 * BT;
+        return rows > 0 ? 2 * (rows / BT) : 0;
+    }
+    const int64_t rows = npad - kk - 4 * BT;
     const int64_t T = rows > 0 ? rows / BT : 0;
     return T * (T + 1) / 2;
 }
@@ -290,8 +305,10 @@ void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int6
         hipLaunchKernelGGL(k_gemm_b<0>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
     else if (kind == 1)
         hipLaunchKernelGGL(k_gemm_b<1>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
-    else
+    else if (kind == 2)
         hipLaunchKernelGGL(k_gemm_b<2>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
+    else
+        hipLaunchKernelGGL(k_gemm_b<3>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
 }
 
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
