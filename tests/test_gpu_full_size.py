@@ -3,7 +3,9 @@ cutoff scale t*), in the launch configuration the benchmark times, checked
 against the CPU oracle on sampled outputs it can compute one by one.
 
 * the FP32-factor + refinement solve: oracle residual rows, the device's own
-  residual, and agreement with the FP64 dense comparator on the same GPU;
+  residual, and agreement with the FP64 dense comparator on the same GPU; the
+  same checks at t*/4, t*/2, 2 t* and t_b, and on the anisotropic cloud with
+  covariance diag(1, 1/2, 1/4);
 * the FP64 matrix-free product Z v: sampled rows against the oracle's row
   products, to the rounding bound of an n-term FP64 sum;
 * the FP32 tile generator: every entry among 384 sampled points against the
@@ -51,6 +53,38 @@ def test_metric_solve_sampled_rows(mag, workload):
     assert np.abs(oracle.residual(X, t, wd, rows)).max() <= 1e-12
     assert np.abs(w - wd).max() <= 1e-9 * np.abs(wd).max()
     assert abs(res.info["magnitude"] - dense.info["magnitude"]) <= 1e-10 * abs(dense.info["magnitude"])
+
+
+def _solve_and_check_rows(mag, X, Xd, t, seed):
+    res = mag.weighting(Xd, t, solver="fp32_ir")
+    w = res.w.cpu().numpy()
+    rows = np.random.default_rng(seed).choice(len(X), size=128, replace=False)
+    r = np.abs(oracle.residual(X, t, w, rows)).max()
+    print(f"n={len(X)} t={t:.6f}: sampled oracle residual {r:.3e}, device {res.info['resid_inf']:.3e}, "
+          f"outer={res.info['outer_iters']} gmres={res.info['gmres_iters']} shifted={res.info['shifted']} "
+          f"M={res.info['magnitude']:.12g}")
+    assert r <= 1e-12
+    assert res.info["resid_inf"] <= 1e-12
+    assert res.info["argmin_w"] == int(np.argmin(w))
+    return res
+
+
+@pytest.mark.parametrize("scale", [0.25, 0.5, 2.0, "t_b"])
+def test_metric_t_sweep_sampled_rows(mag, workload, scale):
+    # the metric cloud at t*/4, t*/2, 2 t* and t_b = log(n - 1)/d_min (d_min from the oracle)
+    X, tstar, Xd = workload
+    t = oracle.t_bound(X) if scale == "t_b" else tstar * scale
+    res = _solve_and_check_rows(mag, X, Xd, t, seed=11)
+    if scale == "t_b":
+        # t_+ <= t_b (the elementary bound of Sections 1 and 2), so w >= 0 there
+        assert res.info["min_w"] >= 0
+
+
+def test_metric_anisotropic_sampled_rows(mag, workload):
+    # the same size with covariance diag(1, 1/2, 1/4), at the isotropic cloud's t*
+    _, tstar, _ = workload
+    X = W.gaussian(N, M_DIM, seed=SEED, diag=(1.0, 0.5, 0.25))
+    _solve_and_check_rows(mag, X, dev(X), tstar, seed=12)
 
 
 def test_metric_zmatvec_sampled_rows(mag, workload):
