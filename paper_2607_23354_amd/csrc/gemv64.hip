@@ -15,6 +15,8 @@
 // 256 rows) x (column splits), partial row sums split-major.
 #include "internal.hpp"
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 
@@ -65,7 +67,7 @@ __device__ __forceinline__ void zmv_partial_body(const double *__restrict__ X, i
                     double s = 0.0;
 #pragma unroll
                     for (int l = 0; l < M; ++l) s = sq_acc(s, xr[l] - Xc[l * CH + c]);
-                    const double z = (k0 + c == j) ? 1.0 : exp(-(t * sqrt(s)));
+                    const double z = (k0 + c == j) ? 1.0 : zexp(t, s);
                     acc = fma(z, vc[c], acc);
                 }
             }
@@ -83,7 +85,7 @@ __device__ __forceinline__ void zmv_partial_body(const double *__restrict__ X, i
                     const double *xk = X + (k0 + c) * m;
                     double s = 0.0;
                     for (int l = 0; l < m; ++l) s = sq_acc(s, xj[l] - xk[l]);
-                    const double z = (k0 + c == j) ? 1.0 : exp(-(t * sqrt(s)));
+                    const double z = (k0 + c == j) ? 1.0 : zexp(t, s);
                     acc = fma(z, vc[c], acc);
                 }
             }
@@ -153,37 +155,49 @@ __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) rowacc[ii] = 0.0;
     // one column at a time: the 8 row entries of a column are independent
-    // exp evaluations, enough parallelism without unrolling the columns
+    // exp evaluations, enough parallelism without unrolling the columns.
+    // Every entry is evaluated (padding coordinates are zero, the diagonal's
+    // s = 0 is harmless) and, in diagonal and edge tiles only, then selected,
+    // so the row entries stay independent straight-line code.
+    auto columns = [&](auto full_tile) {
+        constexpr bool FULL = decltype(full_tile)::value;
 #pragma unroll 1
-    for (int jj = 0; jj < 8; ++jj) {
-        const int c = 8 * tx + jj;
-        double xc[MM];
+        for (int jj = 0; jj < 8; ++jj) {
+            const int c = 8 * tx + jj;
+            double xc[MM];
 #pragma unroll
-        for (int l = 0; l < MM; ++l) xc[l] = (l < m) ? Xc[l][c] : 0.0;
-        const double vcj = vc[c];
-        double colacc = 0.0;
+            for (int l = 0; l < MM; ++l) xc[l] = (l < m) ? Xc[l][c] : 0.0;
+            const double vcj = vc[c];
+            double colacc = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < 8; ++ii) {
-            const int r = 8 * ty + ii;
-            double s = 0.0;
+            for (int ii = 0; ii < 8; ++ii) {
+                const int r = 8 * ty + ii;
+                double s = 0.0;
 #pragma unroll
-            for (int l = 0; l < MM; ++l) {
-                if (l < m) {
-                    const double xrv = (M > 0) ? xr[ii][(M > 0) ? l : 0] : Xr[l][r];
-                    s = sq_acc(s, xrv - xc[l]);
+                for (int l = 0; l < MM; ++l) {
+                    if (l < m) {
+                        const double xrv = (M > 0) ? xr[ii][(M > 0) ? l : 0] : Xr[l][r];
+                        s = sq_acc(s, xrv - xc[l]);
+                    }
                 }
+                double z;
+                if (ENT == kEntExp32) z = (double)expf(-((float)t * sqrtf((float)s)));  // entry in FP32, sums in FP64
+                else if (ENT == kEntShiftDist) z = t - sqrt(s);
+                else z = zexp(t, s);
+                if (!FULL) {
+                    z = (diag && r == c) ? ((ENT == kEntShiftDist) ? t : 1.0) : z;
+                    z = (r < nr && c < nc) ? z : 0.0;
+                }
+                rowacc[ii] = fma(z, vcj, rowacc[ii]);
+                colacc = fma(z, vr[r], colacc);
             }
-            double z;
-            if (r >= nr || c >= nc) z = 0.0;
-            else if (diag && r == c) z = (ENT == kEntShiftDist) ? t : 1.0;
-            else if (ENT == kEntExp32) z = (double)expf(-((float)t * sqrtf((float)s)));  // entry in FP32, sums in FP64
-            else if (ENT == kEntShiftDist) z = t - sqrt(s);
-            else z = exp(-(t * sqrt(s)));
-            rowacc[ii] = fma(z, vcj, rowacc[ii]);
-            colacc = fma(z, vr[r], colacc);
+            colsum[jj] = colacc;
         }
-        colsum[jj] = colacc;
-    }
+    };
+    if (!diag && nr == TS && nc == TS)  // uniform per workgroup
+        columns(std::true_type{});
+    else
+        columns(std::false_type{});
     double *pt = part + tile * 2 * TS;
     // rows: sum over the 16 tx lanes (contiguous) by a fixed butterfly
 #pragma unroll
@@ -221,7 +235,7 @@ __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64
 // and the column sums of tiles (I+1..T-1, I), in that order.  mode 0: y = Z v;
 // mode 1: y = b - Z v (b == NULL: ones) and blkmax[I] = max |y| over the block.
 template <int M, int ENT = kEntExp>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (M >= 1 && M <= 3) ? 4 : 1)
 k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const double *__restrict__ v,
           double *__restrict__ part)
 {
@@ -264,7 +278,7 @@ k_zmv_sym_reduce(const double *__restrict__ part, int64_t T, int64_t n, int64_t 
 // Batched symmetric Z v: units T(T+1)/2 tiles per problem (T = npad / TS),
 // then the per-block reduce (units T per problem); blkmax after the tiles.
 template <int M>
-__global__ void __launch_bounds__(256) k_zmv_sym_b(const BProb *__restrict__ P, BWork w, int v_slot)
+__global__ void __launch_bounds__(256, (M >= 1 && M <= 3) ? 4 : 1) k_zmv_sym_b(const BProb *__restrict__ P, BWork w, int v_slot)
 {
     const int i = bfind(w.pref, w.na, blockIdx.x);
     const BProb &q = P[w.plist[i]];

@@ -154,7 +154,7 @@ k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restri
 #pragma unroll
             for (int l = 0; l < MMAXH; ++l)
                 if (l < m) s = sq_acc(s, xr[l] - Xc[l][p]);
-            Zs[gr][p] = (p < cnt && gr < nr) ? exp(-(t * sqrt(s))) : 0.0;
+            Zs[gr][p] = (p < cnt && gr < nr) ? zexp(t, s) : 0.0;
         }
         __syncthreads();
 #pragma unroll 4
@@ -410,7 +410,7 @@ k_leaf_inv(const double *__restrict__ Xp, int m, double t, const int64_t *__rest
         } else if (i < s && j < s) {
             double d2 = 0.0;
             for (int l = 0; l < m; ++l) d2 = sq_acc(d2, Xp[(lo + i) * m + l] - Xp[(lo + j) * m + l]);
-            v = exp(-(t * sqrt(d2)));
+            v = zexp(t, d2);
         } else {
             v = 0.0;
         }
@@ -1078,7 +1078,7 @@ __global__ void k_hss_leaf_block(const double *__restrict__ Xp, int m, double t,
         } else if (i < sz && j < sz) {
             double q = 0.0;
             for (int l = 0; l < m; ++l) q = sq_acc(q, Xp[(lo + i) * m + l] - Xp[(lo + j) * m + l]);
-            v = exp(-(t * sqrt(q)));
+            v = zexp(t, q);
         } else {
             v = 0.0;
         }

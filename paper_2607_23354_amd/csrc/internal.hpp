@@ -76,6 +76,66 @@ struct BWork {
     int64_t total;
 };
 
+// FP64 kernel entry exp(-t d), d = sqrt(s), for the matrix-free products.
+// sqrt_pos: square root of a normal s > 0 from the hardware reciprocal square
+// root estimate, one Goldschmidt step (g ~ sqrt(s), h ~ 1/(2 sqrt(s))) and two
+// FMA residual corrections g += (s - g^2) h (Markstein's scheme).
+__device__ __forceinline__ double sqrt_pos(double s)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double e = fma(-g, g, s);
+    g = fma(e, h, g);
+    e = fma(-g, g, s);
+    return fma(e, h, g);
+}
+
+// a * b + c with a uniform c held in an SGPR pair: one VOP3 FMA (the compiler's
+// two-address FMA form would copy a loop-invariant addend before every use)
+__device__ __forceinline__ double fma_uc(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
+// exp(x) for x <= 0: Cody-Waite reduction x = k ln2 + r with |r| <= ln2/2 (ln2
+// split into a head with 32 significant bits, so k ln2_head is exact, and a
+// tail), e^r from its Taylor series to degree 13 (truncation below 1e-17
+// relative on that interval) in Horner form, then the exact scaling by 2^k,
+// which underflows to 0 below about -745.
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    x = fmax(x, -1.0e4);
+    const double k = rint(x * 1.4426950408889634);  // log2(e)
+    double r = fma(-k, 6.93147180369123816490e-01, x);
+    r = fma(-k, 1.90821492927058770002e-10, r);
+    double p = fma_uc(1.0 / 6227020800.0, r, 1.0 / 479001600.0);  // 1/13!, 1/12!
+    p = fma_uc(p, r, 1.0 / 39916800.0);
+    p = fma_uc(p, r, 1.0 / 3628800.0);
+    p = fma_uc(p, r, 1.0 / 362880.0);
+    p = fma_uc(p, r, 1.0 / 40320.0);
+    p = fma_uc(p, r, 1.0 / 5040.0);
+    p = fma_uc(p, r, 1.0 / 720.0);
+    p = fma_uc(p, r, 1.0 / 120.0);
+    p = fma_uc(p, r, 1.0 / 24.0);
+    p = fma_uc(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
+// Z entry exp(-t sqrt(s)) for a squared distance s >= 0 (s = 0 gives 1); s is
+// clamped into [1e-300, 1e300], where the entry is 1 and 0 to FP64
+__device__ __forceinline__ double zexp(double t, double s)
+{
+    return exp_nonpos(-(t * sqrt_pos(fmin(fmax(s, 1.0e-300), 1.0e300))));
+}
+
 __device__ inline int bfind(const int64_t *pref, int na, int64_t u)
 {
     int lo = 0, hi = na - 1;

@@ -76,7 +76,7 @@ __device__ __forceinline__ void pair_partial_body(const double *__restrict__ X, 
             for (int l = 0; l < MM; ++l)
                 if (l < m) s = sq_acc(s, xr[l] - Xc[l * CH + c]);
             const double d = sqrt(s);
-            const double z = exp(-(t * d));
+            const double z = exp_nonpos(-(t * d));
             if (MODE == kDZ) {
                 acc[0] = fma(d * z, vc[c], acc[0]);
             } else {

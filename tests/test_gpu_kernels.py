@@ -69,6 +69,27 @@ def test_zmatvec_matches_oracle(mag, n, m, t):
     assert np.all(np.abs(y - y_ref) <= 64 * U64 * scale + 1e-300)
 
 
+@pytest.mark.parametrize("m,t", [(1, 1.0), (3, 20.0), (10, 5.0)])
+def test_zmatvec_entries(mag, m, t):
+    # Z e_k is column k of Z, each entry a single product: every FP64 entry
+    # exp(-t d_jk) (symmetric product for m <= 8, row product beyond) within 2 ulp
+    # of the oracle's libm value, over t d up to 800 (underflow to 0 past ~745)
+    n = 2048
+    if m == 1:
+        X = (np.arange(n, dtype=np.float64) * (800.0 / (n - 1)))[:, None]
+    else:
+        X = W.gaussian(n, m, seed=31 + m)
+    Z = oracle.zmatrix(X, t)
+    for k in (0, n // 2 + 1):
+        e = np.zeros(n)
+        e[k] = 1.0
+        y = mag.zmatvec(dev(X), t, dev(e)).cpu().numpy()
+        ref = Z[:, k]
+        normal = ref >= np.finfo(np.float64).tiny
+        assert np.all(np.abs(y[normal] - ref[normal]) <= 2 * 2.0 ** -52 * ref[normal])
+        assert np.all(np.abs(y[~normal] - ref[~normal]) <= 1e-322)
+
+
 @pytest.mark.parametrize("n,m,t", [(300, 3, 4.0), (1000, 3, 1.5)])
 def test_residual_matches_oracle(mag, n, m, t):
     X = W.gaussian(n, m, seed=n)
