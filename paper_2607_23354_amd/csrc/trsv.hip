@@ -21,10 +21,13 @@
 //   * a "ready" count (blocks [0, ready) are final) replaces per-block flags,
 //     since block b can only finish after block b-1 has; a band publishes
 //     both of its blocks at once.  It is published in
-//     8 mirrored slots 256 bytes apart (each workgroup polls one), with a
-//     release after an agent-scope fence of the solution writes; pollers use
-//     relaxed loads and take one acquire fence per observed advance (an
-//     acquire per poll would invalidate the L2 on every spin);
+//     8 mirrored slots 256 bytes apart (each workgroup polls one);
+//   * every cross-workgroup exchange is done by wave 0 alone, since each
+//     fence a wave executes costs microseconds: wave 0 writes all of the
+//     band's solution entries, takes one agent-scope release fence and stores
+//     the counters; a poller's wave 0 takes one acquire fence per observed
+//     advance (an acquire per poll would invalidate the L2 on every spin) and
+//     reads the published blocks into LDS for the others;
 //   * spin-waits are bounded: on exhaustion the kernel sets a status word and
 //     finishes, and the host reports an error.
 // HBM traffic per apply: the lower triangle read twice (n^2 * 4 bytes).
@@ -60,11 +63,13 @@ __device__ inline int wait_ready(int *ready, int need, int *status)
     return v;
 }
 
+// Called by wave 0, which wrote every published solution entry: one release
+// fence for the wave, then relaxed stores of the mirrored counters.
 __device__ inline void publish(int *base, int value)
 {
-    // every thread fenced its own solution writes before the barrier
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (threadIdx.x < kMirrors)
-        __hip_atomic_store(base + threadIdx.x * kSlot, value, __ATOMIC_RELEASE,
+        __hip_atomic_store(base + threadIdx.x * kSlot, value, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -155,24 +160,37 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     // (bands publish two blocks at a time, so both are ready together)
     auto consume2 = [&](int st, bool two) {
         const int need = st + (two ? 2 : 1);
-        if (need > known) {
-            if (tid == 0) s_ready = wait_ready(ready, need, status);
-            __syncthreads();
-            known = s_ready;
+        if (need > known && tid < 64) {
+            // wave 0 waits, takes the one acquire and reads the published blocks;
+            // the others learn the new count after the barrier below
+            int v = 0;
+            if (tid == 0) v = wait_ready(ready, need, status);
+            v = __builtin_amdgcn_readfirstlane(v);
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (tid == 0) s_ready = v;
         }
-        {
-            const int q = tid >> 7;  // threads 0..127: block of step st, 128..255: st + 1
-            if (q == 0 || two) xs[q][row] = x[(int64_t)jof(st + q) * BS + row];
+        if (tid < 64) {
+            const int lane = tid;
+            const int64_t j0 = (int64_t)jof(st) * BS;
+            xs[0][lane] = x[j0 + lane];
+            xs[0][lane + 64] = x[j0 + lane + 64];
+            if (two) {
+                const int64_t j1 = (int64_t)jof(st + 1) * BS;
+                xs[1][lane] = x[j1 + lane];
+                xs[1][lane + 64] = x[j1 + lane + 64];
+            }
         }
         __syncthreads();
+        known = s_ready;
         gemv(ta0, xs[0], acc0);
         gemv(ta1, xs[0], acc1);
         if (two) {
             gemv(tb0, xs[1], acc0);
             gemv(tb1, xs[1], acc1);
         }
-        __syncthreads();  // xs is rewritten by the next step
+        // xs is rewritten by the next step; after the last one, only once the
+        // partial sums have passed the next barrier
+        if (st + 2 < nsteps) __syncthreads();
     };
     if (nsteps > 0) {
         load(b0, jof(0), ta0);
@@ -211,12 +229,13 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     }
     part[h][row] = v;
     __syncthreads();
-    if (tid < BS) {
-        const double xv = part[0][tid] + part[1][tid];
-        xs[1][tid] = xv;
-        x[(int64_t)b0 * BS + tid] = xv;
-    }
+    if (tid < BS) xs[1][tid] = part[0][tid] + part[1][tid];
     __syncthreads();
+    // wave 0 writes the band's solution entries and publishes them (one release)
+    if (tid < 64) {
+        x[(int64_t)b0 * BS + tid] = xs[1][tid];
+        x[(int64_t)b0 * BS + tid + 64] = xs[1][tid + 64];
+    }
     // second block: acc1 += L(b1, b0) x_b0, then x_b1 = Dinv_b1 (rhs_b1 - acc1)
     gemv(ti, xs[1], acc1);
 #pragma unroll
@@ -238,10 +257,11 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     }
     part[h][row] = v;
     __syncthreads();
-    if (tid < BS) x[(int64_t)b1 * BS + tid] = part[0][tid] + part[1][tid];
-    __threadfence();
-    __syncthreads();
-    publish(counters + (BWD ? kBwdReady : kFwdReady), nsteps + 2);
+    if (tid < 64) {
+        x[(int64_t)b1 * BS + tid] = part[0][tid] + part[1][tid];
+        x[(int64_t)b1 * BS + tid + 64] = part[0][tid + 64] + part[1][tid + 64];
+        publish(counters + (BWD ? kBwdReady : kFwdReady), nsteps + 2);
+    }
 }
 
 template <bool BWD>
