@@ -1492,6 +1492,15 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
     if (hipMemcpyAsync(H.Droot, Dn, sizeof(double) * a[0] * a[0], hipMemcpyDeviceToDevice, s) != hipSuccess)
         return MAG_EHIP;
     HSSCHK(potrf_shifted(H.Droot, Dn, a[0], a[0], 1));
+    // 5. the eliminated blocks' factors L_e are only applied from here on: keep
+    // their inverses in place, so the apply multiplies (trmv) instead of solving
+    for (int l = L; l >= 1; --l) {
+        const int al = a[l], el = al - k[l];
+        if (el <= 0) continue;
+        RBCHK(rocsolver_dtrtri_strided_batched(bh, rocblas_fill_lower, rocblas_diagonal_non_unit, el, H.Dt + off[l], al,
+                                               (rocblas_stride)al * al, info, (rocblas_int)((int64_t)1 << l)));
+        HSSCHK(check_info((int)((int64_t)1 << l)));
+    }
     if (hipGetLastError() != hipSuccess) return MAG_EHIP;
     return MAG_OK;
 }
@@ -1515,7 +1524,7 @@ int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z)
                            H.xl, H.perm, bL, ell, leaves, H.n, H.npad, z);
         return MAG_OK;
     }
-    // up: ub_l[tau] = Q^T (node rhs), then y_e = L_e^{-1} b~_e, b^ = b~_s - W y_e
+    // up: ub_l[tau] = Q^T (node rhs), then y_e = L_e^{-1} b~_e (L_e^{-1} is stored), b^ = b~_s - W y_e
     for (int l = L; l >= 1; --l) {
         const int al = H.a[l], kl = H.k[l], el = al - kl;
         const int64_t nodes = (int64_t)1 << l;
@@ -1533,7 +1542,7 @@ int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z)
         RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_transpose, al, al, &one, Ql, al,
                                             (rocblas_stride)al * al, rin, 1, al, &zero, u, 1, al, (rocblas_int)nodes));
         if (el > 0) {
-            RBCHK(rocblas_dtrsv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_none,
+            RBCHK(rocblas_dtrmv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_none,
                                                 rocblas_diagonal_non_unit, el, Dl, al, (rocblas_stride)al * al, u, 1, al,
                                                 (rocblas_int)nodes));
             RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_none, kl, el, &mone, Dl + el, al,
@@ -1563,7 +1572,7 @@ int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z)
             RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_transpose, kl, el, &mone, Dl + el, al,
                                                 (rocblas_stride)al * al, v + el, 1, al, &one, v, 1, al,
                                                 (rocblas_int)nodes));
-            RBCHK(rocblas_dtrsv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_transpose,
+            RBCHK(rocblas_dtrmv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_transpose,
                                                 rocblas_diagonal_non_unit, el, Dl, al, (rocblas_stride)al * al, v, 1, al,
                                                 (rocblas_int)nodes));
         }

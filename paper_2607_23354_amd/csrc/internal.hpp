@@ -366,9 +366,10 @@ void hodlr_apply(hipStream_t s, const HodlrFactor &H, const double *r, double *z
 // (the leaf size ell at l = L, else the two children's k[l+1]) and orthogonal
 // Q (a x a, column-major) whose last k[l] columns are the node's basis; level
 // 0 is the root, a dense block of a[0] = 2 k[1] unknowns.  Dt holds, per node,
-// the transformed block Q^T D Q after elimination: L_e (the Cholesky factor of
-// the first e = a - k unknowns) top-left, W = D_se L_e^{-T} bottom-left and the
-// Schur complement passed to the parent bottom-right.  Root: Cholesky of its
+// the transformed block Q^T D Q after elimination: L_e^{-1} (the inverse of the
+// Cholesky factor L_e of the first e = a - k unknowns, lower triangle)
+// top-left, W = D_se L_e^{-T} bottom-left and the Schur complement passed to
+// the parent bottom-right.  Root: Cholesky of its
 // block.  ub/xb: per-level work vectors of the apply.
 struct HssFactor {
     int64_t n = 0, npad = 0;
