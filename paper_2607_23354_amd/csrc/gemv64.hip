@@ -234,6 +234,8 @@ __device__ __forceinline__ void zmv_sym_body(const double *__restrict__ X, int64
 // Block I of y (rows r0 .. r0 + TS): sum of the row sums of tiles (I, 0..I)
 // and the column sums of tiles (I+1..T-1, I), in that order.  mode 0: y = Z v;
 // mode 1: y = b - Z v (b == NULL: ones) and blkmax[I] = max |y| over the block.
+// m <= 3: the entry loop fits 128 VGPRs, so four workgroups share a CU (more
+// waves to hide the FP64 latency); larger m keeps its coordinates in registers.
 template <int M, int ENT = kEntExp>
 __global__ void __launch_bounds__(256, (M >= 1 && M <= 3) ? 4 : 1)
 k_zmv_sym(const double *__restrict__ X, int64_t n, int m_rt, double t, const double *__restrict__ v,
