@@ -105,15 +105,18 @@ __global__ void __launch_bounds__(NT) k_omega(double *__restrict__ Om, int64_t n
 // per 64-row block of R and NS slabs; Z is formed 64 x (64 / NS) at a time in
 // LDS and applied to all NS slabs, so each entry's exp is evaluated once per
 // NS slabs.  Every output sums over c in ascending order whatever NS is.
-template <int NS>
+template <int NS, int M>
 __global__ void __launch_bounds__(NT)
-k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restrict__ bnd, int mode,
+k_zblock(const double *__restrict__ Xp, int m_rt, double t, const int64_t *__restrict__ bnd, int mode,
          int rbmax, const double *B, double *out, int ld)
 {
+    // M > 0: compile-time dimension (straight-line distance code); M = 0: m_rt <= MMAXH
+    constexpr int MM = (M > 0) ? M : MMAXH;
+    const int m = (M > 0) ? M : m_rt;
     constexpr int CC = ZC / NS;  // points per chunk
     __shared__ double Bs[CC][NS * SL];
     __shared__ double Zs[ZR][CC + 1];
-    __shared__ double Xc[MMAXH][CC];
+    __shared__ double Xc[MM][CC];
     const int task = blockIdx.x / rbmax, rb = blockIdx.x % rbmax;
     const int col0 = blockIdx.y * NS * SL;
     const int64_t a = bnd[2 * task], b = bnd[2 * task + 1], c = bnd[2 * task + 2];
@@ -125,9 +128,9 @@ k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restri
     const int tid = threadIdx.x;
     const int gr = tid & 63, gp = tid >> 6;  // Z-tile generation: row, group of CC / 4 points
     const int ty = tid >> 4, tx = tid & 15;  // accumulation: rows 4ty.., columns 4tx.. of each slab
-    double xr[MMAXH];
+    double xr[MM];
 #pragma unroll
-    for (int l = 0; l < MMAXH; ++l) xr[l] = (l < m && gr < nr) ? Xp[(r0 + gr) * m + l] : 0.0;
+    for (int l = 0; l < MM; ++l) xr[l] = (l < m && gr < nr) ? Xp[(r0 + gr) * m + l] : 0.0;
     double acc[NS][4][4];
 #pragma unroll
     for (int u = 0; u < NS; ++u)
@@ -152,9 +155,10 @@ k_zblock(const double *__restrict__ Xp, int m, double t, const int64_t *__restri
             const int p = gp * (CC / 4) + q;
             double s = 0.0;
 #pragma unroll
-            for (int l = 0; l < MMAXH; ++l)
-                if (l < m) s = sq_acc(s, xr[l] - Xc[l][p]);
-            Zs[gr][p] = (p < cnt && gr < nr) ? zexp(t, s) : 0.0;
+            for (int l = 0; l < MM; ++l)
+                if (M > 0 || l < m) s = sq_acc(s, xr[l] - Xc[l][p]);
+            const double z = zexp(t, s);  // evaluated for padding too, then selected
+            Zs[gr][p] = (p < cnt && gr < nr) ? z : 0.0;
         }
         __syncthreads();
 #pragma unroll 4
@@ -193,15 +197,17 @@ void launch_zblock(hipStream_t s, const double *Xp, int m, double t, const int64
 {
     const int slabs = cols / SL;
     const unsigned gx = (unsigned)(tasks * rbmax);
-    if (slabs % 4 == 0)
-        hipLaunchKernelGGL(k_zblock<4>, dim3(gx, (unsigned)(slabs / 4)), dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax,
-                           B, out, ld);
-    else if (slabs % 2 == 0)
-        hipLaunchKernelGGL(k_zblock<2>, dim3(gx, (unsigned)(slabs / 2)), dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax,
-                           B, out, ld);
-    else
-        hipLaunchKernelGGL(k_zblock<1>, dim3(gx, (unsigned)slabs), dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B,
-                           out, ld);
+    const int ns = (slabs % 4 == 0) ? 4 : (slabs % 2 == 0) ? 2 : 1;
+    const dim3 g(gx, (unsigned)(slabs / ns));
+    if (m == 3) {
+        if (ns == 4) hipLaunchKernelGGL((k_zblock<4, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
+        else if (ns == 2) hipLaunchKernelGGL((k_zblock<2, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
+        else hipLaunchKernelGGL((k_zblock<1, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
+    } else {
+        if (ns == 4) hipLaunchKernelGGL((k_zblock<4, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
+        else if (ns == 2) hipLaunchKernelGGL((k_zblock<2, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
+        else hipLaunchKernelGGL((k_zblock<1, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
+    }
 }
 
 // Row range of task i: [bnd[ts*i + to], bnd[ts*i + to + 1]).
