@@ -80,6 +80,10 @@ def lib():
         L.orc_chol_solve.argtypes = [_D, ctypes.c_int64, _D, _D]
         L.orc_residual.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D,
                                    _I64, ctypes.c_int64, _D]
+        L.orc_residual_rhs.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D,
+                                       _I64, ctypes.c_int64, _D]
+        L.orc_solve_refine.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D,
+                                       ctypes.c_int, _D, _D]
         L.orc_zmatvec.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D]
         L.orc_dzmatvec.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D]
         L.orc_grad_x.argtypes = [_D, ctypes.c_int64, ctypes.c_int, ctypes.c_double, _D, _D, _D]
@@ -170,13 +174,26 @@ def chol_solve(L, b) -> np.ndarray:
     return x
 
 
-def residual(X, t: float, w, rows=None) -> np.ndarray:
-    """r = 1 - Z w with Z regenerated from X, accumulated with Dot2
-    (compensated: as if computed in doubled precision).  ``rows`` selects a
-    subset of rows."""
+def residual(X, t: float, w, rows=None, b=None) -> np.ndarray:
+    """r = 1 - Z w (or b - Z w for a given right-hand side b) with Z
+    regenerated from X, accumulated with Dot2 (compensated: as if computed in
+    doubled precision).  ``rows`` selects a subset of rows."""
     X = _pts(X)
     n, m = X.shape
     w = np.ascontiguousarray(w, dtype=np.float64)
+    if b is not None:
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        if b.shape != (n,):
+            raise ValueError("b must have one entry per point")
+        if rows is None:
+            r = np.empty(n)
+            lib().orc_residual_rhs(_p(X), n, m, float(t), _p(b), _p(w), None, 0, _p(r))
+        else:
+            rows = np.ascontiguousarray(rows, dtype=np.int64)
+            r = np.empty(len(rows))
+            lib().orc_residual_rhs(_p(X), n, m, float(t), _p(b), _p(w), rows.ctypes.data_as(_I64),
+                                   len(rows), _p(r))
+        return r
     if rows is None:
         r = np.empty(n)
         lib().orc_residual(_p(X), n, m, float(t), _p(w), None, 0, _p(r))
@@ -227,12 +244,13 @@ class Weighting:
         self.min_w = float(w[self.argmin])
 
     def solve(self, b, refine: int = 2):
-        """Z^{-1} b with the stored factor plus Dot2-residual refinement."""
+        """Z^{-1} b with the stored factor plus refinement steps whose
+        residuals b - Z x are Dot2 sums started from b (never through 1 - Z x,
+        which would round away the compensated part when b != 1)."""
         b = np.ascontiguousarray(b, dtype=np.float64)
-        x = chol_solve(self.L, b)
-        for _ in range(refine):
-            r = b - (1.0 - residual(self.X, self.t, x))  # b - Z x, with Z x = 1 - (1 - Z x)
-            x = x + chol_solve(self.L, r)
+        n, m = self.X.shape
+        x = np.empty(n)
+        lib().orc_solve_refine(_p(self.X), n, m, float(self.t), _p(self.L), _p(b), int(refine), None, _p(x))
         return x
 
 
@@ -299,10 +317,11 @@ def dist_residual(X, u, rows=None) -> np.ndarray:
 # Conditioning (Section 4.2 sanity check; acceptance domain of the tests)
 # --------------------------------------------------------------------------
 
-def cond_estimate(sol: Weighting, iters: int = 200, seed: int = 12345):
+def cond_estimate(sol: Weighting, iters: int = 200, seed: int = 12345, rtol: float = 1e-10):
     """(lambda_max, lambda_min, cond) of Z: power iteration with Z for
     lambda_max, inverse iteration through the factor for lambda_min
-    (Rayleigh quotients)."""
+    (Rayleigh quotients; each side stops when its estimate changes by at most
+    rtol relative, or after ``iters`` steps)."""
     X, t = sol.X, sol.t
     n = X.shape[0]
     rng = np.random.default_rng(seed)
@@ -313,7 +332,7 @@ def cond_estimate(sol: Weighting, iters: int = 200, seed: int = 12345):
         y = zmatvec(X, t, v)
         lmax_new = float(v @ y)
         v = y / np.linalg.norm(y)
-        if abs(lmax_new - lmax) <= 1e-10 * abs(lmax_new):
+        if abs(lmax_new - lmax) <= rtol * abs(lmax_new):
             lmax = lmax_new
             break
         lmax = lmax_new
@@ -324,7 +343,7 @@ def cond_estimate(sol: Weighting, iters: int = 200, seed: int = 12345):
         y = chol_solve(sol.L, u)
         mu_new = float(u @ y)  # approx 1/lambda_min
         u = y / np.linalg.norm(y)
-        if abs(mu_new - mu) <= 1e-10 * abs(mu_new):
+        if abs(mu_new - mu) <= rtol * abs(mu_new):
             mu = mu_new
             break
         mu = mu_new

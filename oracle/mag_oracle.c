@@ -191,6 +191,28 @@ void orc_residual(const double *X, int64_t n, int m, double t, const double *w,
     }
 }
 
+/* Residual r_j = b_j - sum_k Z_jk x_k for a general right-hand side b, by the
+ * same Dot2 accumulation as orc_residual (the sum starts from b_j, which is
+ * exact).  Used for the solves Z x = b of the gradient (b = gM 1 + gw) and of
+ * dw/dt (b = (D o Z) w).  rows == NULL means all n rows. */
+void orc_residual_rhs(const double *X, int64_t n, int m, double t, const double *b, const double *x,
+                      const int64_t *rows, int64_t nrows, double *r)
+{
+    int64_t cnt = rows ? nrows : n;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t i = 0; i < cnt; ++i) {
+        int64_t j = rows ? rows[i] : i;
+        double s = b[j], c = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            double p, ep, q;
+            two_prod(zentry(X, m, t, j, k), -x[k], &p, &ep);
+            two_sum(s, p, &s, &q);
+            c = c + (q + ep);
+        }
+        r[i] = s + c;
+    }
+}
+
 /* Plain matrix-vector products with Z regenerated from X, ascending k. */
 void orc_zmatvec(const double *X, int64_t n, int m, double t, const double *v, double *y)
 {
@@ -274,6 +296,33 @@ double orc_sum(const double *v, int64_t n)
         s = u;
     }
     return s + c;
+}
+
+/* Solve Z x = b given the lower Cholesky factor L of Z (row-major lower
+ * triangle of an n x n array; the strict upper triangle is never read):
+ * x = L^{-T} L^{-1} b, then `refine` steps x <- x + L^{-T} L^{-1} r with the
+ * Dot2 residual r = b - Z x (Z regenerated from X).  b == NULL means the ones
+ * vector of eq. weighting.  x_plain (may be NULL) receives the unrefined x. */
+void orc_solve_refine(const double *X, int64_t n, int m, double t, const double *L, const double *b,
+                      int refine, double *x_plain, double *x)
+{
+    double *rhs = (double *)malloc((size_t)n * sizeof(double));
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *dx = (double *)malloc((size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        rhs[i] = b ? b[i] : 1.0;
+    orc_chol_solve(L, n, rhs, x);
+    if (x_plain)
+        memcpy(x_plain, x, (size_t)n * sizeof(double));
+    for (int it = 0; it < refine; ++it) {
+        orc_residual_rhs(X, n, m, t, rhs, x, NULL, 0, r);
+        orc_chol_solve(L, n, r, dx);
+        for (int64_t i = 0; i < n; ++i)
+            x[i] = x[i] + dx[i];
+    }
+    free(rhs);
+    free(r);
+    free(dx);
 }
 
 /* Weighting by a dense FP64 solve of Z w = 1 (eq. weighting):

@@ -452,3 +452,85 @@ def test_scale_zero_dist_residual_exact_rational():
             D[j][k] = Fraction(dd)
     exact = [float(1 - sum(D[j][k] * Fraction(u[k]) for k in range(4))) for j in range(4)]
     assert oracle.dist_residual(X, u).tolist() == exact
+
+
+# ---------------------------------------------------------------- general right-hand side, kappa_M, LAPACK factor
+
+def test_residual_rhs_dot2_exact_rational():
+    # b - Z x by Dot2 vs exact rational arithmetic on the same FP64 entries, for a
+    # right-hand side other than 1 (the gradient's lambda = Z^{-1}(gM 1 + gw))
+    X = W.gaussian(30, 3, seed=21)
+    t = 0.9
+    rng = np.random.default_rng(22)
+    b = rng.standard_normal(30) * 10.0 ** rng.integers(-6, 6, 30)
+    x = rng.standard_normal(30)
+    Z = oracle.zmatrix(X, t)
+    r = oracle.residual(X, t, x, b=b)
+    for j in range(30):
+        terms = [Fraction(Z[j, k]) * Fraction(x[k]) for k in range(30)]
+        ex = float(Fraction(b[j]) - sum(terms))
+        bound = 2.0 ** -52 * abs(ex) + 1e-28 * (abs(b[j]) + float(sum(abs(q) for q in terms)))
+        assert abs(r[j] - ex) <= bound, (j, r[j], ex)
+    rows = np.array([29, 4, 0])
+    assert np.array_equal(oracle.residual(X, t, x, rows, b=b), r[rows])
+    # b = 1 reduces to the ones residual exactly
+    assert np.array_equal(oracle.residual(X, t, x, b=np.ones(30)), oracle.residual(X, t, x))
+
+
+@pytest.mark.parametrize("n,m,t", [(200, 3, 0.4), (150, 2, 3.0)])
+def test_weighting_solve_general_rhs_vs_lapack(n, m, t):
+    # Weighting.solve(b) = Z^{-1} b against LAPACK on numpy's Z, for b far from 1
+    X = W.gaussian(n, m, seed=n + m)
+    s = oracle.weighting(X, t)
+    b = np.random.default_rng(23).standard_normal(n) * 1e3
+    x = s.solve(b)
+    Z = np.exp(-t * scipy.spatial.distance.cdist(X, X))
+    xr = scipy.linalg.solve(Z, b, assume_a="pos")
+    ev = np.linalg.eigvalsh(Z)
+    # both answers lie within cond * u of Z^{-1} b (scaled by |x|)
+    assert np.abs(x - xr).max() <= 50 * (ev[-1] / ev[0]) * 2.0 ** -53 * np.abs(xr).max()
+    # the refined answer's Dot2 residual is at unit roundoff of |Z||x| + |b|
+    scale = np.abs(Z) @ np.abs(x) + np.abs(b)
+    assert np.all(np.abs(oracle.residual(X, t, x, b=b)) <= 4 * 2.0 ** -53 * scale)
+
+
+def _kgon_parts(k, t):
+    q = np.exp(-t)
+    S = 1 + sum(np.exp(-2 * t * np.sin(np.pi * j / k)) for j in range(1, k))
+    wc = (S - k * q) / (S - k * q * q)
+    wr = (1 - q) / (S - k * q * q)
+    return q, S, wc, wr
+
+
+@pytest.mark.parametrize("k,t", [(6, 0.5), (8, 0.7), (12, 1.0), (24, 0.9)])
+def test_kappa_M_kgon_closed_form(k, t):
+    # below t_+ the centre weight is negative; |w|^T Z |w| over centre and ring is
+    # w_c^2 + 2 k |w_c| w_r e^{-t} + k S w_r^2 (each ring row sums to S over the ring)
+    q, S, wc, wr = _kgon_parts(k, t)
+    assert wc < 0  # t below the k-gon's cutoff
+    kappa = (wc * wc + 2 * k * abs(wc) * wr * q + k * S * wr * wr) / abs(wc + k * wr)
+    s = oracle.weighting(W.centre_kgon(k), t)
+    assert oracle.kappa_M(s) == pytest.approx(kappa, rel=1e-12)
+    assert kappa > 1.0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_kappa_M_is_one_for_nonnegative_weights(seed):
+    # w >= 0 gives |w| = w and w^T Z w = 1^T w (the q = 2 diversity identity)
+    X = W.gaussian(120, 3, seed=30 + seed)
+    s = oracle.weighting(X, oracle.t_bound(X))
+    assert s.min_w >= 0
+    assert oracle.kappa_M(s) == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("n,m,t", [(250, 3, 0.3), (180, 2, 1.5)])
+def test_kappa_M_vs_numpy(n, m, t):
+    # with negative weights (t well below t_+) against numpy's own |w|^T Z |w| / |M|
+    X = W.gaussian(n, m, seed=40 + n)
+    s = oracle.weighting(X, t)
+    assert s.min_w < 0
+    Z = np.exp(-t * scipy.spatial.distance.cdist(X, X))
+    aw = np.abs(s.w)
+    ref = float(aw @ Z @ aw) / abs(float(np.sum(s.w)))
+    assert oracle.kappa_M(s) == pytest.approx(ref, rel=1e-11)
+    assert oracle.kappa_M(s) > 1.0
