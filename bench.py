@@ -53,6 +53,41 @@ def counter_traffic(n):
         return None
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "full_size")
+METRIC_SCALES = ("tstar", "tstar_over4", "tstar_over2", "tstar_x2", "t_b")
+
+
+def per_scale_errors(mag, Xd, ctx, w):
+    """relerr_w = |w - w_oracle|_inf / |w_oracle|_inf and relerr_M against the
+    oracle's weighting of the metric cloud at t*, t*/4, t*/2, 2 t*, t_b."""
+    import numpy as np
+    try:
+        with open(os.path.join(GOLDEN, "index.json")) as f:
+            index = json.load(f)
+    except OSError:
+        return None
+    out = []
+    for sc in METRIC_SCALES:
+        rec = index.get(f"gauss_n32768_m3_seed0_{sc}")
+        if rec is None:
+            continue
+        wg = np.load(os.path.join(GOLDEN, rec["w_file"]), allow_pickle=False)
+        t0 = time.perf_counter()
+        r = mag.weighting(Xd, rec["t"], ctx=ctx, out=w, solver="fp32_ir")
+        wh = w.cpu().numpy()
+        ms = (time.perf_counter() - t0) * 1e3
+        out.append({"scale": sc, "t": rec["t"],
+                    "relerr_w": float(np.abs(wh - wg).max() / np.abs(wg).max()),
+                    "relerr_M": abs(r.info["magnitude"] - rec["M"]) / abs(rec["M"]),
+                    "resid_inf_device": r.info["resid_inf"], "outer_iters": r.info["outer_iters"],
+                    "gmres_iters": r.info["gmres_iters"], "min_w": r.info["min_w"],
+                    "kappa_M_oracle": rec["kappa_M"], "cond_est_oracle": rec["cond_est"],
+                    "ms_wall": ms})
+        print(f"[bench] scale {sc}: t={rec['t']:.6g} relerr_w={out[-1]['relerr_w']:.2e} "
+              f"relerr_M={out[-1]['relerr_M']:.2e}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,7 +97,9 @@ def main():
     ap.add_argument("--m", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--dense-steps", type=int, default=2)
-    ap.add_argument("--cpu-sample-n", type=int, default=8192)
+    ap.add_argument("--cpu-sample-n", type=int, default=16384)
+    ap.add_argument("--no-scales", action="store_true",
+                    help="skip the per-scale comparison with the oracle's expected weightings")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--check-rows", type=int, default=512)
@@ -160,6 +197,8 @@ def main():
             dense = {
                 "ms_per_solve": dms,
                 "ms_potrf": dinfo["ms_factor"],
+                # the comparator at the FP64 MFMA peak would still need n^3/3 flops there
+                "ms_fp64_peak_floor": factor_flops / (FP64_MFMA_PEAK_TFLOPS * 1e12) * 1e3,
                 "potrf_frac_fp64_peak": factor_flops / (dinfo["ms_factor"] * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
                 "resid_inf_device": dinfo["resid_inf"],
                 "resid_inf_sampled_oracle": float(np.abs(oracle.residual(X, t, w_dense, rows)).max()),
@@ -169,6 +208,13 @@ def main():
             print(f"[bench] fp64_dense {dms:.2f} ms/solve", file=sys.stderr, flush=True)
         except Exception as e:  # report, do not hide
             dense = {"error": repr(e)}
+
+    # error of w and of M = 1^T w against the oracle at every scale of the metric
+    # cloud (expected values written by tests/golden/make_full_size.py from the
+    # oracle alone; one untimed solve per scale)
+    scales = None
+    if not args.no_scales and n == 32768 and m == 3 and args.seed == 0:
+        scales = per_scale_errors(mag, Xd, ctx, w)
 
     # the positive-definiteness check of the same workload (Lanczos on Z and Z^{-1});
     # reported beside the metric, never part of it
@@ -259,6 +305,8 @@ def main():
                   "min_w": last["min_w"], "shifted": last["shifted"]},
         "fp64_dense": dense,
         "speedup_vs_fp64_dense": (dense["ms_per_solve"] / ms_per_step) if dense and "ms_per_solve" in dense else None,
+        "speedup_vs_fp64_peak_floor": (factor_flops / (FP64_MFMA_PEAK_TFLOPS * 1e12) * 1e3) / ms_per_step,
+        "per_scale_vs_oracle": scales,
         "eig_extremes": eig,
         "weighting_zero": zero,
         "cpu_baseline": cpu,

@@ -51,6 +51,15 @@ typedef struct mag_ctx mag_ctx;
  * (grown on demand, reused across calls, released by mag_destroy). */
 int mag_create(mag_ctx **ctx, int device);
 void mag_destroy(mag_ctx *ctx);
+/* Cap the device memory this context may hold at `bytes` (0 = no cap, the
+ * default unless the environment variable MAG_WORKSPACE_LIMIT holds a byte
+ * count, optionally with a K, M or G suffix, when the context is created).
+ * A call whose workspace would exceed the cap returns MAG_ENOMEM without
+ * allocating; buffers already held are kept.  *held (HOST, may be NULL)
+ * receives the bytes held now. */
+int mag_set_workspace_limit(mag_ctx *ctx, uint64_t bytes);
+int mag_workspace_bytes(const mag_ctx *ctx, uint64_t *held);
+
 /* Enqueue subsequent work on `hip_stream` (a hipStream_t; NULL = the
  * context's own stream, a blocking stream: it is ordered with the device's
  * null stream, so work a caller enqueues there -- e.g. PyTorch's default
@@ -59,8 +68,13 @@ int mag_set_stream(mag_ctx *ctx, void *hip_stream);
 
 /* ---- options and diagnostics --------------------------------------------- */
 enum {
-    MAG_AUTO = 0,        /* MAG_FP32_IR when its FP32 npad^2 factor fits in 3/4 of the    *
-                          * device memory, else MAG_HODLR                                */
+    MAG_AUTO = 0,        /* by measured cost: MAG_FP32_IR up to n = 65536 (its FP32      *
+                          * factor's n^3/3 flops on MFMA are the cheaper solve there),  *
+                          * MAG_HODLR above (max_rank 512, GMRES(100), up to 400 inner  *
+                          * iterations; at n = 131072 it takes 2.0-2.3 s against 5.9 s *
+                          * for the dense factor) when m <= 16; if the HODLR solve does  *
+                          * not converge, or m > 16, MAG_FP32_IR when its npad^2 factor  *
+                          * fits in 3/4 of the device memory, else MAG_ENOMEM            */
     MAG_FP64_DENSE = 1,  /* FP64 Z in HBM + rocSOLVER dpotrf/dpotrs (dense comparator)   */
     MAG_FP32_IR = 2,     /* FP32 MFMA Cholesky + FP64 GMRES iterative refinement         */
     MAG_HODLR = 3,       /* HODLR preconditioner + FP64 GMRES (largest sizes, Sec. 3.2): *
@@ -97,10 +111,18 @@ typedef struct {
                             * entry exp(-t d) in FP32 (sums in FP64; m <= 16, else FP64)   *
                             * and ask at most a 1e-6 reduction of each inner solve; the    *
                             * residuals 1 - Z w that decide convergence stay FP64          */
+    int32_t diag;          /* diagnostics of mag_weighting / mag_magnitude, default 0:      *
+                            * MAG_DIAG_BACKWARD fills mag_info.backward_err (one more       *
+                            * FP64 product Z 1); MAG_DIAG_COND fills mag_info.cond_est      *
+                            * (Lanczos on Z and on Z^{-1} through the solve's own           *
+                            * preconditioner, to 1e-3 relative; about 10 extra products     *
+                            * and 10 extra refinement solves)                              */
 } mag_opts;
 
 #define MAG_INNER_FP64 0
 #define MAG_INNER_FP32 1
+#define MAG_DIAG_BACKWARD 1
+#define MAG_DIAG_COND 2
 
 /* Fill *opts with the defaults above. */
 void mag_opts_default(mag_opts *opts);
@@ -122,7 +144,11 @@ typedef struct {
     double ms_update;      /* summed device time of the trailing-update kernel launches   */
     double flop_update;    /* algorithmic flops of those launches                         */
     int32_t n_update;      /* number of trailing-update launches                          */
-    int32_t pad_;
+    int32_t solver;        /* the solver that ran (MAG_AUTO resolved)                      */
+    double backward_err;   /* ||1 - Z w||_inf / (||Z||_inf ||w||_inf + 1), the normwise    *
+                            * backward error (MAG_DIAG_BACKWARD; else 0)                   */
+    double cond_est;       /* lambda_max(Z) / lambda_min(Z) estimated by Lanczos to 1e-3   *
+                            * relative (MAG_DIAG_COND; else 0)                              */
 } mag_info;
 
 /* ---- the weighting (eq. weighting) ---------------------------------------- */

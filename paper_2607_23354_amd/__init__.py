@@ -26,6 +26,9 @@ __all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "
 
 SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
            "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR, "hss": _lib.MAG_HSS}
+SOLVER_NAMES = {v: k for k, v in SOLVERS.items()}
+DIAG_BACKWARD = 1
+DIAG_COND = 2
 
 
 def _ptr(t: torch.Tensor | None):
@@ -51,6 +54,16 @@ class Context:
         h = ctypes.c_void_p()
         _lib.check(self.lib.mag_create(ctypes.byref(h), self.device), "mag_create")
         self.handle = h
+
+    def set_workspace_limit(self, nbytes: int) -> None:
+        """Cap the device memory this context may hold (0 = no cap); calls that
+        would exceed it fail with MAG_ENOMEM."""
+        _lib.check(self.lib.mag_set_workspace_limit(self.handle, int(nbytes)), "mag_set_workspace_limit")
+
+    def workspace_bytes(self) -> int:
+        held = ctypes.c_uint64()
+        _lib.check(self.lib.mag_workspace_bytes(self.handle, ctypes.byref(held)), "mag_workspace_bytes")
+        return int(held.value)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -95,7 +108,7 @@ def make_opts(solver: str = "auto", tol: float = 1e-12, max_outer: int | None = 
               gmres_restart: int | None = None, max_gmres: int | None = None,
               inner_tol: float | None = None, profile: bool = False, leaf: int | None = None,
               max_rank: int | None = None, oversample: int | None = None,
-              seed: int | None = None, inner_prec: str = "fp64") -> MagOpts:
+              seed: int | None = None, inner_prec: str = "fp64", diag: int = 0) -> MagOpts:
     o = MagOpts()
     _lib.load().mag_opts_default(ctypes.byref(o))
     o.solver = SOLVERS[solver]
@@ -120,6 +133,7 @@ def make_opts(solver: str = "auto", tol: float = 1e-12, max_outer: int | None = 
     if inner_prec not in ("fp64", "fp32"):
         raise ValueError(f"inner_prec must be 'fp64' or 'fp32', not {inner_prec!r}")
     o.inner_prec = 0 if inner_prec == "fp64" else 1
+    o.diag = int(diag)
     return o
 
 

@@ -41,6 +41,7 @@ class MagOpts(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("inner_prec", ctypes.c_int32),
+        ("diag", ctypes.c_int32),
     ]
 
 
@@ -62,11 +63,13 @@ class MagInfo(ctypes.Structure):
         ("ms_update", ctypes.c_double),
         ("flop_update", ctypes.c_double),
         ("n_update", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("solver", ctypes.c_int32),
+        ("backward_err", ctypes.c_double),
+        ("cond_est", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class MagTplusOpts(ctypes.Structure):
@@ -137,6 +140,8 @@ SIGNATURES = {
     "mag_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int]),
     "mag_destroy": (None, [_vp]),
     "mag_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "mag_set_workspace_limit": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "mag_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
     "mag_opts_default": (None, [ctypes.POINTER(MagOpts)]),
     "mag_weighting": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, ctypes.POINTER(MagOpts),
                                      ctypes.POINTER(MagInfo)]),

@@ -28,9 +28,27 @@
 namespace mag {
 
 
+size_t ctx_held_bytes(const mag_ctx *c)
+{
+    size_t sum = 0;
+    for (const DevBuf *b : {&c->factor, &c->dinv, &c->vecs, &c->partial, &c->ints, &c->aux, &c->bfactor,
+                            &c->bdinv, &c->bvec, &c->bscal, &c->bpartial, &c->bints, &c->bdesc, &c->barena,
+                            &c->bstage, &c->hodlr, &c->eig, &c->hss})
+        sum += b->bytes;
+    return sum;
+}
+
+int ctx_may_allocate(const mag_ctx *c, size_t extra)
+{
+    if (c->ws_limit == 0) return MAG_OK;
+    return ctx_held_bytes(c) + extra <= c->ws_limit ? MAG_OK : MAG_ENOMEM;
+}
+
 int ensure(mag_ctx *ctx, DevBuf &b, size_t bytes)
 {
     if (bytes <= b.bytes) return MAG_OK;
+    // the cap counts the buffer at its new size in place of its old one
+    if (ctx->ws_limit && ctx_held_bytes(ctx) - b.bytes + bytes > ctx->ws_limit) return MAG_ENOMEM;
     if (b.p) {
         if (hipStreamSynchronize(ctx->stream) != hipSuccess) return MAG_EHIP;
         hipFree(b.p);
@@ -437,6 +455,39 @@ int ensure_ctx_factor(mag_ctx *ctx, int64_t n)
     return MAG_OK;
 }
 
+using SolveOp = std::function<int(const double *, double *)>;
+int ensure_aux(mag_ctx *ctx, int64_t npad);
+struct LanczosResult;
+int lanczos_top(mag_ctx *ctx, int64_t npad, const SolveOp &op, double *Q, double *u, double *dev, int max_iter,
+                double rtol, LanczosResult &res);
+
+// Normwise backward error of the weighting w (device, n):
+// ||1 - Z w||_inf / (||Z||_inf ||w||_inf + ||1||_inf), with ||Z||_inf the
+// largest entry of Z 1 (every entry of Z is positive) from one FP64 product.
+int diag_backward(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const double *w, double rinf,
+                  double &eta)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure_aux(ctx, npad));
+    double *aux = (double *)ctx->aux.p;
+    double *partial = (double *)ctx->partial.p;
+    double *dsc = aux + 4 * npad;
+    launch_affine_ones(s, nullptr, 1.0, aux, n, npad);
+    launch_zmv(s, X, n, m, t, aux, aux + npad, nullptr, 0, partial, nullptr);
+    launch_amax(s, aux + npad, npad, partial, dsc);
+    launch_amax(s, w, n, partial, dsc + 1);
+    HIPCHK(hipMemcpyAsync(ctx->host_scalars + 48, dsc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    eta = rinf / (ctx->host_scalars[48] * ctx->host_scalars[49] + 1.0);
+    return MAG_OK;
+}
+
+// lambda_max(Z) / lambda_min(Z) by Lanczos to relative accuracy 1e-3: on Z
+// with matrix-free FP64 products, and on Z^{-1} with `inv` (a solve with the
+// caller's preconditioner), from the golden-ratio start vector.
+int diag_cond(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const SolveOp &inv, double &cond);
+
 // FP32-factor + FP64 GMRES iterative refinement for Z w = 1, into the
 // caller's w (n) -- optionally factorising into caller-provided buffers.
 int solve_fp32_ir(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double *w,
@@ -494,6 +545,18 @@ int solve_fp32_ir(mag_ctx *ctx, const double *X, int64_t n, int m, double t, dou
             info->ms_update = msu;
             info->flop_update = fl;
             info->n_update = (int32_t)(ft.used / 2);
+        }
+        info->solver = MAG_FP32_IR;
+        if (o.diag & MAG_DIAG_BACKWARD) CHK(diag_backward(ctx, X, n, m, t, w, st.resid, info->backward_err));
+        if (o.diag & MAG_DIAG_COND) {
+            mag_opts oi = o;
+            oi.tol = 1e-6;
+            const SolveOp inv = [&](const double *in, double *out) -> int {
+                RefineStats s2;
+                const int r2 = refine_solve(ctx, X, n, m, t, F, in, 1.0, out, oi, s2);
+                return r2 == MAG_ENOCONV ? MAG_OK : r2;
+            };
+            CHK(diag_cond(ctx, X, n, m, t, inv, info->cond_est));
         }
     }
     for (auto e : ft.ev) hipEventDestroy(e);
@@ -556,6 +619,18 @@ int solve_fp64_dense(mag_ctx *ctx, const double *X, int64_t n, int m, double t, 
             info->ms_refine = tm.ms(2, 3);
             info->ms_total = tm.ms(0, 3);
         }
+        info->solver = MAG_FP64_DENSE;
+        if (o.diag & MAG_DIAG_BACKWARD) CHK(diag_backward(ctx, X, n, m, t, w, info->resid_inf, info->backward_err));
+        if (o.diag & MAG_DIAG_COND) {
+            const SolveOp inv = [&](const double *in, double *out) -> int {
+                HIPCHK(hipMemcpyAsync(out, in, sizeof(double) * round_up(n, kPad), hipMemcpyDeviceToDevice, s));
+                if (rocsolver_dpotrs(h, rocblas_fill_lower, (rocblas_int)n, 1, A, (rocblas_int)n, out,
+                                     (rocblas_int)n) != rocblas_status_success)
+                    return MAG_EHIP;
+                return MAG_OK;
+            };
+            CHK(diag_cond(ctx, X, n, m, t, inv, info->cond_est));
+        }
     }
     return MAG_OK;
 }
@@ -601,6 +676,18 @@ int solve_hodlr(mag_ctx *ctx, const double *X, int64_t n, int m, double t, doubl
             info->ms_factor = tm.ms(0, 1);
             info->ms_refine = tm.ms(2, 3);
             info->ms_total = tm.ms(0, 4);
+        }
+        info->solver = MAG_HODLR;
+        if (o.diag & MAG_DIAG_BACKWARD) CHK(diag_backward(ctx, X, n, m, t, w, st.resid, info->backward_err));
+        if (o.diag & MAG_DIAG_COND) {
+            mag_opts oi = o;
+            oi.tol = 1e-6;
+            const SolveOp inv = [&](const double *in, double *out) -> int {
+                RefineStats s2;
+                const int r2 = refine_core(ctx, X, n, m, t, H.npad, prec, in, 1.0, out, oi, s2);
+                return r2 == MAG_ENOCONV ? MAG_OK : r2;
+            };
+            CHK(diag_cond(ctx, X, n, m, t, inv, info->cond_est));
         }
     }
     return rc;
@@ -656,19 +743,40 @@ int solve_hss(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double 
             info->ms_refine = tm.ms(2, 3);
             info->ms_total = tm.ms(0, 4);
         }
+        info->solver = MAG_HSS;
+        if (o.diag & MAG_DIAG_BACKWARD) CHK(diag_backward(ctx, X, n, m, t, w, st.resid, info->backward_err));
+        if (o.diag & MAG_DIAG_COND) {
+            mag_opts oi = o;
+            oi.tol = 1e-6;
+            const SolveOp inv = [&](const double *in, double *out) -> int {
+                RefineStats s2;
+                const int r2 = refine_core(ctx, X, n, m, t, H.npad, prec, in, 1.0, out, oi, s2);
+                if (prc != MAG_OK) return prc;
+                return r2 == MAG_ENOCONV ? MAG_OK : r2;
+            };
+            CHK(diag_cond(ctx, X, n, m, t, inv, info->cond_est));
+        }
     }
     return rc;
 }
 
-// MAG_AUTO: the dense FP32 factor when its npad^2 floats fit in three quarters
-// of the device memory (counting what this context already holds for it),
-// else the HODLR preconditioner.
+// MAG_AUTO takes the HODLR preconditioner above this size.  Measured on the
+// MI355X (noisy torus and Gaussian clouds): the dense FP32 factor's n^3/3
+// MFMA flops cost 0.11 s at n = 32768 and 5.9 s at n = 131072, where the HODLR
+// solve takes 2.0-2.3 s; the two cross between 65536 and 131072.
+constexpr int64_t kAutoHodlrMinN = 65536;
+
+// Whether the dense FP32 factor's npad^2 floats fit in three quarters of the
+// device memory (counting what this context already holds for it) and in the
+// context's cap.
 bool auto_dense(mag_ctx *ctx, int64_t n)
 {
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return true;
     const double npad = (double)round_up(n, kPad);
-    return 4.0 * npad * npad <= 0.75 * ((double)fr + (double)ctx->factor.bytes);
+    const double need = 4.0 * npad * npad;
+    if (ctx->ws_limit && need > (double)ctx->ws_limit) return false;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return true;
+    return need <= 0.75 * ((double)fr + (double)ctx->factor.bytes);
 }
 
 // dw/dt = Z^{-1} (D o Z) w with the factor F of Z(t) (differentiating
@@ -840,6 +948,37 @@ int lanczos_top(mag_ctx *ctx, int64_t npad, const std::function<int(const double
     return MAG_OK;
 }
 
+int diag_cond(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const SolveOp &inv, double &cond)
+{
+    constexpr int kIters = 40;
+    constexpr double kRtol = 1e-3;
+    hipStream_t s = ctx->stream;
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure(ctx, ctx->partial, std::max(ctx->partial.bytes, sizeof(double) * (blas1_partial_doubles(kIters + 2) + 64))));
+    CHK(ensure(ctx, ctx->eig, sizeof(double) * ((size_t)(kIters + 3) * npad + 2 * (kIters + 2) + 64)));
+    double *Q = (double *)ctx->eig.p;
+    double *u = Q + (size_t)(kIters + 1) * npad;
+    double *q0 = u + npad;
+    double *dev = q0 + npad;
+    double *partial = (double *)ctx->partial.p;
+    launch_golden(s, q0, n, npad);
+    launch_nrm2(s, q0, npad, partial, dev);
+    HIPCHK(hipMemcpyAsync(ctx->host_scalars + 50, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double q0norm = ctx->host_scalars[50];
+    const SolveOp zop = [&](const double *in, double *out) -> int {
+        launch_zmv(s, X, n, m, t, in, out, nullptr, 0, partial, nullptr);
+        return MAG_OK;
+    };
+    LanczosResult top, bot;
+    launch_scale(s, q0, 1.0 / q0norm, Q, npad, npad);
+    CHK(lanczos_top(ctx, npad, zop, Q, u, dev, kIters, kRtol, top));
+    launch_scale(s, q0, 1.0 / q0norm, Q, npad, npad);
+    CHK(lanczos_top(ctx, npad, inv, Q, u, dev, kIters, kRtol, bot));
+    cond = (bot.theta > 0.0) ? top.theta * bot.theta : INFINITY;
+    return MAG_OK;
+}
+
 }  // namespace
 
 struct mag_factor {
@@ -902,6 +1041,24 @@ int tplus_eval(mag_ctx *ctx, const double *X, int64_t n, int m, double t, const 
 
 }  // namespace
 
+namespace {
+// MAG_WORKSPACE_LIMIT: a byte count with an optional K, M or G suffix (powers of
+// 1024); unset, empty or unreadable means no cap.
+size_t workspace_limit_from_env()
+{
+    const char *e = std::getenv("MAG_WORKSPACE_LIMIT");
+    if (!e || !*e) return 0;
+    char *end = nullptr;
+    const double v = std::strtod(e, &end);
+    if (end == e || !(v > 0.0) || !std::isfinite(v)) return 0;
+    double mul = 1.0;
+    if (*end == 'K' || *end == 'k') mul = 1024.0;
+    else if (*end == 'M' || *end == 'm') mul = 1024.0 * 1024.0;
+    else if (*end == 'G' || *end == 'g') mul = 1024.0 * 1024.0 * 1024.0;
+    return (size_t)(v * mul);
+}
+}  // namespace
+
 extern "C" {
 
 const char *mag_strerror(int code)
@@ -934,6 +1091,7 @@ void mag_opts_default(mag_opts *o)
     o->profile = 0;
     o->seed = 0x9E3779B97F4A7C15ull;
     o->inner_prec = MAG_INNER_FP64;
+    o->diag = 0;
 }
 
 int mag_create(mag_ctx **out, int device)
@@ -961,6 +1119,7 @@ int mag_create(mag_ctx **out, int device)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cu_count = cus;
+    c->ws_limit = workspace_limit_from_env();
     if (ensure(c, c->ints, sizeof(int) * kIntsTotal) != MAG_OK) {
         mag_destroy(c);
         return MAG_ENOMEM;
@@ -983,6 +1142,20 @@ void mag_destroy(mag_ctx *c)
     if (c->host_scalars) hipHostFree(c->host_scalars);
     if (c->own_stream) hipStreamDestroy(c->own_stream);
     delete c;
+}
+
+int mag_set_workspace_limit(mag_ctx *c, uint64_t bytes)
+{
+    if (!c) return MAG_EINVAL;
+    c->ws_limit = (size_t)bytes;
+    return MAG_OK;
+}
+
+int mag_workspace_bytes(const mag_ctx *c, uint64_t *held)
+{
+    if (!c || !held) return MAG_EINVAL;
+    *held = (uint64_t)ctx_held_bytes(c);
+    return MAG_OK;
 }
 
 int mag_set_stream(mag_ctx *c, void *stream)
@@ -1127,8 +1300,11 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
     if (opts) o = *opts;
     else mag_opts_default(&o);
     CHK(ensure_common(c, n, std::max(1, o.gmres_restart)));
+    // MAG_AUTO: the HODLR preconditioner above the measured crossover, the dense
+    // FP32 factor below it or when the HODLR solve does not converge
+    const bool auto_hodlr = o.solver == MAG_AUTO && n > kAutoHodlrMinN && m <= 16;
     // the FP32 path's tile generator checks the pairs itself (no separate O(n^2) pass)
-    const bool fp32 = o.solver == MAG_FP32_IR || (o.solver == MAG_AUTO && auto_dense(c, n));
+    const bool fp32 = o.solver == MAG_FP32_IR || (o.solver == MAG_AUTO && !auto_hodlr);
     int rc = check_points(c, X, n, m, !fp32);
     if (rc == MAG_OK && n == 1) {
         launch_fill(c->stream, w, 1, 1.0);
@@ -1136,14 +1312,28 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
         if (info) {
             info->magnitude = 1.0;
             info->min_w = 1.0;
+            info->solver = MAG_FP32_IR;
         }
     } else if (rc == MAG_OK) {
         switch (o.solver) {
         case MAG_FP64_DENSE: rc = solve_fp64_dense(c, X, n, m, t, w, o, info); break;
         case MAG_HODLR: rc = solve_hodlr(c, X, n, m, t, w, o, info); break;
         case MAG_HSS: rc = solve_hss(c, X, n, m, t, w, o, info); break;
-        case MAG_AUTO: rc = fp32 ? solve_fp32_ir(c, X, n, m, t, w, o, info)
-                                 : solve_hodlr(c, X, n, m, t, w, o, info);
+        case MAG_AUTO:
+            if (auto_hodlr) {
+                mag_opts oh = o;
+                oh.max_rank = std::max(oh.max_rank, 512);
+                oh.gmres_restart = std::max(oh.gmres_restart, 100);
+                oh.max_gmres = std::max(oh.max_gmres, 400);
+                oh.max_outer = std::max(oh.max_outer, 30);
+                CHK(ensure_common(c, n, oh.gmres_restart));
+                rc = solve_hodlr(c, X, n, m, t, w, oh, info);
+                if (rc == MAG_ENOCONV && auto_dense(c, n)) rc = solve_fp32_ir(c, X, n, m, t, w, o, info);
+            } else if (auto_dense(c, n)) {
+                rc = solve_fp32_ir(c, X, n, m, t, w, o, info);
+            } else {
+                rc = MAG_ENOMEM;
+            }
             break;
         case MAG_FP32_IR: rc = solve_fp32_ir(c, X, n, m, t, w, o, info); break;
         default: rc = MAG_EINVAL; break;
@@ -1164,6 +1354,7 @@ int mag_magnitude(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
     if (!wbuf) {
         if (!valid_args(X, n, m, t)) return MAG_EINVAL;
         HIPCHK(hipSetDevice(c->device));
+        CHK(ctx_may_allocate(c, sizeof(double) * n));
         if (hipMalloc(&tmp.p, sizeof(double) * n) != hipSuccess) return MAG_ENOMEM;
         wbuf = (double *)tmp.p;
     }
@@ -1682,6 +1873,10 @@ int mag_weighting_fwd(mag_ctx *c, const double *X, int64_t n, int32_t m, double 
     else mag_opts_default(&o);
     CHK(ensure_solver(c, n, m, std::max(1, o.gmres_restart)));
     CHK(check_points(c, X, n, m));
+    {
+        const size_t np = (size_t)round_up(n, kPad);
+        CHK(ctx_may_allocate(c, sizeof(float) * (np * np + np * kTile)));
+    }
     mag_factor *f = new mag_factor();
     f->device = c->device;
     f->n = n;

@@ -506,8 +506,14 @@ void launch_zmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const B
         hipLaunchKernelGGL(k_max_final_b, dim3(wz.na), dim3(256), 0, s, P, wz, norm_off);
 }
 
+size_t zmv_split_partial_doubles(int64_t n)
+{
+    Plan p = plan_for(n);
+    return (size_t)(p.splits * p.npad + p.npad / 256);
+}
+
 // Row-per-thread form (any m): (row blocks) x (column splits), then the split reduce.
-static void launch_zmv_split(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
+void launch_zmv_split(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
                              double *y, const double *b, int mode, double *partial, double *out_norm)
 {
     Plan p = plan_for(n);

@@ -210,12 +210,20 @@ struct mag_ctx {
     // tuned panel width of the single-solve FP32 factor per size bucket
     // (bucket = bit length of npad); 0 = the built-in choice
     int tune_panel[64] = {};
+    // cap on the device bytes held by the buffers above (0: none)
+    size_t ws_limit = 0;
 };
 
 namespace mag {
 
 // Grow `b` to at least `bytes` (frees the old block; contents are lost).
+// MAG_ENOMEM when the device cannot hold it or the context's cap would be
+// exceeded.
 int ensure(mag_ctx *ctx, DevBuf &b, size_t bytes);
+// Device bytes held by the context's buffers.
+size_t ctx_held_bytes(const mag_ctx *ctx);
+// MAG_OK if `extra` more device bytes stay within the context's cap.
+int ctx_may_allocate(const mag_ctx *ctx, size_t extra);
 // Coordinates finite and pairwise distinct (else MAG_EINVAL / MAG_ENOTPD); one host sync.
 // pairs = false checks finiteness only (the caller's FP32 tile generator checks the pairs).
 int check_points(mag_ctx *ctx, const double *X, int64_t n, int m, bool pairs = true);
@@ -285,6 +293,12 @@ void launch_zmv(hipStream_t s, const double *X, int64_t n, int m, double t,
                 const double *v, double *y, const double *b, int mode,
                 double *partial, double *out_norm, bool f32_entries = false, int kernel = kKernExp);
 size_t zmv_partial_doubles(int64_t n);
+// The row-per-thread form of launch_zmv (any m; no symmetric tiles): partial
+// needs zmv_split_partial_doubles(n) doubles, y npad doubles; the max norm of
+// mode 1 goes to out_norm (may be NULL).
+void launch_zmv_split(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
+                      double *y, const double *b, int mode, double *partial, double *out_norm);
+size_t zmv_split_partial_doubles(int64_t n);
 
 // trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,

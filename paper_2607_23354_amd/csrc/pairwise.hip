@@ -19,7 +19,7 @@ namespace {
 
 constexpr int RT = 256;
 constexpr int CH = 256;
-constexpr int MMAX = 16;  // largest dimension handled by the gradient pass
+constexpr int MMAX = 16;  // largest dimension of the register-held forms
 
 __device__ inline double sq_acc(double s, double e)
 {
@@ -98,6 +98,79 @@ __device__ __forceinline__ void pair_partial_body(const double *__restrict__ X, 
     }
 }
 
+// Any m (used above MMAX): each thread reads its own row and the column points
+// from global memory (L1/L2 cached); the gradient's m outputs are formed in
+// passes of GCH dimensions, each pass recomputing the entries over all m.
+constexpr int GCH = 16;
+
+template <int MODE>
+__device__ __forceinline__ void pair_partial_generic(const double *__restrict__ X, int64_t n, int m, double t,
+                                                     const double *__restrict__ v,
+                                                     const double *__restrict__ lam,
+                                                     double *__restrict__ partial, int64_t cps, int64_t npad,
+                                                     int64_t bx, int64_t by)
+{
+    __shared__ double vc[CH];
+    __shared__ double lc[CH];
+    const int64_t j = bx * RT + threadIdx.x;
+    const int64_t c_lo = by * cps;
+    const int64_t c_hi = min(n, c_lo + cps);
+    const bool live = j < n;
+    const double vj = live ? v[j] : 0.0;
+    const double lj = (MODE == kGradX && live) ? lam[j] : 0.0;
+    const double *xj = X + (live ? j : 0) * m;
+    const int passes = (MODE == kGradX) ? (m + GCH - 1) / GCH : 1;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int l0 = pass * GCH;
+        double acc[GCH];
+#pragma unroll
+        for (int q = 0; q < GCH; ++q) acc[q] = 0.0;
+        for (int64_t k0 = c_lo; k0 < c_hi; k0 += CH) {
+            const int cnt = (int)min((int64_t)CH, c_hi - k0);
+            __syncthreads();
+            if (threadIdx.x < cnt) {
+                vc[threadIdx.x] = v[k0 + threadIdx.x];
+                if (MODE == kGradX) lc[threadIdx.x] = lam[k0 + threadIdx.x];
+            }
+            __syncthreads();
+            if (!live) continue;
+            for (int c = 0; c < cnt; ++c) {
+                if (k0 + c == j) continue;
+                const double *xk = X + (k0 + c) * m;
+                double s = 0.0;
+                for (int l = 0; l < m; ++l) s = sq_acc(s, xj[l] - xk[l]);
+                const double d = sqrt(s);
+                const double z = exp_nonpos(-(t * d));
+                if (MODE == kDZ) {
+                    acc[0] = fma(d * z, vc[c], acc[0]);
+                } else {
+                    const double coef = t * (lj * vc[c] + lc[c] * vj) * z / d;
+#pragma unroll
+                    for (int q = 0; q < GCH; ++q)
+                        if (l0 + q < m) acc[q] = fma(coef, xj[l0 + q] - xk[l0 + q], acc[q]);
+                }
+            }
+        }
+        if (j < npad) {
+            if (MODE == kDZ) {
+                partial[by * npad + j] = live ? acc[0] : 0.0;
+            } else {
+#pragma unroll
+                for (int q = 0; q < GCH; ++q)
+                    if (l0 + q < m) partial[(by * npad + j) * m + l0 + q] = live ? acc[q] : 0.0;
+            }
+        }
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(RT)
+k_pair_partial_generic(const double *__restrict__ X, int64_t n, int m, double t, const double *__restrict__ v,
+                       const double *__restrict__ lam, double *__restrict__ partial, int64_t cps, int64_t npad)
+{
+    pair_partial_generic<MODE>(X, n, m, t, v, lam, partial, cps, npad, blockIdx.x, blockIdx.y);
+}
+
 template <int MODE, int M>
 __global__ void __launch_bounds__(RT)
 k_pair_partial(const double *__restrict__ X, int64_t n, int m_rt, double t,
@@ -152,6 +225,17 @@ __global__ void __launch_bounds__(RT) k_dz_partial_b(const BProb *__restrict__ P
                               q.partial, pl.cps, q.npad, u / pl.splits, u % pl.splits);
 }
 
+__global__ void __launch_bounds__(RT) k_dz_partial_generic_b(const BProb *__restrict__ P, BWork w, int v_slot)
+{
+    const int i = bfind(w.pref, w.na, blockIdx.x);
+    const BProb &q = P[w.plist[i]];
+    if (!q.active) return;
+    const Plan pl = plan_for(q.n);
+    const int64_t u = blockIdx.x - w.pref[i];
+    pair_partial_generic<kDZ>(q.X, q.n, q.m, q.t, q.vec + (int64_t)v_slot * q.npad, nullptr, q.partial, pl.cps,
+                              q.npad, u / pl.splits, u % pl.splits);
+}
+
 __global__ void __launch_bounds__(256) k_dz_reduce_b(const BProb *__restrict__ P, BWork w, int y_slot)
 {
     const int i = bfind(w.pref, w.na, blockIdx.x);
@@ -178,14 +262,20 @@ void launch_mode(hipStream_t s, const Plan &p, dim3 grid, const double *X, int64
     case 3: MAG_PAIR_CASE(3); break;
     case 4: MAG_PAIR_CASE(4); break;
     case 8: MAG_PAIR_CASE(8); break;
-    default: MAG_PAIR_CASE(0); break;
+    default:
+        if (m <= MMAX) MAG_PAIR_CASE(0);
+        else hipLaunchKernelGGL(k_pair_partial_generic<MODE>, grid, dim3(RT), 0, s, X, n, m, t, v, lam, partial,
+                                p.cps, p.npad);
+        break;
     }
 #undef MAG_PAIR_CASE
 }
 
 }  // namespace
 
-int pair_max_dim() { return MMAX; }
+// Every pass accepts any dimension (compile-time forms up to MMAX, the generic
+// form above); the bound only guards the int arithmetic of the layouts.
+int pair_max_dim() { return 1 << 16; }
 
 int64_t dz_b_units(int64_t n)
 {
@@ -204,7 +294,10 @@ void launch_dzmv_b(hipStream_t s, int m, const BProb *P, const BWork &wz, const 
     case 3: hipLaunchKernelGGL(k_dz_partial_b<3>, g, dim3(RT), 0, s, P, wz, v_slot); break;
     case 4: hipLaunchKernelGGL(k_dz_partial_b<4>, g, dim3(RT), 0, s, P, wz, v_slot); break;
     case 8: hipLaunchKernelGGL(k_dz_partial_b<8>, g, dim3(RT), 0, s, P, wz, v_slot); break;
-    default: hipLaunchKernelGGL(k_dz_partial_b<0>, g, dim3(RT), 0, s, P, wz, v_slot); break;
+    default:
+        if (m <= MMAX) hipLaunchKernelGGL(k_dz_partial_b<0>, g, dim3(RT), 0, s, P, wz, v_slot);
+        else hipLaunchKernelGGL(k_dz_partial_generic_b, g, dim3(RT), 0, s, P, wz, v_slot);
+        break;
     }
     hipLaunchKernelGGL(k_dz_reduce_b, dim3((unsigned)wr.total), dim3(256), 0, s, P, wr, y_slot);
 }

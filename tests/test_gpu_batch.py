@@ -103,3 +103,52 @@ def test_tplus_batch_no_sign_change_items(mag):
     assert infos[0]["no_sign_change"] == 1 and tps[0] == 0.0
     assert infos[1]["no_sign_change"] == 1 and tps[1] == 0.0
     assert infos[2]["no_sign_change"] == 0 and tps[2] > 0
+
+
+# ---- the batched cutoff workload at full scale: 64 mixture clouds, n ~ U{1000..6000}
+
+@pytest.fixture(scope="module")
+def mixture64(mag):
+    clouds = W.mixture_clouds(B=64, m=3, seed=0)
+    X, offs = W.pack_clouds(clouds)
+    tps, w, infos = mag.tplus_batch(dev(X), offs, want_w=True)
+    return clouds, offs, tps, w.cpu().numpy(), infos
+
+
+def test_tplus_batch_mixture64_signs(mag, mixture64):
+    # every cloud's cutoff: w >= 0 at t_+(1 + 1e-5) and min w < 0 at t_+(1 - 1e-5),
+    # each decided by the FP64 dense comparator (FP64 Z + rocSOLVER Cholesky), a
+    # solver the search does not use; and w(t_+) returned by the search solves
+    # Z w = 1 (oracle Dot2 residual on sampled rows)
+    clouds, offs, tps, w, infos = mixture64
+    assert len(clouds) == 64
+    sizes = [len(c) for c in clouds]
+    assert min(sizes) >= 1000 and max(sizes) <= 6000
+    for b, Xb in enumerate(clouds):
+        assert infos[b]["no_sign_change"] == 0, b
+        tp = tps[b]
+        assert 0 < tp <= infos[b]["t_bound"]
+        Xd = dev(Xb)
+        above = mag.weighting(Xd, tp * (1 + 1e-5), solver="fp64_dense").info["min_w"]
+        below = mag.weighting(Xd, tp * (1 - 1e-5), solver="fp64_dense").info["min_w"]
+        assert above >= 0 and below < 0, (b, len(Xb), tp, above, below)
+        wb = w[offs[b]:offs[b + 1]]
+        assert wb.min() >= 0
+        rows = np.random.default_rng(b).choice(len(Xb), size=32, replace=False)
+        assert np.abs(oracle.residual(Xb, tp, wb, rows)).max() <= 1e-12
+    print("mixture64: n in [%d, %d], t_+ in [%.4f, %.4f], solves %d" %
+          (min(sizes), max(sizes), min(tps), max(tps), sum(i["solves"] for i in infos)))
+
+
+@pytest.mark.parametrize("rank", [0, 1, 2])
+def test_tplus_batch_mixture64_vs_oracle(mag, mixture64, rank):
+    # the three smallest clouds against the oracle's bisection and the single call
+    clouds, offs, tps, w, infos = mixture64
+    b = int(np.argsort([len(c) for c in clouds])[rank])
+    Xb = clouds[b]
+    ref = oracle.tplus(Xb)
+    single = mag.tplus(dev(Xb))
+    print(f"cloud {b} n={len(Xb)}: batch {tps[b]:.9g} single {single.t_plus:.9g} oracle {ref.t_plus:.9g}")
+    assert abs(tps[b] - ref.t_plus) / ref.t_plus <= 2.5e-6
+    assert abs(single.t_plus - ref.t_plus) / ref.t_plus <= 2.5e-6
+    assert abs(infos[b]["t_bound"] - ref.t_bound) <= 1e-12 * ref.t_bound

@@ -102,18 +102,3 @@ def test_hss_deterministic_and_errors(mag):
     Xd[7] = Xd[300]
     with pytest.raises(mag.MagError):
         mag.weighting(dev(Xd), 1.0, solver="hss")
-
-
-def test_hss_full_size_torus(mag):
-    n, t = 131072, 2.0
-    X = W.noisy_torus(n, seed=0)
-    res = mag.weighting(dev(X), t, solver="hss", max_rank=512, gmres_restart=100, max_gmres=400, max_outer=30,
-                        profile=True)
-    w = res.w.cpu().numpy()
-    rows = np.random.default_rng(5).choice(n, size=256, replace=False)
-    r = np.abs(oracle.residual(X, t, w, rows)).max()
-    print(f"torus n={n} t={t}: sampled residual {r:.3e} device {res.info['resid_inf']:.3e} "
-          f"outer={res.info['outer_iters']} gmres={res.info['gmres_iters']} factor {res.info['ms_factor']:.0f} ms "
-          f"refine {res.info['ms_refine']:.0f} ms M={res.info['magnitude']:.10g}")
-    assert r <= 1e-12
-    assert res.info["resid_inf"] <= 1e-12

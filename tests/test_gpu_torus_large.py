@@ -1,0 +1,64 @@
+"""The large workload: n = 131072 points on a noisy torus (R = 1, r = 0.3,
+sigma = 0.01, seed 0) at t in {0.5, 2, 8}, solved by every solver that
+handles that size:
+
+* MAG_FP32_IR: the FP32 dense factor (npad^2 * 4 B = 68.7 GB in HBM, the only
+  size here whose factor has more than 2^31 entries, so its 64-bit indexing is
+  exercised) + FP64 matrix-free GMRES-IR;
+* MAG_HODLR and MAG_HSS: hierarchical preconditioners + the same FP64 GMRES,
+  with the top-level rank the benchmark uses (max_rank 512).
+
+The oracle cannot hold Z at this size (137 GB in FP64), so it checks the
+residual 1 - Z w on sampled rows one by one (Dot2).  The magnitudes of the
+solvers are compared with each other through an exact identity: if
+Z w_a = 1 - r_a and Z w_b = 1 - r_b, then M_a - M_b = w^T (r_b - r_a) with
+w = Z^{-1} 1, so |M_a - M_b| <= ||w||_1 (||r_a||_inf + ||r_b||_inf).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+N = 131072
+SOLVERS = {
+    "fp32_ir": {},
+    "hodlr": {"max_rank": 512, "gmres_restart": 100, "max_gmres": 400, "max_outer": 30},
+    "hss": {"max_rank": 512, "gmres_restart": 100, "max_gmres": 400, "max_outer": 30},
+}
+
+
+@pytest.fixture(scope="module")
+def torus():
+    X = W.noisy_torus(N, seed=0)
+    return X, torch.from_numpy(X).to("cuda:0")
+
+
+@pytest.mark.parametrize("t", [0.5, 2.0, 8.0])
+def test_torus_full_size_all_solvers(mag, torus, t):
+    X, Xd = torus
+    rows = np.random.default_rng(5).choice(N, size=256, replace=False)
+    got = {}
+    for name, kw in SOLVERS.items():
+        res = mag.weighting(Xd, t, solver=name, profile=True, **kw)
+        w = res.w.cpu().numpy()
+        r = float(np.abs(oracle.residual(X, t, w, rows)).max())
+        info = res.info
+        print(f"torus n={N} t={t} {name}: sampled oracle residual {r:.3e} device {info['resid_inf']:.3e} "
+              f"outer={info['outer_iters']} gmres={info['gmres_iters']} shifted={info['shifted']} "
+              f"factor {info['ms_factor']:.0f} ms refine {info['ms_refine']:.0f} ms M={info['magnitude']:.13g}")
+        assert r <= 1e-12
+        assert info["resid_inf"] <= 1e-12
+        assert info["min_w"] == w.min()
+        got[name] = (info["magnitude"], info["resid_inf"], float(np.abs(w).sum()))
+        del res, w
+    names = list(got)
+    for i in range(len(names)):
+        for j in range(i + 1, len(names)):
+            Ma, ra, w1 = got[names[i]]
+            Mb, rb, _ = got[names[j]]
+            bound = 2.0 * w1 * (ra + rb) + 1e-13 * abs(Ma)
+            assert abs(Ma - Mb) <= bound, (names[i], names[j], Ma, Mb, bound)
