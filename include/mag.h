@@ -223,7 +223,7 @@ int mag_tplus(mag_ctx *ctx, const double *X, int64_t n, int32_t m, const mag_tpl
 
 /* dw/dt = Z^{-1} (D o Z) w at scale t, where (D o Z)_jk = d_jk exp(-t d_jk)
  * (from differentiating eq. weighting in t).  w (device, n, may be NULL)
- * receives the weighting, dwdt (device, n) its derivative.  m <= 16. */
+ * receives the weighting, dwdt (device, n) its derivative.  Any m. */
 int mag_dwdt(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, double *w,
              double *dwdt, const mag_opts *opts);
 
@@ -305,7 +305,7 @@ int mag_weighting_fwd(mag_ctx *ctx, const double *X, int64_t n, int32_t m, doubl
 
 /* gM: dL/dMag; gw: dL/dw (device, n, may be NULL); dX: device n x m row-major
  * output (may be NULL); dt: HOST output (may be NULL).  X, n, m, t must be
- * those of the forward call (EINVAL otherwise).  m <= 16. */
+ * those of the forward call (EINVAL otherwise).  Any m. */
 int mag_weighting_vjp(mag_ctx *ctx, mag_factor *f, const double *X, int64_t n, int32_t m,
                       double t, const double *w, double gM, const double *gw, double *dX,
                       double *dt, const mag_opts *opts);
@@ -395,7 +395,7 @@ int mag_factor32(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
 int mag_prec_apply(mag_ctx *ctx, const float *L, const float *dinv, int64_t n,
                    const double *r, double *z);
 
-/* y = (D o Z) v in FP64, matrix-free (device, n); m <= 16. */
+/* y = (D o Z) v in FP64, matrix-free (device, n); any m. */
 int mag_dzmatvec(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
                  const double *v, double *y);
 
