@@ -26,6 +26,7 @@
 #ifndef MAG_H
 #define MAG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -398,6 +399,24 @@ int mag_prec_apply(mag_ctx *ctx, const float *L, const float *dinv, int64_t n,
 /* y = (D o Z) v in FP64, matrix-free (device, n); any m. */
 int mag_dzmatvec(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
                  const double *v, double *y);
+
+/* ---- no-allocation entry point ---------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residual of mag_residual, r = 1 - Z w (device, n) and *rinf = ||r||_inf
+ * (HOST, may be NULL), with Z regenerated in FP64 from X (device, n x m, any
+ * m), computed without allocating anything.  Its only workspace is a
+ * file-scope device array of mag_residual_noalloc_max_doubles() doubles
+ * (16 MiB) that each GPU the library runs on holds until the process ends;
+ * a call needs npad (1 + s) + npad/256 + 8 of them (s <= 64 column splits,
+ * s = 1 from n = 524288 on), so n up to about one million points; larger n
+ * returns MAG_ENOMEM without launching anything.  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (several streams or
+ * threads) race.  The sums run in another order than mag_residual's, so the
+ * two agree to the rounding of an n-term FP64 sum, not bitwise. */
+int mag_residual_noalloc(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                         const double *w, double *r, double *rinf);
+size_t mag_residual_noalloc_max_doubles(void);
 
 #ifdef __cplusplus
 }

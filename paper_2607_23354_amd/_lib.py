@@ -160,6 +160,8 @@ SIGNATURES = {
     "mag_factor32": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _d, _vp, _vp, ctypes.POINTER(_i32)]),
     "mag_prec_apply": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "mag_dzmatvec": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp]),
+    "mag_residual_noalloc": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp, ctypes.POINTER(_d)]),
+    "mag_residual_noalloc_max_doubles": (ctypes.c_size_t, []),
     "mag_tplus_opts_default": (None, [ctypes.POINTER(MagTplusOpts)]),
     "mag_tplus": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.POINTER(MagTplusOpts), ctypes.POINTER(MagOpts),
                                  ctypes.POINTER(_d), _vp, ctypes.POINTER(MagTplusInfo)]),

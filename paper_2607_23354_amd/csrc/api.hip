@@ -1120,6 +1120,10 @@ int mag_create(mag_ctx **out, int device)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cu_count = cus;
     c->ws_limit = workspace_limit_from_env();
+    if (noalloc_setup(device) != MAG_OK) {
+        mag_destroy(c);
+        return MAG_EHIP;
+    }
     if (ensure(c, c->ints, sizeof(int) * kIntsTotal) != MAG_OK) {
         mag_destroy(c);
         return MAG_ENOMEM;

@@ -299,6 +299,9 @@ size_t zmv_partial_doubles(int64_t n);
 void launch_zmv_split(hipStream_t s, const double *X, int64_t n, int m, double t, const double *v,
                       double *y, const double *b, int mode, double *partial, double *out_norm);
 size_t zmv_split_partial_doubles(int64_t n);
+// Per-device address of the no-allocation entry point's scratch array, taken
+// once per device (with that device current) by mag_create.
+int noalloc_setup(int device);
 
 // trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
