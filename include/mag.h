@@ -69,13 +69,14 @@ int mag_set_stream(mag_ctx *ctx, void *hip_stream);
 
 /* ---- options and diagnostics --------------------------------------------- */
 enum {
-    MAG_AUTO = 0,        /* by measured cost: MAG_FP32_IR up to n = 65536 (its FP32      *
-                          * factor's n^3/3 flops on MFMA are the cheaper solve there),  *
-                          * MAG_HODLR above (max_rank 512, GMRES(100), up to 400 inner  *
-                          * iterations; at n = 131072 it takes 2.0-2.3 s against 5.9 s *
-                          * for the dense factor) when m <= 16; if the HODLR solve does  *
-                          * not converge, or m > 16, MAG_FP32_IR when its npad^2 factor  *
-                          * fits in 3/4 of the device memory, else MAG_ENOMEM            */
+    MAG_AUTO = 0,        /* by measured cost: MAG_FP32_IR up to n = 49152 (its FP32      *
+                          * factor's n^3/3 flops on MFMA are the cheaper solve there:   *
+                          * 0.11-0.13 s against 0.14-0.21 s at n = 32768), MAG_HODLR    *
+                          * above (max_rank 512, GMRES(100), up to 400 inner           *
+                          * iterations; 0.33-0.57 s against 0.76-0.82 s at n = 65536)   *
+                          * when m <= 16; if the HODLR solve does not converge, or      *
+                          * m > 16, MAG_FP32_IR when its npad^2 factor fits in 3/4 of   *
+                          * the device memory, else MAG_ENOMEM                          */
     MAG_FP64_DENSE = 1,  /* FP64 Z in HBM + rocSOLVER dpotrf/dpotrs (dense comparator)   */
     MAG_FP32_IR = 2,     /* FP32 MFMA Cholesky + FP64 GMRES iterative refinement         */
     MAG_HODLR = 3,       /* HODLR preconditioner + FP64 GMRES (largest sizes, Sec. 3.2): *

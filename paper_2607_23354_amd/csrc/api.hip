@@ -761,10 +761,12 @@ int solve_hss(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double 
 }
 
 // MAG_AUTO takes the HODLR preconditioner above this size.  Measured on the
-// MI355X (noisy torus and Gaussian clouds): the dense FP32 factor's n^3/3
-// MFMA flops cost 0.11 s at n = 32768 and 5.9 s at n = 131072, where the HODLR
-// solve takes 2.0-2.3 s; the two cross between 65536 and 131072.
-constexpr int64_t kAutoHodlrMinN = 65536;
+// MI355X, whole solves (noisy torus at t = 0.5, 2, 8; Gaussian cloud at its
+// cutoff scale): n = 32768: dense FP32 factor + refinement 114-132 ms, HODLR
+// (max_rank 512) 143-213 ms; n = 65536: 757-822 ms against 333-570 ms;
+// n = 98304: 2.47-2.62 s against 0.81-1.24 s.  The crossover lies between the
+// first two sizes (nearer the upper for Gaussian clouds, which compress worse).
+constexpr int64_t kAutoHodlrMinN = 49152;
 
 // Whether the dense FP32 factor's npad^2 floats fit in three quarters of the
 // device memory (counting what this context already holds for it) and in the
