@@ -316,13 +316,18 @@ void mag_factor_free(mag_factor *f);
 
 /* ---- batches of problems of uneven n --------------------------------------
  * B problems (clouds and scales) solved together: every phase of the solve is
- * one launch over all problems (device work lists map blocks to problems),
- * the factorisation's launch sequence is captured once in a hipGraph and
- * replayed, and the refinement iterates all unconverged problems in
- * lockstep.  X packs the clouds row-wise (device); offs (HOST, B+1) gives the
- * row ranges, cloud b = rows [offs[b], offs[b+1]); rows may be shared
- * (several scales of one cloud).  Every item gives the same result as the
- * single call up to rounding order. */
+ * one launch over all problems (device work lists map blocks to problems).  A
+ * whole step -- each cloud's next scale, tile generation, factorisation,
+ * refinement, min w, bracket update and Newton derivative -- is captured once
+ * as a hipGraph and replayed; the refinement and search decisions are taken
+ * on the device (a flag word per problem gates every launch), and the host
+ * reads one count per step to know when every cloud is done.  The graph holds
+ * a plain round and three rounds that may run GMRES(12) cycles; items that
+ * mag_weighting_batch finds short of tol after them get the host-driven
+ * refinement with the caller's limits.  X packs the clouds row-wise (device);
+ * offs (HOST, B+1) gives the row ranges, cloud b = rows [offs[b], offs[b+1]);
+ * rows may be shared (several scales of one cloud).  Every item gives the
+ * same result as the single call up to rounding order. */
 
 /* w (device, packed like X, rows offs[b]-offs[0] ...) receives each weighting,
  * M (HOST, B, may be NULL) each magnitude, info (HOST, B, may be NULL) each
@@ -358,9 +363,29 @@ int mag_tune_panel(mag_ctx *ctx, int64_t n, int32_t nb);
 int mag_autotune(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t, int32_t reps,
                  int32_t *nb_out, double *ms_out);
 
-/* Write the tuned table to a JSON text file ({"panel": {"<bucket>": nb, ...}}),
+/* The batched factorisation (mag_weighting_batch, mag_tplus_batch) works in
+ * 256-column panels, either in pairs (a strip update of the second panel by
+ * the first, then one trailing update with K = 512) or singly (one trailing
+ * update with K = 256 per panel: more launches, shallower updates).  The
+ * choice is kept per size bucket of the batch's largest npad.
+ * mag_tune_batch_group sets it (group 1 single, 2 pairs, 0 the built-in
+ * pairs) for the bucket of max_n; MAG_EINVAL for other groups or max_n < 1. */
+int mag_tune_batch_group(mag_ctx *ctx, int64_t max_n, int32_t group);
+
+/* Time the batched tile generation + factorisation of these problems (X, offs,
+ * m, t as for mag_weighting_batch; every cloud at least one point) with each
+ * grouping, best of `reps` graph replays each, and keep the faster for the
+ * bucket of the largest npad.  group_out (HOST, may be NULL) receives 1 or 2;
+ * ms_out (HOST, 2 doubles, may be NULL) the best times of single panels and
+ * pairs.  Uses the context's batch workspace. */
+int mag_autotune_batch(mag_ctx *ctx, int32_t B, const double *X, const int64_t *offs, int32_t m,
+                       const double *t, int32_t reps, int32_t *group_out, double *ms_out);
+
+/* Write the tuned tables to a JSON text file
+ * ({"panel": {"<bucket>": nb, ...}, "batch_group": {"<bucket>": group, ...}}),
  * or read one written by mag_tune_save into the context (entries not in the
- * file are left as they are).  MAG_EINVAL on I/O or format errors. */
+ * file are left as they are; "batch_group" may be absent).  MAG_EINVAL on I/O
+ * or format errors. */
 int mag_tune_save(const mag_ctx *ctx, const char *path);
 int mag_tune_load(mag_ctx *ctx, const char *path);
 

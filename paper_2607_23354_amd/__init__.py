@@ -491,6 +491,29 @@ def autotune(X: torch.Tensor, t: float, *, reps: int = 2, ctx: Context | None = 
     return nb.value, (ms[0], ms[1])
 
 
+def tune_batch_group(max_n: int, group: int, *, ctx: Context | None = None, device: int = 0) -> None:
+    """Panel grouping of the batched factorisation for max_n's size bucket:
+    1 single 256-column panels, 2 pairs, 0 the built-in choice (pairs)."""
+    c = ctx if ctx is not None else _default_ctx(device)
+    _lib.check(c.lib.mag_tune_batch_group(c.handle, int(max_n), int(group)), "mag_tune_batch_group")
+
+
+def autotune_batch(X: torch.Tensor, offs, t, *, reps: int = 2, ctx: Context | None = None):
+    """Time the batched factorisation of these clouds with single panels and
+    with pairs and keep the faster for the bucket of the largest cloud;
+    returns (group, (ms_single, ms_pairs))."""
+    X, offs, arr = _pack(X, offs)
+    B = len(offs) - 1
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    tt = (ctypes.c_double * B)(*[float(v) for v in t])
+    g = ctypes.c_int32(0)
+    ms = (ctypes.c_double * 2)()
+    _lib.check(c.lib.mag_autotune_batch(c.handle, B, _ptr(X), arr, m, tt, int(reps), ctypes.byref(g), ms),
+               "mag_autotune_batch")
+    return g.value, (ms[0], ms[1])
+
+
 def tune_save(path: str, *, ctx: Context | None = None, device: int = 0) -> None:
     c = ctx if ctx is not None else _default_ctx(device)
     _lib.check(c.lib.mag_tune_save(c.handle, os.fsencode(path)), "mag_tune_save")

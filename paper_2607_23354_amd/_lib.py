@@ -152,6 +152,9 @@ SIGNATURES = {
     "mag_tune_panel": (ctypes.c_int, [_vp, _i64, _i32]),
     "mag_autotune": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _i32, ctypes.POINTER(_i32),
                                     ctypes.POINTER(_d)]),
+    "mag_tune_batch_group": (ctypes.c_int, [_vp, _i64, _i32]),
+    "mag_autotune_batch": (ctypes.c_int, [_vp, _i32, _vp, ctypes.POINTER(_i64), _i32, ctypes.POINTER(_d), _i32,
+                                          ctypes.POINTER(_i32), ctypes.POINTER(_d)]),
     "mag_tune_save": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "mag_tune_load": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "mag_zmatvec": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp]),

@@ -1061,6 +1061,38 @@ size_t workspace_limit_from_env()
 }
 }  // namespace
 
+namespace {
+// Parse the object {"<bucket>": value, ...} that follows `key` in text into
+// staged/any; values must satisfy ok(v).  MAG_EINVAL on malformed input; a
+// missing key leaves everything unset when optional.
+template <class Ok>
+int parse_bucket_map(const std::string &text, const char *key, bool optional, int (&staged)[64], bool (&any)[64],
+                     Ok ok)
+{
+    const size_t at = text.find(key);
+    if (at == std::string::npos) return optional ? MAG_OK : MAG_EINVAL;
+    size_t p = text.find('{', at);
+    const size_t end = (p == std::string::npos) ? std::string::npos : text.find('}', p);
+    if (end == std::string::npos) return MAG_EINVAL;
+    while (true) {
+        const size_t q0 = text.find('"', p + 1);
+        if (q0 == std::string::npos || q0 > end) break;
+        const size_t q1 = text.find('"', q0 + 1);
+        const size_t colon = (q1 == std::string::npos) ? std::string::npos : text.find(':', q1);
+        if (colon == std::string::npos || colon > end) return MAG_EINVAL;
+        char *stop = nullptr;
+        const long b = std::strtol(text.c_str() + q0 + 1, &stop, 10);
+        if (stop != text.c_str() + q1 || b < 0 || b >= 64) return MAG_EINVAL;
+        const long v = std::strtol(text.c_str() + colon + 1, &stop, 10);
+        if (stop == text.c_str() + colon + 1 || !ok(v)) return MAG_EINVAL;
+        staged[b] = (int)v;
+        any[b] = true;
+        p = (size_t)(stop - text.c_str());
+    }
+    return MAG_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *mag_strerror(int code)
@@ -1239,9 +1271,18 @@ int mag_tune_save(const mag_ctx *c, const char *path)
         std::fprintf(f, "%s\"%d\": %d", first ? "" : ", ", b, c->tune_panel[b]);
         first = false;
     }
+    std::fprintf(f, "}, \"batch_group\": {");
+    first = true;
+    for (int b = 0; b < 64; ++b) {
+        if (c->tune_bgroup[b] == 0) continue;
+        std::fprintf(f, "%s\"%d\": %d", first ? "" : ", ", b, c->tune_bgroup[b]);
+        first = false;
+    }
     std::fprintf(f, "}}\n");
     return std::fclose(f) == 0 ? MAG_OK : MAG_EINVAL;
 }
+
+
 
 int mag_tune_load(mag_ctx *c, const char *path)
 {
@@ -1253,30 +1294,15 @@ int mag_tune_load(mag_ctx *c, const char *path)
     size_t got;
     while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
     std::fclose(f);
-    const size_t key = text.find("\"panel\"");
-    if (key == std::string::npos) return MAG_EINVAL;
-    size_t p = text.find('{', key);
-    const size_t end = (p == std::string::npos) ? std::string::npos : text.find('}', p);
-    if (end == std::string::npos) return MAG_EINVAL;
-    int staged[64] = {};
-    bool any[64] = {};
-    while (true) {
-        const size_t q0 = text.find('"', p + 1);
-        if (q0 == std::string::npos || q0 > end) break;
-        const size_t q1 = text.find('"', q0 + 1);
-        const size_t colon = (q1 == std::string::npos) ? std::string::npos : text.find(':', q1);
-        if (colon == std::string::npos || colon > end) return MAG_EINVAL;
-        char *stop = nullptr;
-        const long b = std::strtol(text.c_str() + q0 + 1, &stop, 10);
-        if (stop != text.c_str() + q1 || b < 0 || b >= 64) return MAG_EINVAL;
-        const long v = std::strtol(text.c_str() + colon + 1, &stop, 10);
-        if (stop == text.c_str() + colon + 1 || (v != 0 && v != 256 && v != 512)) return MAG_EINVAL;
-        staged[b] = (int)v;
-        any[b] = true;
-        p = (size_t)(stop - text.c_str());
-    }
-    for (int b = 0; b < 64; ++b)
+    int staged[64] = {}, bstaged[64] = {};
+    bool any[64] = {}, bany[64] = {};
+    CHK(parse_bucket_map(text, "\"panel\"", false, staged, any,
+                         [](long v) { return v == 0 || v == 256 || v == 512; }));
+    CHK(parse_bucket_map(text, "\"batch_group\"", true, bstaged, bany, [](long v) { return v >= 0 && v <= 2; }));
+    for (int b = 0; b < 64; ++b) {
         if (any[b]) c->tune_panel[b] = staged[b];
+        if (bany[b]) c->tune_bgroup[b] = bstaged[b];
+    }
     return MAG_OK;
 }
 

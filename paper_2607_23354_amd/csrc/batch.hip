@@ -36,18 +36,6 @@ namespace {
         if (rc_ != MAG_OK) return rc_;              \
     } while (0)
 
-// scalar slots of each problem (BProb::scal)
-enum : int64_t {
-    SC_RNORM = 0,   // ||b - Z x||_inf
-    SC_BETA = 1,    // ||M^{-1} r||_2
-    SC_SUM = 2,     // sum, min, argmin (3)
-    SC_AMAX = 5,
-    SC_PICK = 6,    // d(min w)/dt picked at argmin
-    SC_H = 16,      // Arnoldi column h (2 (k+1)) and h_{k+1,k}
-    SC_Y = 96,      // GMRES solution coefficients
-    SC_COUNT = 160
-};
-constexpr int kIntsPer = 2048;
 
 struct Slots {
     int R, V0, X, Rr, Z, Y, U, Best, Rhs, W, D, DZ, n;
@@ -93,9 +81,11 @@ struct Batch {
         if (graph_def) hipGraphDestroy(graph_def);
     }
 
-    // Append bytes to an arena region; the host copy is made now, the device
-    // copy enqueued on the stream (pinned source).  Transient data are reset at
-    // every host sync (all copies done by then).
+    // Append bytes to an arena region.  Transient data: the host copy is made
+    // now and the device copy enqueued on the stream (pinned source); they are
+    // reset at every host sync (all copies done by then).  Persistent data (the
+    // step graph's work lists and states): only the host copy is made; one
+    // flush_persistent() uploads the whole region before anything reads it.
     template <class T>
     T *put(const std::vector<T> &v, bool persist)
     {
@@ -107,11 +97,18 @@ struct Batch {
         char *dp = dev_arena + base + used;
         if (!v.empty()) {
             std::memcpy(hp, v.data(), v.size() * sizeof(T));
-            if (hipMemcpyAsync(dp, hp, v.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
+            if (!persist && hipMemcpyAsync(dp, hp, v.size() * sizeof(T), hipMemcpyHostToDevice, s) != hipSuccess)
                 return nullptr;
         }
         used += bytes;
         return reinterpret_cast<T *>(dp);
+    }
+    int flush_persistent()
+    {
+        if (persist_used == 0) return MAG_OK;
+        return hipMemcpyAsync(dev_arena, host_arena, persist_used, hipMemcpyHostToDevice, s) == hipSuccess
+                   ? MAG_OK
+                   : MAG_EHIP;
     }
     void reset_transient() { trans_used = 0; }
 
@@ -159,6 +156,15 @@ struct Batch {
     }
 };
 
+// split-reduction doubles of one problem: products, derivatives, dot products, d_min
+size_t batch_partial_doubles(int64_t n, int restart)
+{
+    size_t p = std::max(zmv_partial_doubles(n), pair_partial_doubles(n, 1));
+    p = std::max(p, blas1_partial_doubles(restart + 2));
+    p = std::max(p, dmin_partial_doubles(n) + 8);
+    return p + 64;
+}
+
 // Allocate every problem's buffers and the descriptors.  items: (X, n, t).
 int batch_setup(mag_ctx *c, Batch &bt, const std::vector<const double *> &Xs,
                 const std::vector<int64_t> &ns, int m, const std::vector<double> &ts, int restart)
@@ -176,8 +182,7 @@ int batch_setup(mag_ctx *c, Batch &bt, const std::vector<const double *> &Xs,
         fac += (size_t)np[b] * np[b];
         dv += (size_t)np[b] * kTile;
         vec += (size_t)bt.sl.n * np[b];
-        part += std::max(std::max(zmv_partial_doubles(ns[b]), pair_partial_doubles(ns[b], 1)),
-                         blas1_partial_doubles(restart + 2)) + 64;
+        part += batch_partial_doubles(ns[b], restart);
         bt.maxpad = std::max(bt.maxpad, np[b]);
         bt.maxn = std::max(bt.maxn, ns[b]);
     }
@@ -224,34 +229,63 @@ int batch_setup(mag_ctx *c, Batch &bt, const std::vector<const double *> &Xs,
         vp += (size_t)bt.sl.n * np[b];
         q.scal = (double *)c->bscal.p + (size_t)b * SC_COUNT;
         q.partial = pp;
-        pp += std::max(std::max(zmv_partial_doubles(ns[b]), pair_partial_doubles(ns[b], 1)),
-                       blas1_partial_doubles(restart + 2)) + 64;
+        pp += batch_partial_doubles(ns[b], restart);
         q.ints = (int *)c->bints.p + (size_t)b * kIntsPer;
         q.m = m;
         q.active = 1;
     }
     BCHK(hipMemsetAsync(c->bvec.p, 0, sizeof(double) * vec, bt.s));
+    BCHK(hipMemsetAsync(c->bscal.p, 0, sizeof(double) * (size_t)B * SC_COUNT, bt.s));
+    BCHK(hipMemsetAsync(c->bints.p, 0, sizeof(int) * (size_t)B * kIntsPer, bt.s));
     return bt.upload_desc();
 }
 
-// Record the factorisation schedule of all problems into a hipGraph.
-int batch_build_graph(Batch &bt)
+// The factorisation schedule of all problems (work lists in the persistent
+// arena), launched inside the step graph's capture; every kernel skips problems
+// whose descriptor is inactive.
+struct FLaunch {
+    int kind;  // 0 trsm, 1 subupdate, 2 syrk (pair), 3 potrf, 4 tilegen, 5 zero status, 6 strip, 7 syrk (single)
+    int64_t kk;
+    BWork w;
+};
+
+// group: 0 the context's tuned choice for this batch's largest npad, 1 single
+// panels, 2 pairs.
+int batch_factor_schedule(Batch &bt, std::vector<FLaunch> &seq, int group = 0)
 {
     std::vector<int> all(bt.B);
     for (int b = 0; b < bt.B; ++b) all[b] = b;
-    // work lists (persistent arena), built before capture
-    struct Launch {
-        int kind;  // 0 trsm, 1 subupdate, 2 syrk, 3 potrf, 4 tilegen, 5 zero status, 6 strip
-        int64_t kk;
-        BWork w;
-    };
-    std::vector<Launch> seq;
     BWork wall;
     BRC(bt.make_work(all, [&](int) { return (int64_t)1; }, true, wall));
     seq.push_back({5, 0, wall});
     BWork wt;
     BRC(bt.make_work(all, [&](int p) { return tilegen32_blocks(bt.h[p].npad); }, true, wt));
     seq.push_back({4, 0, wt});
+    if (group == 0) group = bt.c->tune_bgroup[size_bucket(bt.maxpad)];
+    if (group == 1) {
+        // single panels of kPanel columns: two 128-column sub-panels, then one
+        // trailing update with K = 256
+        for (int64_t k = 0; k < bt.maxpad; k += kPanel) {
+            for (int sub = 0; sub < kPanel / kTile; ++sub) {
+                const int64_t kk = k + sub * kTile;
+                BWork wp;
+                BRC(bt.make_work(all, [&](int p) { return (int64_t)(kk < bt.h[p].npad ? 1 : 0); }, true, wp));
+                seq.push_back({3, kk, wp});
+                BWork w0;
+                BRC(bt.make_work(all, [&](int p) { return kk < bt.h[p].npad ? gemm_b_units(0, bt.h[p].npad, kk) : 0; }, true, w0));
+                seq.push_back({0, kk, w0});
+                if (sub == 0) {
+                    BWork w1;
+                    BRC(bt.make_work(all, [&](int p) { return kk < bt.h[p].npad ? gemm_b_units(1, bt.h[p].npad, kk) : 0; }, true, w1));
+                    seq.push_back({1, kk, w1});
+                }
+            }
+            BWork w4;
+            BRC(bt.make_work(all, [&](int p) { return k < bt.h[p].npad ? gemm_b_units(4, bt.h[p].npad, k) : 0; }, true, w4));
+            seq.push_back({7, k, w4});
+        }
+        return MAG_OK;
+    }
     // panels of kPanel columns in pairs: first panel, strip update of the second
     // panel by the first, second panel, then one trailing update by both
     for (int64_t k = 0; k < bt.maxpad; k += 2 * kPanel) {
@@ -281,54 +315,21 @@ int batch_build_graph(Batch &bt)
         BRC(bt.make_work(all, [&](int p) { return k < bt.h[p].npad ? gemm_b_units(2, bt.h[p].npad, k) : 0; }, true, w2));
         seq.push_back({2, k, w2});
     }
-    BCHK(hipStreamSynchronize(bt.s));  // schedule uploaded
-    BCHK(hipStreamBeginCapture(bt.s, hipStreamCaptureModeThreadLocal));
-    for (const Launch &L : seq) {
+    return MAG_OK;
+}
+
+void record_factor(Batch &bt, const std::vector<FLaunch> &seq)
+{
+    for (const FLaunch &L : seq) {
         switch (L.kind) {
         case 5: launch_zero_status_b(bt.s, bt.d, L.w.plist, L.w.na); break;
         case 4: launch_tilegen32_b(bt.s, bt.d, L.w); break;
         case 3: launch_potrf128_b(bt.s, bt.d, L.w, L.kk); break;
         case 6: launch_gemm_b(bt.s, 3, bt.d, L.w, L.kk); break;
+        case 7: launch_gemm_b(bt.s, 4, bt.d, L.w, L.kk); break;
         default: launch_gemm_b(bt.s, L.kind, bt.d, L.w, L.kk); break;
         }
     }
-    if (hipStreamEndCapture(bt.s, &bt.graph_def) != hipSuccess) return MAG_EHIP;
-    BCHK(hipGraphInstantiate(&bt.graph, bt.graph_def, nullptr, nullptr, 0));
-    return MAG_OK;
-}
-
-// Factor every active problem (graph replay), retrying problems whose FP32
-// factor broke down with a growing diagonal shift.
-int batch_factor(Batch &bt, std::vector<int> &shifted)
-{
-    shifted.assign(bt.B, 0);
-    std::vector<int> saved_active(bt.B);
-    for (int b = 0; b < bt.B; ++b) saved_active[b] = bt.h[b].active;
-    for (int attempt = 0;; ++attempt) {
-        BRC(bt.upload_desc());
-        BCHK(hipGraphLaunch(bt.graph, bt.s));
-        // breakdown status of every problem
-        std::vector<int> st(bt.B, 0);
-        for (int b = 0; b < bt.B; ++b)
-            if (bt.h[b].active)
-                BCHK(hipMemcpyAsync(&st[b], bt.h[b].ints + kStBreakdown, sizeof(int), hipMemcpyDeviceToHost, bt.s));
-        BRC(bt.sync());
-        bool any = false;
-        for (int b = 0; b < bt.B; ++b) {
-            if (bt.h[b].active && st[b] != 0) {
-                any = true;
-                shifted[b] = 1;
-                const double n = (double)bt.h[b].n;
-                bt.h[b].shift = bt.h[b].shift == 0.0 ? 1e-6 * std::max(1.0, std::sqrt(n)) : bt.h[b].shift * 10.0;
-            } else {
-                bt.h[b].active = 0;  // factor done: not refactored in the next attempt
-            }
-        }
-        if (!any) break;
-        if (attempt >= 6) return MAG_ENOTPD;
-    }
-    for (int b = 0; b < bt.B; ++b) bt.h[b].active = saved_active[b];
-    return bt.upload_desc();
 }
 
 struct BRefine {
@@ -557,14 +558,184 @@ int batch_refine(Batch &bt, const std::vector<int> &ids, int rhs_slot, const std
     return MAG_OK;
 }
 
-int validate_batch(mag_ctx *c, const std::vector<const double *> &Xs, const std::vector<int64_t> &ns,
-                   int m)
+// Work lists of the step graph's products over all problems (persistent arena).
+struct AllWork {
+    const int *all = nullptr;  // 0..B-1
+    BWork wz, wr, wp, wdz, wdr;
+};
+
+int make_all_work(Batch &bt, AllWork &A)
 {
-    for (size_t b = 0; b < ns.size(); ++b) {
-        if (ns[b] < 1) return MAG_EINVAL;
-        BRC(check_points(c, Xs[b], ns[b], m));
+    std::vector<int> all(bt.B);
+    for (int b = 0; b < bt.B; ++b) all[b] = b;
+    BRC(bt.make_work(all, [&](int p) { return zmv_b_units(bt.h[p].n, bt.m); }, true, A.wz));
+    BRC(bt.make_work(all, [&](int p) { return zmv_b_reduce_units(bt.h[p].n, bt.m); }, true, A.wr));
+    BRC(bt.make_work(all, [&](int p) { return prec_b_units(bt.h[p].npad); }, true, A.wp));
+    BRC(bt.make_work(all, [&](int p) { return dz_b_units(bt.h[p].n); }, true, A.wdz));
+    BRC(bt.make_work(all, [&](int p) { return bt.h[p].npad / 256; }, true, A.wdr));
+    A.all = bt.put(all, true);
+    return A.all ? MAG_OK : MAG_ENOMEM;
+}
+
+struct RefPlan {
+    int rounds = 4;      // correction rounds (each a residual, then a plain step or a GMRES cycle)
+    int kcycle = 12;     // Arnoldi steps per GMRES cycle
+    int max_gmres = 200;
+    double tol = 1e-12, inner_tol = 1e-10;
+};
+
+// Record the device-controlled refinement of Z x = b (b in rhs_slot, zero
+// padded) for the problems active on entry; the best iterate lands in slot
+// Best.  bnorm_off: scalar slot of ||b||_inf (tol scales with it), or -1.
+void record_refine(Batch &bt, const AllWork &A, int rhs_slot, int64_t bnorm_off, const RefPlan &rp)
+{
+    const Slots &S = bt.sl;
+    hipStream_t s = bt.s;
+    BProb *P = bt.d;
+    const int B = bt.B;
+    const int64_t mp = bt.maxpad;
+    launch_ref_init_b(s, P, B, bnorm_off, rp.tol);
+    launch_gate_b(s, P, B, F_REF);
+    launch_prec_apply_b(s, P, A.wp, rhs_slot, S.Y, S.X);  // x0 = M^{-1} b
+    for (int round = 0; round <= rp.rounds; ++round) {
+        const int final_round = round == rp.rounds ? 1 : 0;
+        launch_gate_b(s, P, B, F_REF);
+        launch_zmv_b(s, bt.m, P, A.wz, A.wr, S.X, S.Rr, rhs_slot, 1, SC_RNORM);
+        launch_ref_decide_b(s, P, B, final_round, rp.max_gmres);
+        launch_gate_b(s, P, B, F_COPYBEST);
+        launch_copy_b(s, P, A.all, B, mp, S.X, S.Best);
+        if (final_round) break;
+        if (round > 0) {  // the first round cannot revert (no best iterate before it)
+            launch_gate_b(s, P, B, F_REVERT);
+            launch_copy_b(s, P, A.all, B, mp, S.Best, S.X);
+        }
+        launch_gate_b(s, P, B, F_DOPLAIN);
+        launch_prec_apply_b(s, P, A.wp, S.Rr, S.Y, S.Z);
+        launch_axpy_slot_b(s, P, B, mp, S.Z, S.X);
+        // the first round's correction is always a plain step (plain mode starts
+        // on, and a switch to GMRES needs a plain step that gained too little)
+        if (round == 0) continue;
+        launch_gate_b(s, P, B, F_DOGMRES);
+        launch_prec_apply_b(s, P, A.wp, S.Rr, S.Y, S.Z);
+        launch_nrm2_b(s, P, A.all, B, S.Z, SC_BETA);
+        launch_gmres_start_b(s, P, B);
+        launch_gate_b(s, P, B, F_INNER);
+        launch_scale_inv_b(s, P, A.all, B, mp, S.Z, S.V0, SC_BETA);
+        for (int k = 0; k < rp.kcycle; ++k) {
+            launch_gate_b(s, P, B, F_INNER);
+            launch_zmv_b(s, bt.m, P, A.wz, A.wr, S.V0 + k, S.U, -1, 0, 0);
+            launch_prec_apply_b(s, P, A.wp, S.U, S.Y, S.V0 + k + 1);
+            launch_arnoldi_b(s, P, B, k, S.V0, rp.kcycle, rp.inner_tol, rp.max_gmres);
+        }
+        launch_gmres_finish_b(s, P, B, rp.kcycle);
+        launch_gate_b(s, P, B, F_DOGMRES);
+        launch_multi_axpy_b(s, P, A.all, B, mp, S.V0, rp.kcycle, SC_Y, S.X, 1.0);
     }
+}
+
+// Capture one step of the batched search (or of the fixed-scale solves) as a
+// graph: each cloud's next scale, the factorisation, the refinement, min w,
+// the bracket update and, for Newton steps, d(min w)/dt; then the count of
+// clouds still searching into dcount[0..2).
+int build_step_graph(Batch &bt, const std::vector<FLaunch> &fseq, const AllWork &A, SState *S, const SParams &prm,
+                     const RefPlan &rp, const RefPlan &dp, int *dcount)
+{
+    const Slots &SL = bt.sl;
+    hipStream_t s = bt.s;
+    BProb *P = bt.d;
+    const int B = bt.B;
+    const int64_t mp = bt.maxpad;
+    BRC(bt.flush_persistent());     // work lists and states, in one copy
+    BCHK(hipStreamSynchronize(s));
+    BCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    launch_search_select_b(s, P, S, B, prm);
+    record_factor(bt, fseq);
+    launch_breakdown_b(s, P, S, B);
+    launch_gate_b(s, P, B, F_SEARCH);
+    launch_fill_b(s, P, A.all, B, mp, SL.Rhs, 1.0, true);
+    record_refine(bt, A, SL.Rhs, -1, rp);
+    launch_gate_b(s, P, B, F_SEARCH);
+    launch_summin_b(s, P, A.all, B, SL.Best, SC_SUM);
+    launch_search_update_b(s, P, S, B, prm);
+    launch_gate_b(s, P, B, F_HI);
+    launch_copy_b(s, P, A.all, B, mp, SL.Best, SL.W);
+    if (prm.newton) {
+        // dw/dt = Z^{-1} (D o Z) w with this step's factor; its entry at argmin w
+        launch_gate_b(s, P, B, F_NEEDD);
+        launch_copy_b(s, P, A.all, B, mp, SL.Best, SL.DZ);
+        launch_dzmv_b(s, bt.m, P, A.wdz, A.wdr, SL.DZ, SL.Rhs);
+        launch_amax_b(s, P, A.all, B, SL.Rhs, SC_AMAX);
+        record_refine(bt, A, SL.Rhs, SC_AMAX, dp);
+        launch_gate_b(s, P, B, F_NEEDD);
+        launch_pick_b(s, P, A.all, B, SL.Best, SC_SUM + 2, SC_PICK);
+        launch_search_deriv_b(s, P, S, B);
+    }
+    launch_search_count_b(s, S, B, dcount);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(s, &g) != hipSuccess) return MAG_EHIP;
+    bt.graph_def = g;
+    BCHK(hipGraphInstantiate(&bt.graph, g, nullptr, nullptr, 0));
     return MAG_OK;
+}
+
+// Run step graphs until no cloud is searching (one count read per step).
+// Returns the number of steps, or a negative error code.
+int run_steps(Batch &bt, const int *dcount, int max_steps)
+{
+    int *hc = reinterpret_cast<int *>(bt.c->host_scalars + 60);
+    for (int step = 0; step < max_steps; ++step) {
+        BCHK(hipGraphLaunch(bt.graph, bt.s));
+        BCHK(hipMemcpyAsync(hc, dcount, 2 * sizeof(int), hipMemcpyDeviceToHost, bt.s));
+        BCHK(hipStreamSynchronize(bt.s));
+        if (hc[1]) return MAG_ENOTPD;  // the FP32 factor broke down at every shift
+        if (hc[0] == 0) return step + 1;
+    }
+    return MAG_ENOCONV;
+}
+
+// Checks of every cloud in one pass: finite coordinates (MAG_EINVAL) and the
+// squared minimum distance by brute force (0: coincident points, MAG_ENOTPD),
+// returned in dmin2.  One host sync.
+int batch_validate(Batch &bt, std::vector<double> &dmin2)
+{
+    mag_ctx *c = bt.c;
+    int *status = (int *)c->ints.p;
+    launch_fill_ints(bt.s, status, 8, 0);
+    std::vector<int> pl;
+    for (int b = 0; b < bt.B; ++b) {
+        const BProb &q = bt.h[b];
+        launch_check_finite(bt.s, q.X, q.n * (int64_t)bt.m, status);
+        if (q.n >= 2) {
+            launch_dmin2(bt.s, q.X, q.n, bt.m, q.partial, nullptr, q.scal + SC_PICK);
+            pl.push_back(b);
+        }
+    }
+    BCHK(hipMemcpyAsync(c->host_scalars + 56, status, 8 * sizeof(int), hipMemcpyDeviceToHost, bt.s));
+    dmin2.assign(bt.B, INFINITY);
+    if (!pl.empty()) {
+        const int *pd = bt.put(pl, false);
+        if (!pd) return MAG_ENOMEM;
+        std::vector<double> v;
+        BRC(bt.gather(pd, (int)pl.size(), SC_PICK, 1, v));
+        for (size_t i = 0; i < pl.size(); ++i) dmin2[pl[i]] = v[i];
+    } else {
+        BRC(bt.sync());
+    }
+    if (((const int *)(c->host_scalars + 56))[kStNonFinite]) return MAG_EINVAL;
+    for (int b = 0; b < bt.B; ++b)
+        if (!(dmin2[b] > 0.0)) return MAG_ENOTPD;
+    return MAG_OK;
+}
+
+RefPlan main_plan(const mag_opts &o, int restart)
+{
+    RefPlan rp;
+    rp.rounds = std::max(1, std::min(o.max_outer, 4));  // one plain round, then three that may run GMRES
+    rp.kcycle = std::max(1, std::min(restart, 12));
+    rp.max_gmres = o.max_gmres > 0 ? o.max_gmres : 200;
+    rp.tol = o.tol > 0 ? o.tol : 1e-12;
+    rp.inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-10;
+    return rp;
 }
 
 }  // namespace
@@ -590,53 +761,165 @@ int mag_weighting_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *o
         Xs[b] = X + offs[b] * m;
         ns[b] = offs[b + 1] - offs[b];
         ts[b] = t[b];
+        if (ns[b] < 1) return MAG_EINVAL;
     }
-    BRC(validate_batch(c, Xs, ns, m));
     Batch bt;
-    const int restart = std::min(38, std::max(1, o.gmres_restart));
+    const int restart = std::min(kMaxRestart, std::max(1, o.gmres_restart));
     BRC(batch_setup(c, bt, Xs, ns, m, ts, restart));
-    BRC(batch_build_graph(bt));
-    std::vector<int> shifted;
-    BRC(batch_factor(bt, shifted));
-    std::vector<int> ids(B);
-    for (int b = 0; b < B; ++b) ids[b] = b;
-    {
-        BWork w1;
-        BRC(bt.make_work(ids, [](int) { return (int64_t)1; }, false, w1));
-        launch_fill_b(bt.s, bt.d, w1.plist, w1.na, bt.maxpad, bt.sl.Rhs, 1.0, true);
-    }
-    std::vector<BRefine> st;
-    std::vector<double> bn(B, 1.0);
-    BRC(batch_refine(bt, ids, bt.sl.Rhs, bn, o, st));
+    std::vector<double> dmin2;
+    BRC(batch_validate(bt, dmin2));
+    // one fixed-scale solve per problem, retried with a shift after an FP32 breakdown
+    std::vector<SState> st0(B);
+    std::memset(st0.data(), 0, sizeof(SState) * B);
+    SState *Sd = bt.put(st0, true);
+    if (!Sd) return MAG_ENOMEM;
+    std::vector<FLaunch> fseq;
+    BRC(batch_factor_schedule(bt, fseq));
+    AllWork A;
+    BRC(make_all_work(bt, A));
+    SParams prm{};
+    prm.fixed = 1;
+    int *dcount = reinterpret_cast<int *>(bt.dstage + (size_t)B * 128);
+    const RefPlan rp = main_plan(o, restart);
+    BRC(build_step_graph(bt, fseq, A, Sd, prm, rp, rp, dcount));
+    const int steps = run_steps(bt, dcount, 8);
+    if (steps < 0) return steps;
+    std::vector<SState> st(B);
+    BCHK(hipMemcpyAsync(st.data(), Sd, sizeof(SState) * B, hipMemcpyDeviceToHost, bt.s));
+    std::vector<int> all(B);
+    for (int b = 0; b < B; ++b) all[b] = b;
     BWork w1;
-    BRC(bt.make_work(ids, [](int) { return (int64_t)1; }, false, w1));
+    BRC(bt.make_work(all, [](int) { return (int64_t)1; }, false, w1));
+    std::vector<double> rc;
+    BRC(bt.gather(w1.plist, w1.na, SC_RC, 8, rc));
+    // items the graph's rounds did not take to tol: the host-driven refinement
+    // from scratch with the factor in place (GMRES with the caller's limits)
+    std::vector<int> redo;
+    for (int b = 0; b < B; ++b)
+        if (st[b].unconverged) redo.push_back(b);
+    std::vector<BRefine> fb;
+    if (!redo.empty()) {
+        for (int b = 0; b < B; ++b) bt.h[b].active = 0;
+        for (int b : redo) bt.h[b].active = 1;
+        BRC(bt.upload_desc());
+        BWork wr;
+        BRC(bt.make_work(redo, [](int) { return (int64_t)1; }, false, wr));
+        launch_fill_b(bt.s, bt.d, wr.plist, wr.na, bt.maxpad, bt.sl.Rhs, 1.0, true);
+        std::vector<double> bn(B, 1.0);
+        BRC(batch_refine(bt, redo, bt.sl.Rhs, bn, o, fb));
+    }
+    for (int b = 0; b < B; ++b) bt.h[b].active = 1;
+    BRC(bt.upload_desc());
+    // transient lists do not outlive a sync (the gathers above reset the arena)
+    BWork wo;
+    BRC(bt.make_work(all, [](int) { return (int64_t)1; }, false, wo));
     std::vector<int64_t> po(B);
     for (int b = 0; b < B; ++b) po[b] = offs[b] - offs[0];
     const int64_t *po_dev = bt.put(po, false);
     if (!po_dev) return MAG_ENOMEM;
-    launch_unpack_b(bt.s, bt.d, w1.plist, w1.na, po_dev, bt.sl.Best, w, bt.maxn);
-    launch_summin_b(bt.s, bt.d, w1.plist, w1.na, bt.sl.Best, SC_SUM);
+    launch_unpack_b(bt.s, bt.d, wo.plist, wo.na, po_dev, bt.sl.Best, w, bt.maxn);
+    launch_summin_b(bt.s, bt.d, wo.plist, wo.na, bt.sl.Best, SC_SUM);
     std::vector<double> sums;
-    BRC(bt.gather(w1.plist, w1.na, SC_SUM, 3, sums));
-    int rc = MAG_OK;
+    BRC(bt.gather(wo.plist, wo.na, SC_SUM, 3, sums));
+    int rc_all = MAG_OK;
     for (int b = 0; b < B; ++b) {
+        const bool redone = st[b].unconverged != 0;
+        const bool ok = redone ? fb[b].ok != 0 : true;
         if (M) M[b] = sums[3 * b];
-        if (!st[b].ok) rc = MAG_ENOCONV;
+        if (!ok) rc_all = MAG_ENOCONV;
         if (info) {
             mag_info &f = info[b];
             std::memset(&f, 0, sizeof(f));
-            f.status = st[b].ok ? MAG_OK : MAG_ENOCONV;
-            f.outer_iters = st[b].outer;
-            f.gmres_iters = st[b].inner;
-            f.shifted = shifted[b];
-            f.shift = bt.h[b].shift;
-            f.resid_inf = st[b].best;
+            f.status = ok ? MAG_OK : MAG_ENOCONV;
+            f.outer_iters = redone ? fb[b].outer : (int)rc[8 * b + RC_ROUND];
+            f.gmres_iters = redone ? fb[b].inner : (int)rc[8 * b + RC_INNER];
+            f.shifted = st[b].shift > 0.0 ? 1 : 0;
+            f.shift = st[b].shift;
+            f.resid_inf = redone ? fb[b].best : rc[8 * b + RC_BEST];
             f.magnitude = sums[3 * b];
             f.min_w = sums[3 * b + 1];
             f.argmin_w = (int64_t)sums[3 * b + 2];
+            f.solver = MAG_FP32_IR;
         }
     }
-    return rc;
+    return rc_all;
+}
+
+// ---- tuning of the batched factorisation ---------------------------------------
+
+int mag_tune_batch_group(mag_ctx *c, int64_t max_n, int32_t group)
+{
+    if (!c || max_n < 1 || group < 0 || group > 2) return MAG_EINVAL;
+    c->tune_bgroup[size_bucket(round_up(max_n, kPad))] = group;
+    return MAG_OK;
+}
+
+int mag_autotune_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs, int32_t m, const double *t,
+                       int32_t reps, int32_t *group_out, double *ms_out)
+{
+    if (!c || B < 1 || !X || !offs || !t || m < 1) return MAG_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return MAG_EHIP;
+    std::vector<const double *> Xs(B);
+    std::vector<int64_t> ns(B);
+    std::vector<double> ts(B);
+    for (int b = 0; b < B; ++b) {
+        if (offs[b + 1] <= offs[b] || !(std::isfinite(t[b]) && t[b] > 0.0)) return MAG_EINVAL;
+        Xs[b] = X + offs[b] * m;
+        ns[b] = offs[b + 1] - offs[b];
+        ts[b] = t[b];
+    }
+    Batch bt;
+    BRC(batch_setup(c, bt, Xs, ns, m, ts, 1));
+    std::vector<double> dmin2;
+    BRC(batch_validate(bt, dmin2));
+    // the two schedules' launch sequences, each captured into a graph of its own
+    hipGraph_t gdef[2] = {nullptr, nullptr};
+    hipGraphExec_t gexe[2] = {nullptr, nullptr};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double best[2] = {INFINITY, INFINITY};
+    int rc = MAG_OK;
+    std::vector<FLaunch> seq[2];
+    for (int q = 0; q < 2 && rc == MAG_OK; ++q) rc = batch_factor_schedule(bt, seq[q], q + 1);
+    if (rc == MAG_OK) rc = bt.flush_persistent();
+    if (rc == MAG_OK && hipStreamSynchronize(bt.s) != hipSuccess) rc = MAG_EHIP;
+    for (int q = 0; q < 2 && rc == MAG_OK; ++q) {
+        if (hipStreamBeginCapture(bt.s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = MAG_EHIP;
+            break;
+        }
+        record_factor(bt, seq[q]);
+        if (hipStreamEndCapture(bt.s, &gdef[q]) != hipSuccess ||
+            hipGraphInstantiate(&gexe[q], gdef[q], nullptr, nullptr, 0) != hipSuccess)
+            rc = MAG_EHIP;
+    }
+    if (rc == MAG_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = MAG_EHIP;
+    for (int rep = 0; rep < std::max(1, reps) && rc == MAG_OK; ++rep) {
+        for (int q = 0; q < 2; ++q) {
+            float ms = 0.0f;
+            if (hipEventRecord(e0, bt.s) != hipSuccess || hipGraphLaunch(gexe[q], bt.s) != hipSuccess ||
+                hipEventRecord(e1, bt.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = MAG_EHIP;
+                break;
+            }
+            best[q] = std::min(best[q], (double)ms);
+        }
+    }
+    for (int q = 0; q < 2; ++q) {
+        if (gexe[q]) hipGraphExecDestroy(gexe[q]);
+        if (gdef[q]) hipGraphDestroy(gdef[q]);
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (rc != MAG_OK) return rc;
+    const int pick = best[0] < best[1] ? 1 : 2;
+    c->tune_bgroup[size_bucket(bt.maxpad)] = pick;
+    if (group_out) *group_out = pick;
+    if (ms_out) {
+        ms_out[0] = best[0];
+        ms_out[1] = best[1];
+    }
+    return MAG_OK;
 }
 
 // ---- batched cutoff search -----------------------------------------------------
@@ -661,274 +944,84 @@ int mag_tplus_batch(mag_ctx *c, int32_t B, const double *X, const int64_t *offs,
         if (offs[b + 1] < offs[b]) return MAG_EINVAL;
         Xs[b] = X + offs[b] * m;
         ns[b] = offs[b + 1] - offs[b];
+        if (ns[b] < 1) return MAG_EINVAL;
     }
-    BRC(validate_batch(c, Xs, ns, m));
-    if (m > pair_max_dim() && to.newton) to.newton = 0;
     const bool ridders = to.method == MAG_TPLUS_RIDDERS;
-    if (ridders) to.newton = 0;
-
-    // per-cloud state of the search (same rules as mag_tplus)
-    struct Cloud {
-        int phase = 0;  // 0 grid scan, 1 bracket refinement, 2 done
-        double tb = 0, dmin = 0, eps = 0, top = 0;
-        int gi = 0, ext = 0;
-        bool have_hi = false, have_lo = false, prev_newton = false, want_deriv = false;
-        double hi = 0, hi_min = 0, lo = 0, lo_min = 0;
-        double last_t = 0, last_min = 0, last_d = 0;
-        bool last_has_d = false;
-        double prev_step = INFINITY;
-        int solves = 0, newton_steps = 0, no_sign = 0;
-        double cur = 0;
-        bool cur_newton = false;
-        // Ridders: the bracket (log t, min w) at the start of a step, whether its
-        // midpoint has been evaluated (then the Ridders point is next), and what
-        // the current evaluation is (0 other, 1 midpoint, 2 Ridders point)
-        double ra = 0, rga = 0, rb = 0, rgb = 0, rgm = 0;
-        bool rid_pending = false;
-        int cur_kind = 0;
-    };
-    std::vector<Cloud> cl(B);
-    std::vector<double> ts(B, 1.0);
+    Batch bt;
+    const int restart = std::min(kMaxRestart, std::max(1, o.gmres_restart));
+    BRC(batch_setup(c, bt, Xs, ns, m, std::vector<double>(B, 1.0), restart));
+    std::vector<double> dmin2;
+    BRC(batch_validate(bt, dmin2));
+    // each cloud's search state: the bound t_b = log(n - 1)/d_min, the grid from it
+    std::vector<SState> st0(B);
+    std::memset(st0.data(), 0, sizeof(SState) * B);
     for (int b = 0; b < B; ++b) {
-        Cloud &q = cl[b];
+        SState &q = st0[b];
         if (ns[b] <= 2) {
             q.phase = 2;
             q.no_sign = 1;
             continue;
         }
-        double dm = 0.0;
-        BRC(mag_dmin(c, Xs[b], ns[b], m, &dm));
-        q.dmin = dm;
+        const double dm = std::sqrt(dmin2[b]);
         q.tb = std::log((double)(ns[b] - 1)) / dm;
         q.eps = to.eps > 0.0 ? to.eps : (double)ns[b] * std::ldexp(1.0, -53);
         q.top = q.tb;
         q.gi = to.grid - 1;
-        ts[b] = q.tb;
+        q.prev_step = INFINITY;
     }
-    Batch bt;
-    const int restart = std::min(38, std::max(1, o.gmres_restart));
-    BRC(batch_setup(c, bt, Xs, ns, m, ts, restart));
-    BRC(batch_build_graph(bt));
-    const Slots &S = bt.sl;
-    auto one = [](int) { return (int64_t)1; };
-    const bool newton = to.newton != 0;
-
-    for (int step = 0; step < 1000; ++step) {
-        // choose every active cloud's next scale
-        std::vector<int> act;
-        for (int b = 0; b < B; ++b) {
-            Cloud &q = cl[b];
-            bt.h[b].active = 0;
-            if (q.phase == 2) continue;
-            double tc = 0.0;
-            q.cur_newton = false;
-            if (q.phase == 0) {
-                // next grid point below the current upper end
-                for (;;) {
-                    if (q.gi < 0) {
-                        if (q.ext >= to.max_extend) break;
-                        ++q.ext;
-                        q.top *= to.lo_factor;
-                        q.gi = to.grid - 1;
-                    }
-                    tc = q.top * std::pow(to.lo_factor, (double)(to.grid - 1 - q.gi) / (to.grid - 1));
-                    --q.gi;
-                    if (!(q.have_hi && tc >= q.hi)) break;
-                    tc = 0.0;
-                }
-                if (tc <= 0.0) {
-                    q.phase = 2;
-                    q.no_sign = 1;
-                    continue;
-                }
-            } else {
-                if ((q.hi - q.lo) / q.hi <= to.rtol) {
-                    q.phase = 2;
-                    continue;
-                }
-                const double slo = std::log(q.lo), shi = std::log(q.hi), mid = 0.5 * (slo + shi);
-                double sc = mid;
-                q.cur_kind = 0;
-                if (ridders) {
-                    // the same steps as mag_tplus, one evaluation per batched solve
-                    if (q.rid_pending) {
-                        const double sx = ridders_point(q.ra, q.rga, q.rb, q.rgb, q.rgm);
-                        if (sx > slo && sx < shi) {
-                            sc = sx;
-                            q.cur_kind = 2;
-                        }
-                    }
-                    if (q.cur_kind == 0) {
-                        q.ra = slo;
-                        q.rga = q.lo_min;
-                        q.rb = shi;
-                        q.rgb = q.hi_min;
-                        q.cur_kind = 1;
-                    }
-                }
-                if (newton && q.last_has_d && q.last_d != 0.0) {
-                    const double sl = std::log(q.last_t);
-                    const double sn = sl - q.last_min / (q.last_t * q.last_d);
-                    const double stp = std::fabs(sn - sl);
-                    if (sn > slo && sn < shi && (!q.prev_newton || stp <= 0.5 * q.prev_step)) {
-                        sc = sn;
-                        q.cur_newton = true;
-                        q.prev_step = stp;
-                        const double close = 0.25 * to.rtol;
-                        if (sc - slo < close) sc = std::min(slo + 0.75 * to.rtol, mid);
-                        if (shi - sc < close) sc = std::max(shi - 0.75 * to.rtol, mid);
-                    }
-                }
-                q.prev_newton = q.cur_newton;
-                if (!q.cur_newton) q.prev_step = INFINITY;
-                tc = std::exp(sc);
-                if (q.cur_kind == 2 && !(tc > q.lo && tc < q.hi)) {
-                    // the Ridders point rounds onto a bracket end: take the midpoint
-                    q.ra = slo;
-                    q.rga = q.lo_min;
-                    q.rb = shi;
-                    q.rgb = q.hi_min;
-                    q.cur_kind = 1;
-                    tc = std::exp(mid);
-                }
-                if (!(tc > q.lo && tc < q.hi)) {
-                    q.phase = 2;
-                    continue;
-                }
-            }
-            q.cur = tc;
-            bt.h[b].t = tc;
-            bt.h[b].active = 1;
-            bt.h[b].shift = 0.0;
-            act.push_back(b);
-        }
-        if (act.empty()) break;
-        // one batched solve at every active cloud's scale
-        std::vector<int> shifted;
-        BRC(batch_factor(bt, shifted));
-        {
-            BWork w1;
-            BRC(bt.make_work(act, one, false, w1));
-            launch_fill_b(bt.s, bt.d, w1.plist, w1.na, bt.maxpad, S.Rhs, 1.0, true);
-        }
-        std::vector<BRefine> st;
-        std::vector<double> bn(B, 1.0);
-        BRC(batch_refine(bt, act, S.Rhs, bn, o, st));
-        std::vector<double> mins;
-        {
-            BWork w1;
-            BRC(bt.make_work(act, one, false, w1));
-            launch_summin_b(bt.s, bt.d, w1.plist, w1.na, S.Best, SC_SUM);
-            launch_copy_b(bt.s, bt.d, w1.plist, w1.na, bt.maxpad, S.Best, S.DZ);  // w of this step
-            BRC(bt.gather(w1.plist, w1.na, SC_SUM, 3, mins));
-        }
-        // update the states; collect clouds that need d(min w)/dt at this point
-        std::vector<int> need_d;
-        for (size_t i = 0; i < act.size(); ++i) {
-            const int b = act[i];
-            Cloud &q = cl[b];
-            const double mw = mins[3 * i + 1];
-            ++q.solves;
-            if (q.cur_newton) ++q.newton_steps;
-            if (ridders && q.phase == 1) {
-                if (q.cur_kind == 2) ++q.newton_steps;
-                q.rid_pending = q.cur_kind == 1;
-                q.rgm = mw;
-            }
-            q.last_t = q.cur;
-            q.last_min = mw;
-            q.last_has_d = false;
-            if (q.phase == 0) {
-                if (mw < 0.0) {
-                    q.have_lo = true;
-                    q.lo = q.cur;
-                    q.lo_min = mw;
-                    q.phase = 1;
-                    if (newton) need_d.push_back(b);
-                } else {
-                    q.have_hi = true;
-                    q.hi = q.cur;
-                    q.hi_min = mw;
-                    std::vector<int> one_b(1, b);
-                    BWork w1;
-                    BRC(bt.make_work(one_b, one, false, w1));
-                    launch_copy_b(bt.s, bt.d, w1.plist, 1, bt.maxpad, S.Best, S.W);  // w at hi
-                }
-            } else {
-                if (mw < 0.0) {
-                    q.lo = q.cur;
-                    q.lo_min = mw;
-                } else {
-                    q.hi = q.cur;
-                    q.hi_min = mw;
-                    std::vector<int> one_b(1, b);
-                    BWork w1;
-                    BRC(bt.make_work(one_b, one, false, w1));
-                    launch_copy_b(bt.s, bt.d, w1.plist, 1, bt.maxpad, S.Best, S.W);
-                    if (mw < q.eps) q.phase = 2;  // halting rule: 0 <= min w < eps
-                }
-                if (newton && q.phase == 1) need_d.push_back(b);
-            }
-        }
-        if (!need_d.empty()) {
-            // (D o Z) w with the factor of this step, then Z^{-1} of it
-            BWork wz, wr, w1;
-            BRC(bt.make_work(need_d, [&](int p) { return dz_b_units(bt.h[p].n); }, false, wz));
-            BRC(bt.make_work(need_d, [&](int p) { return bt.h[p].npad / 256; }, false, wr));
-            BRC(bt.make_work(need_d, one, false, w1));
-            for (int b = 0; b < B; ++b) bt.h[b].active = 0;
-            for (int b : need_d) bt.h[b].active = 1;
-            BRC(bt.upload_desc());
-            launch_dzmv_b(bt.s, bt.m, bt.d, wz, wr, S.DZ, S.Rhs);
-            launch_amax_b(bt.s, bt.d, w1.plist, w1.na, S.Rhs, SC_AMAX);
-            std::vector<double> am;
-            BRC(bt.gather(w1.plist, w1.na, SC_AMAX, 1, am));
-            std::vector<double> bnd(B, 1.0);
-            for (size_t i = 0; i < need_d.size(); ++i) bnd[need_d[i]] = am[i];
-            std::vector<BRefine> st2;
-            BRC(batch_refine(bt, need_d, S.Rhs, bnd, o, st2));
-            BWork w2;
-            BRC(bt.make_work(need_d, one, false, w2));
-            launch_pick_b(bt.s, bt.d, w2.plist, w2.na, S.Best, SC_SUM + 2, SC_PICK);
-            std::vector<double> dd;
-            BRC(bt.gather(w2.plist, w2.na, SC_PICK, 1, dd));
-            for (size_t i = 0; i < need_d.size(); ++i) {
-                Cloud &q = cl[need_d[i]];
-                q.last_d = dd[i];
-                q.last_has_d = std::isfinite(dd[i]);
-            }
-        }
-    }
-    // outputs
+    SState *Sd = bt.put(st0, true);
+    if (!Sd) return MAG_ENOMEM;
+    std::vector<FLaunch> fseq;
+    BRC(batch_factor_schedule(bt, fseq));
+    AllWork A;
+    BRC(make_all_work(bt, A));
+    SParams prm{};
+    prm.grid = to.grid;
+    prm.max_extend = to.max_extend;
+    prm.newton = (to.newton && !ridders) ? 1 : 0;
+    prm.ridders = ridders ? 1 : 0;
+    prm.fixed = 0;
+    prm.lo_factor = to.lo_factor;
+    prm.rtol = to.rtol;
+    int *dcount = reinterpret_cast<int *>(bt.dstage + (size_t)B * 128);
+    const RefPlan rp = main_plan(o, restart);
+    RefPlan dp = rp;  // the Newton derivative: a shorter refinement suffices for a safeguarded step
+    dp.rounds = std::min(rp.rounds, 2);
+    dp.kcycle = std::min(rp.kcycle, 8);
+    BRC(build_step_graph(bt, fseq, A, Sd, prm, rp, dp, dcount));
+    const int steps = run_steps(bt, dcount, 1000);
+    if (steps < 0) return steps;
+    std::vector<SState> st(B);
+    BCHK(hipMemcpyAsync(st.data(), Sd, sizeof(SState) * B, hipMemcpyDeviceToHost, bt.s));
+    BRC(bt.sync());
     std::vector<int> ids;
     for (int b = 0; b < B; ++b) {
-        t_plus[b] = (cl[b].no_sign || !cl[b].have_lo) ? 0.0 : cl[b].hi;
-        if (w && !cl[b].no_sign && cl[b].have_lo) ids.push_back(b);
+        const bool none = st[b].no_sign || !st[b].have_lo;
+        t_plus[b] = none ? 0.0 : st[b].hi;
+        if (w && !none) ids.push_back(b);
         if (info) {
             mag_tplus_info &f = info[b];
             std::memset(&f, 0, sizeof(f));
             f.t_plus = t_plus[b];
-            f.t_bound = cl[b].tb;
-            f.d_min = cl[b].dmin;
-            f.min_w = cl[b].hi_min;
-            f.t_bracket_lo = cl[b].lo;
-            f.t_bracket_hi = cl[b].hi;
-            f.solves = cl[b].solves;
-            f.newton_steps = cl[b].newton_steps;
-            f.no_sign_change = (cl[b].no_sign || !cl[b].have_lo) ? 1 : 0;
+            f.t_bound = st[b].tb;
+            f.d_min = std::sqrt(dmin2[b]);
+            f.min_w = st[b].hi_min;
+            f.t_bracket_lo = st[b].lo;
+            f.t_bracket_hi = st[b].hi;
+            f.solves = st[b].solves;
+            f.newton_steps = st[b].newton_steps;
+            f.no_sign_change = none ? 1 : 0;
             f.status = MAG_OK;
         }
     }
     if (!ids.empty()) {
-        for (int b = 0; b < B; ++b) bt.h[b].active = 1;
-        BRC(bt.upload_desc());
         BWork w1;
-        BRC(bt.make_work(ids, one, false, w1));
+        BRC(bt.make_work(ids, [](int) { return (int64_t)1; }, false, w1));
         std::vector<int64_t> po;
         for (int b : ids) po.push_back(offs[b] - offs[0]);
         const int64_t *po_dev = bt.put(po, false);
         if (!po_dev) return MAG_ENOMEM;
-        launch_unpack_b(bt.s, bt.d, w1.plist, w1.na, po_dev, S.W, w, bt.maxn);
+        launch_unpack_b(bt.s, bt.d, w1.plist, w1.na, po_dev, bt.sl.W, w, bt.maxn);
         BRC(bt.sync());
     }
     return MAG_OK;

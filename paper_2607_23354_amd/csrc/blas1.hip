@@ -237,6 +237,7 @@ __global__ void k_scale(const double *x, double a, double *y, int64_t n, int64_t
 __global__ void k_fill_b(const BProb *__restrict__ P, const int *plist, int slot, double v, int upto_n)
 {
     const BProb &q = P[plist[blockIdx.y]];
+    if (!q.active) return;
     double *x = q.vec + (int64_t)slot * q.npad;
     const int64_t len = upto_n ? q.n : q.npad;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q.npad;
@@ -247,6 +248,7 @@ __global__ void k_fill_b(const BProb *__restrict__ P, const int *plist, int slot
 __global__ void k_copy_b(const BProb *__restrict__ P, const int *plist, int src, int dst)
 {
     const BProb &q = P[plist[blockIdx.y]];
+    if (!q.active) return;
     const double *x = q.vec + (int64_t)src * q.npad;
     double *y = q.vec + (int64_t)dst * q.npad;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < q.npad;
@@ -259,6 +261,7 @@ __global__ void k_scale_inv_b(const BProb *__restrict__ P, const int *plist, int
                               int64_t scal_off)
 {
     const BProb &q = P[plist[blockIdx.y]];
+    if (!q.active) return;
     const double a = 1.0 / q.scal[scal_off];
     const double *x = q.vec + (int64_t)src * q.npad;
     double *y = q.vec + (int64_t)dst * q.npad;
@@ -273,6 +276,7 @@ k_multidot_partial_b(const BProb *__restrict__ P, const int *plist, int v0, int 
 {
     __shared__ double red[RB];
     const BProb &q = P[plist[blockIdx.y]];
+    if (!q.active) return;
     const int g = blockIdx.x;
     const int64_t len = q.npad;
     const double *u = q.vec + (int64_t)u_slot * len;
@@ -293,6 +297,7 @@ __global__ void __launch_bounds__(RB) k_rows_sum_b(const BProb *__restrict__ P, 
 {
     __shared__ double red[RB];
     const BProb &q = P[plist[blockIdx.x]];
+    if (!q.active) return;
     for (int j = 0; j < k; ++j) {
         double s = (threadIdx.x < RG) ? q.partial[(int64_t)j * RG + threadIdx.x] : 0.0;
         s = block_sum(s, red);
@@ -305,6 +310,7 @@ __global__ void k_multi_axpy_b(const BProb *__restrict__ P, const int *plist, in
                                int64_t h_off, int u_slot, double sign)
 {
     const BProb &q = P[plist[blockIdx.y]];
+    if (!q.active) return;
     const double *h = q.scal + h_off;
     double *u = q.vec + (int64_t)u_slot * q.npad;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < q.npad;
@@ -320,6 +326,7 @@ __global__ void k_multi_axpy_hb(const BProb *__restrict__ P, const int *plist, i
                                 const double *hb, int u_slot, double sign)
 {
     const BProb &q = P[plist[blockIdx.y]];
+    if (!q.active) return;
     const double *h = hb + (int64_t)blockIdx.y * k;
     double *u = q.vec + (int64_t)u_slot * q.npad;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < q.npad;
@@ -336,6 +343,7 @@ __global__ void __launch_bounds__(RB) k_nrm2_b(const BProb *__restrict__ P, cons
     // one block per problem (vectors are short in batched use)
     __shared__ double red[RB];
     const BProb &q = P[plist[blockIdx.x]];
+    if (!q.active) return;
     const double *x = q.vec + (int64_t)slot * q.npad;
     double s = 0.0;
     for (int64_t e = threadIdx.x; e < q.npad; e += RB) s = fma(x[e], x[e], s);
@@ -351,6 +359,7 @@ __global__ void __launch_bounds__(RB) k_summin_b(const BProb *__restrict__ P, co
     __shared__ double rmin[RB];
     __shared__ int64_t rarg[RB];
     const BProb &q = P[plist[blockIdx.x]];
+    if (!q.active) return;
     const double *x = q.vec + (int64_t)slot * q.npad;
     double s = 0.0, c = 0.0, mn = INFINITY;
     int64_t am = -1;
@@ -387,6 +396,7 @@ __global__ void __launch_bounds__(RB) k_amax_b(const BProb *__restrict__ P, cons
 {
     __shared__ double red[RB];
     const BProb &q = P[plist[blockIdx.x]];
+    if (!q.active) return;
     const double *x = q.vec + (int64_t)slot * q.npad;
     double s = 0.0;
     for (int64_t e = threadIdx.x; e < q.npad; e += RB) s = fmax(s, fabs(x[e]));
@@ -415,6 +425,7 @@ __global__ void k_pick_b(const BProb *__restrict__ P, const int *plist, int na, 
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= na) return;
     const BProb &q = P[plist[i]];
+    if (!q.active) return;
     const int64_t j = (int64_t)q.scal[idx_off];
     q.scal[dst] = (j >= 0 && j < q.n) ? q.vec[(int64_t)slot * q.npad + j] : 0.0;
 }

@@ -248,6 +248,8 @@ k_syrk_lower(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, in
 //           kk + 256) by the first panel of the pair at kk (K = 256); the
 //           tile above the strip's 128-diagonal is rewritten by the second
 //           panel's own TRSM
+//   KIND 4: trailing SYRK (lower tiles) by the single panel at kk (K = 256),
+//           for the schedule without pairs
 template <int KIND>
 __global__ void __launch_bounds__(NT, 2)
 k_gemm_b(const BProb *__restrict__ Pr, BWork w, int64_t kk)
@@ -272,10 +274,16 @@ k_gemm_b(const BProb *__restrict__ Pr, BWork w, int64_t kk)
         const float *Pp = A + kk * np + kk + 4 * BT;
         gemm_tile_body<kGemmSub, true>(A + (kk + 4 * BT) * np + kk + 4 * BT, np, Pp, np, Pp, np, ti, tj,
                                        4 * BT, nullptr);
-    } else {
+    } else if (KIND == 3) {
         const int64_t T = (np - kk - 2 * BT) / BT;
         const float *Pp = A + kk * np + kk + 2 * BT;
         gemm_tile_body<kGemmSub, true>(A + (kk + 2 * BT) * np + kk + 2 * BT, np, Pp, np, Pp, np, u % T, u / T,
+                                       2 * BT, nullptr);
+    } else {
+        int64_t ti, tj;
+        tri_index(u, ti, tj);
+        const float *Pp = A + kk * np + kk + 2 * BT;
+        gemm_tile_body<kGemmSub, true>(A + (kk + 2 * BT) * np + kk + 2 * BT, np, Pp, np, Pp, np, ti, tj,
                                        2 * BT, nullptr);
     }
 }
@@ -293,6 +301,11 @@ int64_t gemm_b_units(int kind, int64_t npad, int64_t kk)
         const int64_t rows = npad - kk - 2 * BT;
         return rows > 0 ? 2 * (rows / BT) : 0;
     }
+    if (kind == 4) {
+        const int64_t rows = npad - kk - 2 * BT;
+        const int64_t T = rows > 0 ? rows / BT : 0;
+        return T * (T + 1) / 2;
+    }
     const int64_t rows = npad - kk - 4 * BT;
     const int64_t T = rows > 0 ? rows / BT : 0;
     return T * (T + 1) / 2;
@@ -307,6 +320,8 @@ void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int6
         hipLaunchKernelGGL(k_gemm_b<1>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
     else if (kind == 2)
         hipLaunchKernelGGL(k_gemm_b<2>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
+    else if (kind == 4)
+        hipLaunchKernelGGL(k_gemm_b<4>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
     else
         hipLaunchKernelGGL(k_gemm_b<3>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
 }

@@ -304,6 +304,7 @@ __global__ void __launch_bounds__(256) k_max_final_sym_b(const BProb *__restrict
 {
     __shared__ double red[256];
     const BProb &q = P[w.plist[blockIdx.x]];
+    if (!q.active) return;
     const int64_t T = q.npad / TS;
     const double *blkmax = q.partial + T * (T + 1) / 2 * 2 * TS;
     double v = 0.0;
@@ -430,6 +431,7 @@ __global__ void __launch_bounds__(256) k_max_final_b(const BProb *__restrict__ P
 {
     __shared__ double red[256];
     const BProb &q = P[w.plist[blockIdx.x]];
+    if (!q.active) return;
     const Plan pl = plan_for(q.n);
     const double *blkmax = q.partial + pl.splits * q.npad;
     const int64_t nb = q.npad / 256;

@@ -76,6 +76,62 @@ struct BWork {
     int64_t total;
 };
 
+// ---- device-side control of the batched refinement and cutoff search -------
+// Largest Krylov dimension of a batched refinement.
+constexpr int kMaxRestart = 38;
+// Scalar slots of each problem (BProb::scal, doubles).
+enum : int64_t {
+    SC_RNORM = 0,   // ||b - Z x||_inf of the last residual evaluation
+    SC_BETA = 1,    // ||M^{-1} r||_2
+    SC_SUM = 2,     // sum, min, argmin of w (3)
+    SC_AMAX = 5,    // ||b||_inf of a right-hand side
+    SC_PICK = 6,    // an entry picked at a device index
+    SC_H = 16,      // Arnoldi column h (2 (k+1)) and h_{k+1,k}
+    SC_Y = 96,      // GMRES solution coefficients (kMaxRestart + 1)
+    SC_RC = 136,    // refinement state (RC_* offsets)
+    SC_HH = 160,    // Hessenberg matrix, column-major, (kMaxRestart + 1) x kMaxRestart
+    SC_CS = SC_HH + (kMaxRestart + 1) * kMaxRestart,  // Givens cosines
+    SC_SN = SC_CS + kMaxRestart,                      // Givens sines
+    SC_G = SC_SN + kMaxRestart,                       // rotated right-hand side (kMaxRestart + 1)
+    SC_COUNT = (SC_G + kMaxRestart + 1 + 63) / 64 * 64
+};
+enum : int { RC_RNORM = 0, RC_BEST, RC_PREV, RC_TOL, RC_BETA, RC_INNER, RC_KDONE, RC_ROUND };
+// Control word of each problem (BProb::ints[kIntFlags]; status words and the
+// preconditioner counters sit below it).
+constexpr int kIntsPer = 2048;
+constexpr int kIntFlags = kIntsPer - 8;
+enum : int {
+    F_SEARCH = 1 << 0,     // solved in this step
+    F_REF = 1 << 1,        // refinement still running
+    F_COPYBEST = 1 << 2,   // this round: x improved, copy it to the best iterate
+    F_REVERT = 1 << 3,     // this round: back to the best iterate
+    F_DOPLAIN = 1 << 4,    // this round: plain step x += M^{-1} r
+    F_DOGMRES = 1 << 5,    // this round: a GMRES cycle
+    F_INNER = 1 << 6,      // the GMRES cycle continues
+    F_LASTPLAIN = 1 << 7,  // the last correction was a plain step
+    F_PLAINMODE = 1 << 8,  // plain steps still gain two digits each
+    F_REVERTED = 1 << 9,   // x was reset to the best iterate last round
+    F_OK = 1 << 10,        // tol reached
+    F_HI = 1 << 11,        // this step's w is the search's new upper bracket end
+    F_NEEDD = 1 << 12,     // the search wants d(min w)/dt at this step's point
+    F_BROKEN = 1 << 13     // the FP32 factor broke down (retaken with a shift)
+};
+// State of one cloud's cutoff search (device array, one thread per cloud).
+// The rules are those of the single search: grid scan downward from the bound,
+// then bisection in log t with safeguarded Newton steps, or Ridders' method.
+struct SState {
+    double tb, eps, top, hi, hi_min, lo, lo_min, last_t, last_min, last_d, prev_step, cur;
+    double ra, rga, rb, rgb, rgm, shift;
+    int32_t phase;       // 0 grid scan, 1 bracket refinement, 2 done; fixed-scale solves: 0 first, 2 done
+    int32_t gi, ext, have_hi, have_lo, prev_newton, last_has_d, solves, newton_steps, no_sign;
+    int32_t cur_newton, rid_pending, cur_kind, retry, attempts, err, unconverged, pad_;
+};
+struct SParams {
+    int32_t grid, max_extend, newton, ridders, fixed;  // fixed: one solve per problem at BProb::t
+    int32_t pad_;
+    double lo_factor, rtol;
+};
+
 // FP64 kernel entry exp(-t d), d = sqrt(s), for the matrix-free products.
 // sqrt_pos: square root of a normal s > 0 from the hardware reciprocal square
 // root estimate, one Goldschmidt step (g ~ sqrt(s), h ~ 1/(2 sqrt(s))) and two
@@ -182,6 +238,30 @@ void launch_gather_scal_b(hipStream_t s, const BProb *P, const int *plist, int n
 void launch_pick_b(hipStream_t s, const BProb *P, const int *plist, int na, int slot, int64_t idx_off,
                    int64_t dst);
 void launch_zero_status_b(hipStream_t s, const BProb *P, const int *plist, int na);
+
+// ---- device-side control kernels (bctl.hip); problems are P[0..B) ----------
+// active = ((flags & mask) == mask) for every problem
+void launch_gate_b(hipStream_t s, BProb *P, int B, int mask);
+// start a refinement for the active problems: F_REF set, tolerance
+// tol * max(1, scal[bnorm_off]) (bnorm_off < 0: tol)
+void launch_ref_init_b(hipStream_t s, BProb *P, int B, int64_t bnorm_off, double tol);
+// decisions after a residual evaluation (see bctl.hip); final: no corrections
+void launch_ref_decide_b(hipStream_t s, BProb *P, int B, int final_round, int max_gmres);
+void launch_gmres_start_b(hipStream_t s, BProb *P, int B);
+// Arnoldi step k on slots v0.. (V_{k+1} holds M^{-1} Z V_k): two classical
+// Gram-Schmidt passes, norm, Givens rotation, the continue decision, scaling
+void launch_arnoldi_b(hipStream_t s, BProb *P, int B, int k, int v0, int kcycle, double inner_tol,
+                      int max_gmres);
+void launch_gmres_finish_b(hipStream_t s, BProb *P, int B, int kcycle);
+// x_slot += z_slot for the active problems
+void launch_axpy_slot_b(hipStream_t s, BProb *P, int B, int64_t maxpad, int z_slot, int x_slot);
+// cutoff search / fixed-scale solves
+void launch_search_select_b(hipStream_t s, BProb *P, SState *S, int B, SParams prm);
+void launch_breakdown_b(hipStream_t s, BProb *P, SState *S, int B);
+void launch_search_update_b(hipStream_t s, BProb *P, SState *S, int B, SParams prm);
+void launch_search_deriv_b(hipStream_t s, BProb *P, SState *S, int B);
+// out[0] = clouds still searching, out[1] = any error
+void launch_search_count_b(hipStream_t s, const SState *S, int B, int *out);
 void launch_unpack_b(hipStream_t s, const BProb *P, const int *plist, int na, const int64_t *offs, int slot,
                      double *out, int64_t maxn);
 
@@ -210,6 +290,10 @@ struct mag_ctx {
     // tuned panel width of the single-solve FP32 factor per size bucket
     // (bucket = bit length of npad); 0 = the built-in choice
     int tune_panel[64] = {};
+    // tuned grouping of the batched factorisation's 256-column panels per size
+    // bucket of the largest npad: 0 = built-in (pairs), 1 = single panels
+    // (trailing updates with K = 256), 2 = pairs (K = 512)
+    int tune_bgroup[64] = {};
     // cap on the device bytes held by the buffers above (0: none)
     size_t ws_limit = 0;
 };
@@ -355,14 +439,14 @@ struct HodlrFactor {
 // Ridders' point for the bracket s_a < s_b with g_a < 0 <= g_b, from g_m at the
 // midpoint: s_m + (s_m - s_a) sign(g_a - g_b) g_m / sqrt(g_m^2 - g_a g_b).  It lies
 // in [s_a, s_b] since g_m^2 - g_a g_b >= g_m^2; the midpoint when undefined.
-inline double ridders_point(double sa, double ga, double sb, double gb, double gm)
+__host__ __device__ inline double ridders_point(double sa, double ga, double sb, double gb, double gm)
 {
     const double sm = 0.5 * (sa + sb);
-    const double den = std::sqrt(gm * gm - ga * gb);
-    if (!(den > 0.0) || !std::isfinite(den)) return sm;
+    const double den = sqrt(gm * gm - ga * gb);
+    if (!(den > 0.0) || !(den < INFINITY)) return sm;
     const double sgn = (ga - gb) < 0.0 ? -1.0 : 1.0;
     const double sx = sm + (sm - sa) * sgn * gm / den;
-    return std::min(std::max(sx, sa), sb);
+    return fmin(fmax(sx, sa), sb);
 }
 
 int hodlr_max_leaf();

@@ -289,6 +289,7 @@ k_trsv_b(const BProb *__restrict__ P, BWork w, int rhs_slot, int x_slot)
 __global__ void k_zero_counters_b(const BProb *__restrict__ P, BWork w)
 {
     const BProb &q = P[w.plist[blockIdx.x]];
+    if (!q.active) return;
     for (int e = threadIdx.x; e < kCounterInts; e += blockDim.x) q.ints[64 + e] = 0;
 }
 

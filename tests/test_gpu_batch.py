@@ -152,3 +152,53 @@ def test_tplus_batch_mixture64_vs_oracle(mag, mixture64, rank):
     assert abs(tps[b] - ref.t_plus) / ref.t_plus <= 2.5e-6
     assert abs(single.t_plus - ref.t_plus) / ref.t_plus <= 2.5e-6
     assert abs(infos[b]["t_bound"] - ref.t_bound) <= 1e-12 * ref.t_bound
+
+
+# ---- panel grouping of the batched factorisation and its autotuner
+
+def test_batch_groupings_against_oracle(mag):
+    clouds = [W.gaussian_mixture(n, 3, seed=40 + i) for i, n in enumerate([700, 1300, 2600, 257])]
+    X, offs = W.pack_clouds(clouds)
+    ts = [20.0, 35.0, 50.0, 8.0]
+    res = {}
+    try:
+        for group in (1, 2):
+            mag.tune_batch_group(max(len(c) for c in clouds), group)
+            w, Ms, infos = mag.weighting_batch(dev(X), offs, ts)
+            w = w.cpu().numpy()
+            for b, (Xb, t) in enumerate(zip(clouds, ts)):
+                wb = w[offs[b]:offs[b + 1]]
+                assert infos[b]["status"] == 0
+                assert np.abs(oracle.residual(Xb, t, wb)).max() <= 1e-12, (group, b)
+                ref = oracle.weighting(Xb, t)
+                assert abs(Ms[b] - ref.M) / abs(ref.M) <= 1e-10
+            res[group] = w
+        assert np.abs(res[1] - res[2]).max() <= 1e-10 * np.abs(res[2]).max()
+    finally:
+        mag.tune_batch_group(max(len(c) for c in clouds), 0)
+
+
+def test_autotune_batch_and_table_file(mag, tmp_path):
+    clouds = W.mixture_clouds(B=8, m=3, seed=21, n_lo=1000, n_hi=3000)
+    X, offs = W.pack_clouds(clouds)
+    ts = [40.0] * len(clouds)
+    group, ms = mag.autotune_batch(dev(X), offs, ts, reps=2)
+    print(f"batched factor of 8 clouds (n <= {max(len(c) for c in clouds)}): single {ms[0]:.2f} ms, "
+          f"pairs {ms[1]:.2f} ms -> group {group}")
+    assert group in (1, 2) and all(v > 0 for v in ms)
+    assert group == (1 if ms[0] < ms[1] else 2)
+    path = str(tmp_path / "tune.json")
+    mag.tune_save(path)
+    text = open(path).read()
+    assert '"batch_group"' in text and f": {group}" in text
+    nmax = max(len(c) for c in clouds)
+    mag.tune_batch_group(nmax, 0)
+    mag.tune_load(path)
+    # the tuned grouping solves the batch to the same acceptance
+    w, Ms, infos = mag.weighting_batch(dev(X), offs, ts)
+    w = w.cpu().numpy()
+    for b in (0, len(clouds) - 1):
+        assert np.abs(oracle.residual(clouds[b], ts[b], w[offs[b]:offs[b + 1]])).max() <= 1e-12
+    mag.tune_batch_group(nmax, 0)
+    with pytest.raises(mag.MagError):
+        mag.tune_batch_group(nmax, 3)
