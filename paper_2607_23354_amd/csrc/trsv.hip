@@ -64,13 +64,14 @@ __device__ inline int wait_ready(int *ready, int need, int *status)
 }
 
 // Called by wave 0, which wrote every published solution entry: one release
-// fence for the wave, then relaxed stores of the mirrored counters.
+// fence for the wave, then a relaxed atomic maximum on each mirrored counter
+// (a counter only grows, whatever order the bands' updates reach a mirror in).
 __device__ inline void publish(int *base, int value)
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     if (threadIdx.x < kMirrors)
-        __hip_atomic_store(base + threadIdx.x * kSlot, value, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        (void)__hip_atomic_fetch_max(base + threadIdx.x * kSlot, value, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One triangular solve.  Forward (BWD = false): y = L^{-1} r, block b pulls

@@ -18,6 +18,7 @@ import torch
 
 import oracle
 import workloads as W
+from parity_util import w_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -83,7 +84,9 @@ def test_hss_parity(mag, name, mkX, t, kw):
     X = mkX()
     res = mag.weighting(dev(X), float(t), solver="hss", **kw)
     w, ref, errM = check(X, float(t), res)
+    tol_w, _ = w_tolerance(X, float(t), w, ref)
     relw = np.abs(w - ref.w).max() / np.abs(ref.w).max()
+    assert np.abs(w - ref.w).max() <= tol_w
     hod = mag.weighting(dev(X), float(t), solver="hodlr", **kw).info
     print(f"{name}: n={len(X)} t={t:.4g} relerr_w={relw:.2e} relerr_M={errM:.2e} "
           f"outer={res.info['outer_iters']} gmres={res.info['gmres_iters']} (hodlr gmres={hod['gmres_iters']})")

@@ -12,6 +12,7 @@ import torch
 
 import oracle
 import workloads as W
+from parity_util import w_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -62,9 +63,12 @@ def test_weighting_parity(mag, name, mkX, mkt, solver):
         assert res.info["resid_inf"] <= 1e-12
     assert res.info["argmin_w"] == int(np.argmin(w))
     assert res.info["min_w"] == w.min()
-    relw = np.abs(w - ref.w).max() / np.abs(ref.w).max()
-    print(f"{name} {solver}: t={t:.4g} relerr_w={relw:.2e} relerr_M={errM:.2e} "
+    tol_w, _ = w_tolerance(X, t, w, ref)
+    dw = np.abs(w - ref.w).max()
+    print(f"{name} {solver}: t={t:.4g} relerr_w={dw / np.abs(ref.w).max():.2e} "
+          f"(tol {tol_w / np.abs(ref.w).max():.1e}) relerr_M={errM:.2e} "
           f"outer={res.info['outer_iters']} gmres={res.info['gmres_iters']}")
+    assert dw <= tol_w
 
 
 def test_magnitude_entry_point(mag):

@@ -144,9 +144,15 @@ def test_vjp_vs_oracle(mag, with_gw):
     loss.backward()
     dt_ref, dX_ref, sol = oracle.grad(X, t, gM=1.0, gw=gw)
     assert abs(M.item() - sol.M) / abs(sol.M) <= 1e-10
-    assert abs(td.grad.item() - dt_ref) <= 1e-9 * abs(dt_ref)
+    err_t = abs(td.grad.item() - dt_ref) / abs(dt_ref)
     err = np.abs(Xd.grad.cpu().numpy() - dX_ref).max() / np.abs(dX_ref).max()
-    assert err <= 1e-9, err
+    print(f"vjp n={n} m={m} gw={with_gw}: dL/dt rel err {err_t:.2e}, dL/dX rel err {err:.2e}, "
+          f"kappa_M {oracle.kappa_M(sol):.3g}")
+    # the oracle's analytic gradient to 1e-10 where kappa_M allows it (two correct
+    # FP64 evaluations may differ by about 2 u kappa_M), else to that bound
+    tol = 1e-10 if 2.0 ** -52 * oracle.kappa_M(sol) <= 1e-11 else 1e-10 + 8 * 2.0 ** -53 * oracle.kappa_M(sol)
+    assert err_t <= tol
+    assert err <= tol, err
 
 
 def test_two_point_gradient_closed_form(mag):
@@ -185,8 +191,11 @@ def test_vjp_finite_differences_full_size(mag):
         return r.info["magnitude"] + float(gw @ r.w.cpu().numpy())
 
     fd_t = (L(X, t + h) - L(X, t - h)) / (2 * h)
-    assert td.grad.item() == pytest.approx(fd_t, rel=1e-5)
     V = np.random.default_rng(3).standard_normal((n, m))
     fd_x = (L(X + h * V, t) - L(X - h * V, t)) / (2 * h)
     gX = Xd.grad.cpu().numpy()
-    assert float(np.sum(gX * V)) == pytest.approx(fd_x, rel=1e-5)
+    print(f"finite differences n={n}: dL/dt rel {abs(td.grad.item() - fd_t) / abs(fd_t):.2e}, "
+          f"directional dL/dX rel {abs(float(np.sum(gX * V)) - fd_x) / abs(fd_x):.2e}")
+    # h = 1e-6 central differences: truncation ~h^2, rounding ~u |L| / h
+    assert td.grad.item() == pytest.approx(fd_t, rel=1e-6)
+    assert float(np.sum(gX * V)) == pytest.approx(fd_x, rel=1e-6)
