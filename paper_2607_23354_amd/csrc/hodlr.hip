@@ -1152,6 +1152,99 @@ __global__ void k_hss_down_vec(const double *__restrict__ ub, const double *__re
     }
 }
 
+// ---- batched dense matrix-vector products of the HSS apply ------------------
+// One problem per node: A column-major (ld lda, node stride sA), x and y with
+// node strides sx and sy.  Every sum runs in a fixed order, so the apply is
+// bitwise reproducible.
+
+__device__ inline double hss_wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Transposed: y[j] = beta y[j] + alpha sum_i A[i + j lda] x[i] for j < N, i over
+// [0, M) or, lower, [j, M).  One wave per output (column j is contiguous).
+__global__ void __launch_bounds__(NT)
+k_bgemv_t(const double *__restrict__ A, int lda, int64_t sA, const double *__restrict__ x, int64_t sx,
+          double *__restrict__ y, int64_t sy, int M, int N, double alpha, double beta, int lower)
+{
+    const int node = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = blockIdx.x * (NT / 64) + wv;
+    if (j >= N) return;  // whole waves; no barriers below
+    const double *Aj = A + node * sA + (int64_t)j * lda;
+    const double *xn = x + node * sx;
+    double acc = 0.0;
+    for (int i = (lower ? j : 0) + lane; i < M; i += 64) acc = fma(Aj[i], xn[i], acc);
+    acc = hss_wave_sum(acc);
+    if (lane == 0) {
+        double *yn = y + node * sy;
+        yn[j] = (beta == 0.0 ? 0.0 : beta * yn[j]) + alpha * acc;
+    }
+}
+
+// Not transposed: y[i] = beta y[i] + alpha sum_j A[i + j lda] x[j] for i < M, j
+// over [0, N) or, lower, [0, min(i + 1, N)).  One thread per row; the columns
+// split into gridDim.y chunks of cs, whose partial sums go to part (node, split,
+// row) for k_bgemv_n_reduce when there is more than one.
+__global__ void __launch_bounds__(NT)
+k_bgemv_n(const double *__restrict__ A, int lda, int64_t sA, const double *__restrict__ x, int64_t sx,
+          double *__restrict__ y, int64_t sy, double *__restrict__ part, int M, int N, int cs, double alpha,
+          double beta, int lower)
+{
+    __shared__ double xs[NT];
+    const int node = blockIdx.z, sp = blockIdx.y, S = gridDim.y;
+    const int i = blockIdx.x * NT + threadIdx.x;
+    const int c0 = sp * cs, c1 = min(N, c0 + cs);
+    const double *An = A + node * sA;
+    const double *xn = x + node * sx;
+    double acc = 0.0;
+    for (int jb = c0; jb < c1; jb += NT) {
+        const int cnt = min(NT, c1 - jb);
+        __syncthreads();
+        if (threadIdx.x < cnt) xs[threadIdx.x] = xn[jb + threadIdx.x];
+        __syncthreads();
+        if (i < M) {
+            const int jend = lower ? min(cnt, i - jb + 1) : cnt;
+            for (int q = 0; q < jend; ++q) acc = fma(An[i + (int64_t)(jb + q) * lda], xs[q], acc);
+        }
+    }
+    if (i < M) {
+        if (S == 1) {
+            double *yn = y + node * sy;
+            yn[i] = (beta == 0.0 ? 0.0 : beta * yn[i]) + alpha * acc;
+        } else {
+            part[((int64_t)node * S + sp) * M + i] = acc;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT)
+k_bgemv_n_reduce(const double *__restrict__ part, double *__restrict__ y, int64_t sy, int M, int S, int64_t nodes,
+                 double alpha, double beta)
+{
+    for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < nodes * M; e += (int64_t)gridDim.x * NT) {
+        const int64_t node = e / M;
+        const int i = (int)(e % M);
+        double s = 0.0;
+        for (int q = 0; q < S; ++q) s += part[(node * S + q) * M + i];
+        double *yn = y + node * sy;
+        yn[i] = (beta == 0.0 ? 0.0 : beta * yn[i]) + alpha * s;
+    }
+}
+
+// y[node][0, e) = x[node][0, e), node strides a
+__global__ void k_hss_copy_head(const double *__restrict__ x, double *__restrict__ y, int a, int e, int64_t nodes)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nodes * e; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t node = q / e;
+        const int i = (int)(q % e);
+        y[node * a + i] = x[node * a + i];
+    }
+}
+
 // D[node][i][i] += sigma for i < e (the block to eliminate), every node.
 __global__ void k_hss_shift(double *__restrict__ D, int a, int e, int64_t nodes, double sigma)
 {
@@ -1184,6 +1277,36 @@ __global__ void k_hss_diagmax(const double *__restrict__ D, int a, int e, int64_
 inline unsigned hss_grid(int64_t total)
 {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + NT - 1) / NT, 4096));
+}
+
+// Capacity of the apply's partial-sum buffer (doubles).
+constexpr int64_t kHssPart = (int64_t)1 << 19;
+
+void launch_bgemv_t(hipStream_t s, const double *A, int lda, int64_t sA, const double *x, int64_t sx, double *y,
+                    int64_t sy, int M, int N, int64_t nodes, double alpha, double beta, bool lower)
+{
+    if (N <= 0 || nodes <= 0) return;
+    const dim3 g((unsigned)((N + NT / 64 - 1) / (NT / 64)), (unsigned)nodes);
+    hipLaunchKernelGGL(k_bgemv_t, g, dim3(NT), 0, s, A, lda, sA, x, sx, y, sy, M, N, alpha, beta, lower ? 1 : 0);
+}
+
+void launch_bgemv_n(hipStream_t s, const double *A, int lda, int64_t sA, const double *x, int64_t sx, double *y,
+                    int64_t sy, double *part, int M, int N, int64_t nodes, double alpha, double beta, bool lower)
+{
+    if (M <= 0 || nodes <= 0) return;
+    const int64_t rb = (M + NT - 1) / NT;
+    // column splits until about 1024 workgroups, within the partial buffer
+    int64_t S = std::max<int64_t>(1, std::min<int64_t>((1024 + rb * nodes - 1) / (rb * nodes), (N + 63) / 64));
+    while (S > 1 && nodes * S * M > kHssPart) --S;
+    int cs = (int)((N + S - 1) / S);
+    cs = (cs + 63) / 64 * 64;
+    S = std::max<int64_t>(1, (N + cs - 1) / cs);
+    const dim3 g((unsigned)rb, (unsigned)S, (unsigned)nodes);
+    hipLaunchKernelGGL(k_bgemv_n, g, dim3(NT), 0, s, A, lda, sA, x, sx, y, sy, part, M, N, cs, alpha, beta,
+                       lower ? 1 : 0);
+    if (S > 1)
+        hipLaunchKernelGGL(k_bgemv_n_reduce, dim3(hss_grid(nodes * M)), dim3(NT), 0, s, part, y, sy, M, (int)S, nodes,
+                           alpha, beta);
 }
 
 }  // namespace
@@ -1277,12 +1400,14 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
     }
     maxEig = std::max(maxEig, 2 * amax);
     maxQ = std::max(maxQ, amax * amax);  // the root block passes through Dn too
+    int64_t maxV = std::max<int64_t>(amax, (int64_t)ell);  // the apply's temporary vector (nodes x a per level)
+    for (int l = 1; l <= L; ++l) maxV = std::max(maxV, ((int64_t)1 << l) * a[l]);
 
     // device workspace (doubles, then int64, then int)
     const size_t nd = (size_t)n * m + 3 * (size_t)n * r + 3 * (size_t)n * kmax + 2 * (size_t)qtot +
                       (size_t)amax * amax + (size_t)maxT + 2 * (size_t)maxQ + 4 * (size_t)maxSt +
                       (size_t)(L + 1) * maxB + (size_t)gpart + 2 * (size_t)vtot + (size_t)leaves * ell +
-                      2 * (size_t)amax + (size_t)maxEig + 256;
+                      2 * (size_t)amax + (size_t)maxV + (size_t)kHssPart + (size_t)maxEig + 256;
     const size_t nint = (size_t)n + bnd.size() + 16;
     const size_t nsmall = (size_t)std::max<int64_t>(leaves, 2) + 64;
     if (ensure(ctx, ctx->hss, sizeof(double) * nd + sizeof(int64_t) * nint + sizeof(int) * nsmall + 4096) != MAG_OK)
@@ -1310,6 +1435,8 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
     H.xb = p; p += vtot;
     H.xl = p; p += (size_t)leaves * ell;
     H.rr = p; p += 2 * (size_t)amax;
+    H.tv = p; p += (size_t)maxV;
+    H.part = p; p += (size_t)kHssPart;
     double *eigw = p; p += maxEig;
     p += 256;
     int64_t *ip = (int64_t *)p;
@@ -1366,7 +1493,10 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
         hipLaunchKernelGGL(k_hss_leaf_block, dim3(hss_grid((int64_t)ell * ell)), dim3(NT), 0, s, H.Xp, m, t, bL, ell,
                            (int64_t)1, H.Droot);
         RBCHK(rocsolver_dpotrf(bh, rocblas_fill_lower, ell, H.Droot, ell, info));
-        return check_info(1);  // exact Z: not positive definite only for coincident points
+        HSSCHK(check_info(1));  // exact Z: not positive definite only for coincident points
+        // the apply multiplies by the factor's inverse
+        RBCHK(rocsolver_dtrtri(bh, rocblas_fill_lower, rocblas_diagonal_non_unit, ell, H.Droot, ell, info));
+        return check_info(1);
     }
 
     // 1. S = (Z - leaf blocks) Omega, from the sibling-pair products of every level
@@ -1498,8 +1628,11 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
     if (hipMemcpyAsync(H.Droot, Dn, sizeof(double) * a[0] * a[0], hipMemcpyDeviceToDevice, s) != hipSuccess)
         return MAG_EHIP;
     HSSCHK(potrf_shifted(H.Droot, Dn, a[0], a[0], 1));
-    // 5. the eliminated blocks' factors L_e are only applied from here on: keep
-    // their inverses in place, so the apply multiplies (trmv) instead of solving
+    RBCHK(rocsolver_dtrtri(bh, rocblas_fill_lower, rocblas_diagonal_non_unit, a[0], H.Droot, a[0], info));
+    HSSCHK(check_info(1));
+    // 5. the eliminated blocks' factors L_e (and the root's) are only applied from
+    // here on: keep their inverses in place, so the apply multiplies instead of
+    // solving
     for (int l = L; l >= 1; --l) {
         const int al = a[l], el = al - k[l];
         if (el <= 0) continue;
@@ -1513,24 +1646,20 @@ int hss_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int le
 
 int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z)
 {
-    rocblas_handle bh = (rocblas_handle)H.blas;
-    if (rocblas_set_stream(bh, s) != rocblas_status_success) return MAG_EHIP;
     const int L = H.L, ell = H.ell;
     const int64_t leaves = (int64_t)1 << L;
     const int64_t *bL = H.bnd + boff(L);
-    const double one = 1.0, mone = -1.0, zero = 0.0;
     hipLaunchKernelGGL(k_hss_gather_vec, dim3(hss_grid(leaves * ell)), dim3(NT), 0, s, r, H.perm, bL, ell, leaves,
                        H.xl);
     if (L == 0) {
-        RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, ell, H.Droot,
-                            ell, H.xl, 1));
-        RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, ell,
-                            H.Droot, ell, H.xl, 1));
+        // one leaf: x = R^{-T} R^{-1} r with the inverse R^{-1} of Z's Cholesky factor
+        launch_bgemv_n(s, H.Droot, ell, 0, H.xl, 0, H.tv, 0, H.part, ell, ell, 1, 1.0, 0.0, true);
+        launch_bgemv_t(s, H.Droot, ell, 0, H.tv, 0, H.xl, 0, ell, ell, 1, 1.0, 0.0, true);
         hipLaunchKernelGGL(k_hss_scatter_vec, dim3(hss_grid(std::max<int64_t>(leaves * ell, H.npad))), dim3(NT), 0, s,
                            H.xl, H.perm, bL, ell, leaves, H.n, H.npad, z);
-        return MAG_OK;
+        return hipGetLastError() == hipSuccess ? MAG_OK : MAG_EHIP;
     }
-    // up: ub_l[tau] = Q^T (node rhs), then y_e = L_e^{-1} b~_e (L_e^{-1} is stored), b^ = b~_s - W y_e
+    // up: u = Q^T (node rhs); y_e = L_e^{-1} u_e (L_e^{-1} is stored); u_s -= W y_e
     for (int l = L; l >= 1; --l) {
         const int al = H.a[l], kl = H.k[l], el = al - kl;
         const int64_t nodes = (int64_t)1 << l;
@@ -1545,25 +1674,20 @@ int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z)
         }
         double *u = H.ub + H.voff[l];
         const double *Ql = H.Q + H.off[l], *Dl = H.Dt + H.off[l];
-        RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_transpose, al, al, &one, Ql, al,
-                                            (rocblas_stride)al * al, rin, 1, al, &zero, u, 1, al, (rocblas_int)nodes));
+        const int64_t sq = (int64_t)al * al;
+        launch_bgemv_t(s, Ql, al, sq, rin, al, u, al, al, al, nodes, 1.0, 0.0, false);
         if (el > 0) {
-            RBCHK(rocblas_dtrmv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_none,
-                                                rocblas_diagonal_non_unit, el, Dl, al, (rocblas_stride)al * al, u, 1, al,
-                                                (rocblas_int)nodes));
-            RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_none, kl, el, &mone, Dl + el, al,
-                                                (rocblas_stride)al * al, u, 1, al, &one, u + el, 1, al,
-                                                (rocblas_int)nodes));
+            launch_bgemv_n(s, Dl, al, sq, u, al, H.tv, al, H.part, el, el, nodes, 1.0, 0.0, true);
+            launch_bgemv_n(s, Dl + el, al, sq, H.tv, al, u + el, al, H.part, kl, el, nodes, -1.0, 1.0, false);
+            hipLaunchKernelGGL(k_hss_copy_head, dim3(hss_grid(nodes * el)), dim3(NT), 0, s, H.tv, u, al, el, nodes);
         }
     }
-    // root
+    // root: x = R^{-T} R^{-1} b
     const int a0 = H.a[0];
     hipLaunchKernelGGL(k_hss_stack, dim3(hss_grid(a0)), dim3(NT), 0, s, H.ub + H.voff[1], (int64_t)H.a[1], H.a[1],
                        H.a[1] - H.k[1], H.k[1], 1, (int64_t)1, H.rr);
-    RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_none, rocblas_diagonal_non_unit, a0, H.Droot, a0,
-                        H.rr, 1));
-    RBCHK(rocblas_dtrsv(bh, rocblas_fill_lower, rocblas_operation_transpose, rocblas_diagonal_non_unit, a0, H.Droot, a0,
-                        H.rr, 1));
+    launch_bgemv_n(s, H.Droot, a0, 0, H.rr, 0, H.tv, 0, H.part, a0, a0, 1, 1.0, 0.0, true);
+    launch_bgemv_t(s, H.Droot, a0, 0, H.tv, 0, H.rr, 0, a0, a0, 1, 1.0, 0.0, true);
     // down: v = [y_e; x_s], x_e = L_e^{-T} (y_e - W^T x_s), x = Q v
     for (int l = 1; l <= L; ++l) {
         const int al = H.a[l], kl = H.k[l], el = al - kl;
@@ -1574,21 +1698,18 @@ int hss_apply(hipStream_t s, const HssFactor &H, const double *r, double *z)
         hipLaunchKernelGGL(k_hss_down_vec, dim3(hss_grid(nodes * al)), dim3(NT), 0, s, H.ub + H.voff[l], xpar, apar, al,
                            kl, nodes, v);
         const double *Ql = H.Q + H.off[l], *Dl = H.Dt + H.off[l];
+        const int64_t sq = (int64_t)al * al;
         if (el > 0) {
-            RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_transpose, kl, el, &mone, Dl + el, al,
-                                                (rocblas_stride)al * al, v + el, 1, al, &one, v, 1, al,
-                                                (rocblas_int)nodes));
-            RBCHK(rocblas_dtrmv_strided_batched(bh, rocblas_fill_lower, rocblas_operation_transpose,
-                                                rocblas_diagonal_non_unit, el, Dl, al, (rocblas_stride)al * al, v, 1, al,
-                                                (rocblas_int)nodes));
+            launch_bgemv_t(s, Dl + el, al, sq, v + el, al, v, al, kl, el, nodes, -1.0, 1.0, false);
+            launch_bgemv_t(s, Dl, al, sq, v, al, H.tv, al, el, el, nodes, 1.0, 0.0, true);
+            hipLaunchKernelGGL(k_hss_copy_head, dim3(hss_grid(nodes * el)), dim3(NT), 0, s, H.tv, v, al, el, nodes);
         }
         double *xo = (l == L) ? H.xl : H.xb + H.voff[l];
-        RBCHK(rocblas_dgemv_strided_batched(bh, rocblas_operation_none, al, al, &one, Ql, al, (rocblas_stride)al * al,
-                                            v, 1, al, &zero, xo, 1, al, (rocblas_int)nodes));
+        launch_bgemv_n(s, Ql, al, sq, v, al, xo, al, H.part, al, al, nodes, 1.0, 0.0, false);
     }
     hipLaunchKernelGGL(k_hss_scatter_vec, dim3(hss_grid(std::max<int64_t>(leaves * ell, H.npad))), dim3(NT), 0, s, H.xl,
                        H.perm, bL, ell, leaves, H.n, H.npad, z);
-    return MAG_OK;
+    return hipGetLastError() == hipSuccess ? MAG_OK : MAG_EHIP;
 }
 
 }  // namespace mag

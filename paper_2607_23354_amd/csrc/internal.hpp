@@ -478,6 +478,7 @@ struct HssFactor {
     double t = 0.0;
     double *Xp = nullptr, *Q = nullptr, *Dt = nullptr, *Droot = nullptr, *ub = nullptr, *xb = nullptr;
     double *xl = nullptr, *rr = nullptr;
+    double *tv = nullptr, *part = nullptr;  // the apply's temporary vector and partial sums
     int64_t *perm = nullptr, *bnd = nullptr;
     std::vector<int> k, a;
     std::vector<int64_t> off;  // per level: offset of its Q / Dt blocks (doubles)
