@@ -100,7 +100,7 @@ typedef struct {
     int32_t max_gmres;     /* total inner iterations over the whole solve, default 200    */
     double tol;            /* target ||1 - Z w||_inf, default 1e-12                       */
     double inner_tol;      /* relative reduction asked of each inner GMRES, default 1e-10 */
-    int32_t leaf;          /* HODLR largest leaf, 2..128, default 128 (else MAG_EINVAL)   */
+    int32_t leaf;          /* HODLR/HSS largest leaf, 2..256, default 128 (else MAG_EINVAL) */
     int32_t max_rank;      /* HODLR rank of the top level's sibling blocks, default 256;  *
                             * level l samples max_rank 2^{-l/2} + oversample columns,     *
                             * rounded up to a multiple of 64 within [64, 512] and the     *

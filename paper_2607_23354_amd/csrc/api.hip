@@ -642,7 +642,7 @@ int solve_hodlr(mag_ctx *ctx, const double *X, int64_t n, int m, double t, doubl
 {
     hipStream_t s = ctx->stream;
     const int restart = std::max(1, o.gmres_restart);
-    const int leaf = o.leaf > 0 ? o.leaf : hodlr_max_leaf();
+    const int leaf = o.leaf > 0 ? o.leaf : hodlr_default_leaf();
     if (leaf < 2 || leaf > hodlr_max_leaf() || m > 16) return MAG_EINVAL;
     CHK(ensure_solver(ctx, n, m, restart));
     Timer tm;
@@ -699,7 +699,7 @@ int solve_hss(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double 
 {
     hipStream_t s = ctx->stream;
     const int restart = std::max(1, o.gmres_restart);
-    const int leaf = o.leaf > 0 ? o.leaf : hodlr_max_leaf();
+    const int leaf = o.leaf > 0 ? o.leaf : hodlr_default_leaf();
     if (leaf < 2 || leaf > hodlr_max_leaf() || m > 16) return MAG_EINVAL;
     CHK(ensure_solver(ctx, n, m, restart));
     Timer tm;

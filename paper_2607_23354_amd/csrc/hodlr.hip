@@ -11,7 +11,7 @@
 // Cluster tree.  Points are ordered by recursive coordinate bisection: each
 // node is split at the median of its widest coordinate (ties by index).  The
 // tree is perfect with L levels (2^l nodes at level l, leaves at level L,
-// every leaf holding at most 128 points); node (l, i) covers the permuted
+// every leaf holding at most 256 points); node (l, i) covers the permuted
 // index range [bnd_l[i], bnd_l[i+1]).
 //
 // Off-diagonal blocks.  For node N = (l, i) with children I (left) and J
@@ -36,10 +36,13 @@
 // starts as D_L^{-1} P_l and receives the corrections of every deeper level,
 // bottom-up.
 //
-// Sampling, Gram and row products, leaf inverses and the apply are kernels of
-// this file; the per-node k x k algebra (Cholesky and triangular inverse of
-// the Gram matrices, the Schur complements and their LU inverses, products of
-// k x k blocks) goes to rocSOLVER / rocBLAS.  Everything is FP64.
+// Sampling, Gram and row products, leaf inverses of up to 128 points (whole in
+// LDS) and the apply are kernels of this file; the per-node k x k algebra
+// (Cholesky and triangular inverse of the Gram matrices, the Schur complements
+// and their LU inverses, products of k x k blocks) and the batched Cholesky
+// factor and inverse of leaves of 129..256 points go to rocSOLVER / rocBLAS on
+// the factor path.  The apply runs on this file's kernels only.  Everything is
+// FP64.
 #include "internal.hpp"
 
 #include <rocblas/rocblas.h>
@@ -55,7 +58,8 @@ namespace {
 
 constexpr int SL = 64;      // slab / tile width of every basis
 constexpr int KMAXC = 8;    // widest basis: KMAXC * SL columns
-constexpr int LMAX = 128;   // largest leaf
+constexpr int LMAX = 256;   // largest leaf
+constexpr int LSW = 128;    // largest leaf inverted inside LDS (sweep operator)
 constexpr int MMAXH = 16;   // largest point dimension
 constexpr int ZR = 64;      // rows per sampling workgroup
 constexpr int ZC = 64;      // points per sampling column chunk
@@ -397,19 +401,20 @@ k_copy_rows(const double *__restrict__ src, double *__restrict__ dst, int ld, co
 // Inverse of each leaf block Z(leaf, leaf) (exact FP64 entries) by the sweep
 // operator (Goodnight, 1979): sweeping every pivot of a symmetric positive
 // definite A turns it into -A^{-1}; pivots are the Schur-complement
-// diagonals, positive for SPD A.  Dinv: LMAX x LMAX per leaf (symmetric; the
-// padding is the identity).  A pivot that is not positive marks status.
+// diagonals, positive for SPD A.  Leaves of at most LSW points, whole in LDS.
+// Dinv: LSW x LSW per leaf (symmetric; the padding is the identity).  A pivot
+// that is not positive marks status.
 __global__ void __launch_bounds__(NT)
 k_leaf_inv(const double *__restrict__ Xp, int m, double t, const int64_t *__restrict__ bndL,
            double *__restrict__ Dinv, int *__restrict__ status)
 {
-    __shared__ double A[LMAX][LMAX + 1];
-    __shared__ double colk[LMAX];
+    __shared__ double A[LSW][LSW + 1];
+    __shared__ double colk[LSW];
     const int tid = threadIdx.x;
     const int64_t lo = bndL[blockIdx.x], hi = bndL[blockIdx.x + 1];
     const int s = (int)(hi - lo);
-    for (int e = tid; e < LMAX * LMAX; e += NT) {
-        const int i = e / LMAX, j = e % LMAX;
+    for (int e = tid; e < LSW * LSW; e += NT) {
+        const int i = e / LSW, j = e % LSW;
         double v;
         if (i == j) {
             v = 1.0;
@@ -425,7 +430,7 @@ k_leaf_inv(const double *__restrict__ Xp, int m, double t, const int64_t *__rest
     bool bad = false;
     for (int k = 0; k < s; ++k) {
         __syncthreads();
-        if (tid < LMAX) colk[tid] = A[tid][k];
+        if (tid < LSW) colk[tid] = A[tid][k];
         __syncthreads();
         double akk = colk[k];
         if (!(akk > 0.0) || !isfinite(akk)) {
@@ -433,8 +438,8 @@ k_leaf_inv(const double *__restrict__ Xp, int m, double t, const int64_t *__rest
             akk = 1.0;
         }
         const double inv = 1.0 / akk;
-        for (int e = tid; e < LMAX * LMAX; e += NT) {
-            const int i = e / LMAX, j = e % LMAX;
+        for (int e = tid; e < LSW * LSW; e += NT) {
+            const int i = e / LSW, j = e % LSW;
             if (i == k && j == k) A[i][j] = -inv;
             else if (i == k) A[i][j] = colk[j] * inv;
             else if (j == k) A[i][j] = colk[i] * inv;
@@ -442,42 +447,91 @@ k_leaf_inv(const double *__restrict__ Xp, int m, double t, const int64_t *__rest
         }
     }
     __syncthreads();
-    double *D = Dinv + (int64_t)blockIdx.x * LMAX * LMAX;
-    for (int e = tid; e < LMAX * LMAX; e += NT) {
-        const int i = e / LMAX, j = e % LMAX;
+    double *D = Dinv + (int64_t)blockIdx.x * LSW * LSW;
+    for (int e = tid; e < LSW * LSW; e += NT) {
+        const int i = e / LSW, j = e % LSW;
         D[e] = (i < s && j < s) ? -A[i][j] : (i == j ? 1.0 : 0.0);
     }
     if (bad && tid == 0) atomicCAS(&status[kStBreakdown], 0, (int)(lo + 1));
 }
 
+// Leaves larger than LSW: the blocks Z(leaf, leaf), padded to ls x ls with the
+// identity, written to Dinv for a batched Cholesky factor and inverse in HBM.
+// Grid (leaves, chunks); the entries of one leaf are spread over the chunks.
+__global__ void __launch_bounds__(NT)
+k_leaf_fill(const double *__restrict__ Xp, int m, double t, const int64_t *__restrict__ bndL, int ls,
+            double *__restrict__ Dinv)
+{
+    const int64_t lo = bndL[blockIdx.x], hi = bndL[blockIdx.x + 1];
+    const int s = (int)(hi - lo);
+    double *D = Dinv + (int64_t)blockIdx.x * ls * ls;
+    for (int e = blockIdx.y * NT + threadIdx.x; e < ls * ls; e += gridDim.y * NT) {
+        const int i = e / ls, j = e % ls;  // symmetric: row and column order agree
+        double v;
+        if (i == j) {
+            v = 1.0;
+        } else if (i < s && j < s) {
+            double d2 = 0.0;
+            for (int l = 0; l < m; ++l) d2 = sq_acc(d2, Xp[(lo + i) * m + l] - Xp[(lo + j) * m + l]);
+            v = zexp(t, d2);
+        } else {
+            v = 0.0;
+        }
+        D[e] = v;
+    }
+}
+
+// A leaf whose batched factorisation reported a failed pivot (info > 0) marks
+// status with its first point, as the sweep does.
+__global__ void k_leaf_info(const int *__restrict__ info, const int64_t *__restrict__ bndL, int64_t leaves,
+                            int *__restrict__ status)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < leaves; i += (int64_t)gridDim.x * blockDim.x)
+        if (info[i] != 0) atomicCAS(&status[kStBreakdown], 0, (int)(bndL[i] + 1));
+}
+
+// The lower triangle (column-major) of each ls x ls inverse mirrored into its
+// upper triangle.
+__global__ void __launch_bounds__(NT)
+k_leaf_symm(double *__restrict__ Dinv, int ls)
+{
+    double *D = Dinv + (int64_t)blockIdx.x * ls * ls;
+    for (int e = blockIdx.y * NT + threadIdx.x; e < ls * ls; e += gridDim.y * NT) {
+        const int c = e / ls, r = e % ls;  // entry (r, c) at D[c ls + r]
+        if (r < c) D[e] = D[(int64_t)r * ls + c];
+    }
+}
+
 // Ph[leaf rows, slab] = Dinv_leaf P[leaf rows, slab] (both n x ld); grid
-// (leaves, ld / 64).  Dinv streamed through LDS 32 columns at a time.
+// (leaves, ld / 64, LS / 128): 128 output rows by 64 columns per workgroup,
+// the contraction over the leaf in chunks of 32 through LDS.
+template <int LS>
 __global__ void __launch_bounds__(NT)
 k_leaf_apply(const double *__restrict__ Dinv, const int64_t *__restrict__ bndL, const double *__restrict__ P,
              double *__restrict__ Ph, int ld)
 {
-    __shared__ double Bs[LMAX][SL];
-    __shared__ double Ms[LMAX][33];
+    __shared__ double Bs[32][SL];
+    __shared__ double Ms[128][33];
     const int64_t lo = bndL[blockIdx.x], hi = bndL[blockIdx.x + 1];
     const int s = (int)(hi - lo);
-    const int col0 = blockIdx.y * SL;
-    const double *M = Dinv + (int64_t)blockIdx.x * LMAX * LMAX;
+    const int col0 = blockIdx.y * SL, row0 = blockIdx.z * 128;
+    const double *M = Dinv + (int64_t)blockIdx.x * LS * LS;
     const int tid = threadIdx.x;
-    for (int e = tid; e < LMAX * SL; e += NT) {
-        const int rr = e / SL, q = e % SL;
-        Bs[rr][q] = (rr < s) ? P[(lo + rr) * ld + col0 + q] : 0.0;
-    }
-    const int ty = tid >> 3, tx = tid & 7;  // rows 4ty.., columns 8tx..
+    const int ty = tid >> 3, tx = tid & 7;  // rows row0 + 4ty.., columns 8tx..
     double acc[4][8];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 8; ++j) acc[i][j] = 0.0;
-    for (int kc = 0; kc < LMAX; kc += 32) {
+    for (int kc = 0; kc < s; kc += 32) {
         __syncthreads();
-        for (int e = tid; e < LMAX * 32; e += NT) {
+        for (int e = tid; e < 128 * 32; e += NT) {
             const int i = e / 32, j = e % 32;
-            Ms[i][j] = M[i * LMAX + kc + j];
+            Ms[i][j] = M[(int64_t)(row0 + i) * LS + kc + j];
+        }
+        for (int e = tid; e < 32 * SL; e += NT) {
+            const int rr = e / SL, q = e % SL;
+            Bs[rr][q] = (kc + rr < s) ? P[(lo + kc + rr) * ld + col0 + q] : 0.0;
         }
         __syncthreads();
         for (int kk = 0; kk < 32; ++kk) {
@@ -485,7 +539,7 @@ k_leaf_apply(const double *__restrict__ Dinv, const int64_t *__restrict__ bndL, 
 #pragma unroll
             for (int i = 0; i < 4; ++i) av[i] = Ms[4 * ty + i][kk];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) bv[j] = Bs[kc + kk][8 * tx + j];
+            for (int j = 0; j < 8; ++j) bv[j] = Bs[kk][8 * tx + j];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -494,7 +548,7 @@ k_leaf_apply(const double *__restrict__ Dinv, const int64_t *__restrict__ bndL, 
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int r = 4 * ty + i;
+        const int r = row0 + 4 * ty + i;
         if (r < s) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) Ph[(lo + r) * ld + col0 + 8 * tx + j] = acc[i][j];
@@ -535,23 +589,34 @@ __global__ void k_scatter(const double *__restrict__ xp, const int64_t *__restri
     }
 }
 
-// x[leaf] = Dinv_leaf x[leaf] in place (Dinv symmetric: column access coalesces)
+// x[leaf] = Dinv_leaf x[leaf] in place (Dinv symmetric: column access
+// coalesces).  A thread per row, the leaf's columns split over NT / LS threads.
+template <int LS>
 __global__ void __launch_bounds__(NT)
 k_leaf_gemv(const double *__restrict__ Dinv, const int64_t *__restrict__ bndL, double *__restrict__ x)
 {
-    __shared__ double xs[LMAX];
-    __shared__ double hs[LMAX];
+    constexpr int SPLIT = NT / LS, KC = LS / SPLIT;
+    __shared__ double xs[LS];
+    __shared__ double hs[NT];
     const int64_t lo = bndL[blockIdx.x], hi = bndL[blockIdx.x + 1];
     const int s = (int)(hi - lo);
-    const int tid = threadIdx.x, row = tid & (LMAX - 1), half = tid >> 7;
-    if (tid < LMAX) xs[tid] = (tid < s) ? x[lo + tid] : 0.0;
+    const int tid = threadIdx.x, row = tid % LS, part = tid / LS;
+    if (tid < LS) xs[tid] = (tid < s) ? x[lo + tid] : 0.0;
     __syncthreads();
-    const double *D = Dinv + (int64_t)blockIdx.x * LMAX * LMAX;
+    const double *D = Dinv + (int64_t)blockIdx.x * LS * LS;
     double acc = 0.0;
-    for (int k = half * 64; k < half * 64 + 64; ++k) acc = fma(D[k * LMAX + row], xs[k], acc);
-    if (half == 1) hs[row] = acc;
+    for (int k = part * KC; k < part * KC + KC; ++k) acc = fma(D[k * LS + row], xs[k], acc);
+    if (SPLIT == 1) {
+        if (row < s) x[lo + row] = acc;
+        return;
+    }
+    hs[tid] = acc;
     __syncthreads();
-    if (half == 0 && row < s) x[lo + row] = acc + hs[row];
+    if (part == 0 && row < s) {
+        double v = acc;
+        for (int q = 1; q < SPLIT; ++q) v += hs[q * LS + row];
+        x[lo + row] = v;
+    }
 }
 
 // partial[(c * cmax + ch) * ld + q] = sum_{r in chunk} P[r, q] x[r] over the
@@ -645,6 +710,7 @@ inline int64_t boff(int l) { return ((int64_t)1 << l) - 1 + l; }
 // ---- host side -------------------------------------------------------------------
 
 int hodlr_max_leaf() { return LMAX; }
+int hodlr_default_leaf() { return LSW; }
 int hodlr_max_cols() { return KMAXC * SL; }
 
 // Perfect tree of L levels over n points: level bounds and the permutation
@@ -802,8 +868,11 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
         return MAG_EHIP;
     std::vector<int64_t> perm, bnd;
     build_tree(Xh, n, m, L, perm, bnd);
-    for (int64_t i = 0; i < ((int64_t)1 << L); ++i)  // the leaf kernels hold a leaf in LDS
-        if (bnd[boff(L) + i + 1] - bnd[boff(L) + i] > LMAX) return MAG_EINTERNAL;
+    int64_t maxleaf = 0;
+    for (int64_t i = 0; i < ((int64_t)1 << L); ++i) maxleaf = std::max(maxleaf, bnd[boff(L) + i + 1] - bnd[boff(L) + i]);
+    if (maxleaf > LMAX) return MAG_EINTERNAL;
+    // leaf storage: LSW x LSW (inverted in LDS) or LMAX x LMAX (batched Cholesky in HBM)
+    const int ls = maxleaf <= LSW ? LSW : LMAX;
     std::vector<double> Xp((size_t)n * m);
     for (int64_t i = 0; i < n; ++i)
         for (int l = 0; l < m; ++l) Xp[i * m + l] = Xh[perm[i] * m + l];
@@ -812,7 +881,7 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
     // device workspace
     const int64_t leaves = (int64_t)1 << L;
     const size_t nd = (size_t)n * m + 2 * (size_t)pl.ptotal + 2 * (size_t)n * pl.kmax +
-                      (size_t)leaves * LMAX * LMAX + (size_t)pl.wtotal + (size_t)pl.gpart + 2 * (size_t)pl.gout +
+                      (size_t)leaves * ls * ls + (size_t)pl.wtotal + (size_t)pl.gpart + 2 * (size_t)pl.gout +
                       (size_t)pl.tbuf + (size_t)pl.apart + (size_t)leaves * 2 * pl.kmax + 2 * (size_t)npad + 64;
     const size_t nint = (size_t)n + bnd.size() + 16;
     const size_t nsmall = (size_t)pl.ipiv + leaves + 64;  // rocsolver pivots and infos (int32)
@@ -825,7 +894,7 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
     H.Ph = p; p += pl.ptotal;
     double *Om = p; p += (size_t)n * pl.kmax;
     double *W2 = p; p += (size_t)n * pl.kmax;
-    H.Dinv = p; p += (size_t)leaves * LMAX * LMAX;
+    H.Dinv = p; p += (size_t)leaves * ls * ls;
     H.W = p; p += pl.wtotal;
     double *gpart = p; p += pl.gpart;
     double *G = p; p += pl.gout;
@@ -844,6 +913,7 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
     H.m = m;
     H.t = t;
     H.L = L;
+    H.ls = ls;
     H.npad = npad;
     H.bnd_host = bnd;
     H.k = pl.k;
@@ -901,10 +971,30 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
 
     // 2. leaves: exact inverses, applied to every level's basis
     const int64_t *bL = H.bnd + boff(L);
-    hipLaunchKernelGGL(k_leaf_inv, dim3((unsigned)leaves), dim3(NT), 0, s, H.Xp, m, t, bL, H.Dinv, status);
-    for (int l = 0; l < L; ++l)
-        hipLaunchKernelGGL(k_leaf_apply, dim3((unsigned)leaves, (unsigned)(pl.k[l] / SL)), dim3(NT), 0, s, H.Dinv,
-                           bL, H.P + pl.poff[l], H.Ph + pl.poff[l], pl.k[l]);
+    if (ls == LSW) {
+        hipLaunchKernelGGL(k_leaf_inv, dim3((unsigned)leaves), dim3(NT), 0, s, H.Xp, m, t, bL, H.Dinv, status);
+    } else {
+        // Cholesky factor and inverse of the padded blocks, batched in HBM (lower, column-major)
+        if (!bh && blas_handle(ctx, bh) != MAG_OK) return MAG_EHIP;
+        const unsigned chunks = (unsigned)(ls * ls / (NT * 16));
+        hipLaunchKernelGGL(k_leaf_fill, dim3((unsigned)leaves, chunks), dim3(NT), 0, s, H.Xp, m, t, bL, ls, H.Dinv);
+        RBCHK(rocsolver_dpotrf_strided_batched(bh, rocblas_fill_lower, ls, H.Dinv, ls, (rocblas_stride)ls * ls, rinfo,
+                                               (rocblas_int)leaves));
+        hipLaunchKernelGGL(k_leaf_info, dim3((unsigned)cdiv(leaves, NT)), dim3(NT), 0, s, rinfo, bL, leaves, status);
+        RBCHK(rocsolver_dpotri_strided_batched(bh, rocblas_fill_lower, ls, H.Dinv, ls, (rocblas_stride)ls * ls, rinfo,
+                                               (rocblas_int)leaves));
+        hipLaunchKernelGGL(k_leaf_info, dim3((unsigned)cdiv(leaves, NT)), dim3(NT), 0, s, rinfo, bL, leaves, status);
+        hipLaunchKernelGGL(k_leaf_symm, dim3((unsigned)leaves, chunks), dim3(NT), 0, s, H.Dinv, ls);
+    }
+    for (int l = 0; l < L; ++l) {
+        const dim3 g((unsigned)leaves, (unsigned)(pl.k[l] / SL), (unsigned)(ls / 128));
+        if (ls == LSW)
+            hipLaunchKernelGGL(k_leaf_apply<LSW>, g, dim3(NT), 0, s, H.Dinv, bL, H.P + pl.poff[l],
+                               H.Ph + pl.poff[l], pl.k[l]);
+        else
+            hipLaunchKernelGGL(k_leaf_apply<LMAX>, g, dim3(NT), 0, s, H.Dinv, bL, H.P + pl.poff[l],
+                               H.Ph + pl.poff[l], pl.k[l]);
+    }
 
     // 3. bottom-up Woodbury factors
     for (int l = L - 1; l >= 0; --l) {
@@ -967,7 +1057,10 @@ void hodlr_apply(hipStream_t s, const HodlrFactor &H, const double *r, double *z
     const int64_t leaves = (int64_t)1 << L;
     const unsigned gb = (unsigned)std::min<int64_t>(cdiv(H.npad, 256), 2048);
     hipLaunchKernelGGL(k_gather, dim3(gb), dim3(256), 0, s, r, H.perm, n, H.xp);
-    hipLaunchKernelGGL(k_leaf_gemv, dim3((unsigned)leaves), dim3(NT), 0, s, H.Dinv, H.bnd + boff(L), H.xp);
+    if (H.ls == LSW)
+        hipLaunchKernelGGL(k_leaf_gemv<LSW>, dim3((unsigned)leaves), dim3(NT), 0, s, H.Dinv, H.bnd + boff(L), H.xp);
+    else
+        hipLaunchKernelGGL(k_leaf_gemv<LMAX>, dim3((unsigned)leaves), dim3(NT), 0, s, H.Dinv, H.bnd + boff(L), H.xp);
     for (int l = L - 1; l >= 0; --l) {
         const int k = H.k[l];
         const int64_t tasks = (int64_t)1 << l, nch = 2 * tasks;

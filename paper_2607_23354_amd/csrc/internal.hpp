@@ -428,7 +428,7 @@ void launch_golden(hipStream_t s, double *y, int64_t n, int64_t len);
 // its nodes' [B | C | S^{-1}] blocks (k[l] x k[l] each) start at W + woff[l].
 struct HodlrFactor {
     int64_t n = 0, npad = 0;
-    int m = 0, L = 0;
+    int m = 0, L = 0, ls = 0;  // ls: leaf storage stride (ls x ls inverse per leaf)
     double t = 0.0;
     double *Xp = nullptr, *P = nullptr, *Ph = nullptr, *Dinv = nullptr, *W = nullptr;
     double *apart = nullptr, *tv = nullptr, *xp = nullptr;
@@ -450,6 +450,7 @@ __host__ __device__ inline double ridders_point(double sa, double ga, double sb,
 }
 
 int hodlr_max_leaf();
+int hodlr_default_leaf();
 int hodlr_max_cols();
 int hodlr_levels(int64_t n, int leaf);
 // Build the factor of Z(t) for the points X (device, n x m); rank0 is the

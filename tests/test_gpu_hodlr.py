@@ -54,6 +54,15 @@ CASES = [
     ("torus2000_rank512", lambda: W.noisy_torus(2000, seed=5), 0.5, {"max_rank": 512}),
     ("gauss5000_rank512_tstar", lambda: W.gaussian(5000, 3, seed=17), W.gaussian_cutoff_estimate(5000, 3),
      {"max_rank": 512}),
+    # leaves of 129..256 points: batched Cholesky factor and inverse in HBM
+    ("single_leaf200_leaf256", lambda: W.gaussian(200, 3, seed=18), 2.0, {"leaf": 256}),
+    ("torus3000_leaf256_t05", lambda: W.noisy_torus(3000, seed=5), 0.5, {"leaf": 256}),
+    ("torus3000_leaf256_rank64_t2", lambda: W.noisy_torus(3000, seed=5), 2.0,
+     {"leaf": 256, "max_rank": 64, "oversample": 0, "gmres_restart": 100, "max_gmres": 400, "max_outer": 30}),
+    ("gauss3001_leaf256_tstar", lambda: W.gaussian(3001, 3, seed=11), W.gaussian_cutoff_estimate(3001, 3),
+     {"leaf": 256}),
+    ("gauss1200_m8_leaf256_t1", lambda: W.gaussian(1200, 8, seed=12), 1.0, {"leaf": 256}),
+    ("mixture2500_leaf160_t30", lambda: W.gaussian_mixture(2500, 3, seed=14), 30.0, {"leaf": 160}),
 ]
 
 
@@ -92,18 +101,35 @@ def test_hodlr_permutation_equivariant(mag):
 def test_hodlr_rejects_bad_options(mag):
     X = dev(W.gaussian(300, 3, seed=1))
     with pytest.raises(mag.MagError):
-        mag.weighting(X, 1.0, solver="hodlr", leaf=256)
+        mag.weighting(X, 1.0, solver="hodlr", leaf=257)
     with pytest.raises(mag.MagError):
         mag.weighting(X, 1.0, solver="hodlr", leaf=1)
     with pytest.raises(mag.MagError):
         mag.weighting(dev(W.gaussian(300, 17, seed=1)), 1.0, solver="hodlr")
 
 
-def test_hodlr_duplicates(mag):
+@pytest.mark.parametrize("leaf", [128, 256])
+def test_hodlr_duplicates(mag, leaf):
+    # two equal points in one leaf: the leaf block is singular (the sweep's or the
+    # batched Cholesky's failed pivot)
     X = W.gaussian(400, 3, seed=2)
     X[7] = X[300]
     with pytest.raises(mag.MagError):
-        mag.weighting(dev(X), 1.0, solver="hodlr")
+        mag.weighting(dev(X), 1.0, solver="hodlr", leaf=leaf)
+
+
+def test_hodlr_leaf256_matches_leaf128(mag):
+    # two different preconditioners of one system: the answers agree to the solves'
+    # accuracy, and the one-leaf factor (n <= leaf) is the exact inverse
+    X = W.noisy_torus(2500, seed=9)
+    a = mag.weighting(dev(X), 2.0, solver="hodlr", leaf=128)
+    b = mag.weighting(dev(X), 2.0, solver="hodlr", leaf=256)
+    wa, wb = a.w.cpu().numpy(), b.w.cpu().numpy()
+    assert np.abs(wa - wb).max() <= 1e-10 * np.abs(wa).max()
+    Xs = W.gaussian(250, 3, seed=4)
+    one = mag.weighting(dev(Xs), 1.5, solver="hodlr", leaf=256)
+    assert one.info["gmres_iters"] <= 2
+    assert np.abs(oracle.residual(Xs, 1.5, one.w.cpu().numpy())).max() <= 1e-12
 
 
 INNER32 = [c for c in CASES if c[0] in ("torus2000_t05", "torus2000_t8", "gauss3001_tstar",

@@ -76,6 +76,10 @@ CASES = [
     ("square4000_rank512", lambda: W.uniform_square(4000, seed=3), 20.0, {"max_rank": 512}),
     ("torus5000_rank64", lambda: W.noisy_torus(5000, seed=7), 2.0, {"max_rank": 64, "oversample": 0,
                                                                      "gmres_restart": 100, "max_gmres": 400}),
+    ("torus5000_leaf256_rank64", lambda: W.noisy_torus(5000, seed=7), 2.0,
+     {"leaf": 256, "max_rank": 64, "oversample": 0, "gmres_restart": 100, "max_gmres": 400}),
+    ("gauss3001_leaf256_tstar", lambda: W.gaussian(3001, 3, seed=11), W.gaussian_cutoff_estimate(3001, 3),
+     {"leaf": 256}),
 ]
 
 
