@@ -71,12 +71,14 @@ int mag_set_stream(mag_ctx *ctx, void *hip_stream);
 enum {
     MAG_AUTO = 0,        /* by measured cost: MAG_FP32_IR up to n = 49152 (its FP32      *
                           * factor's n^3/3 flops on MFMA are the cheaper solve there:   *
-                          * 0.11-0.13 s against 0.14-0.21 s at n = 32768), MAG_HODLR    *
-                          * above (max_rank 512, GMRES(100), up to 400 inner           *
-                          * iterations; 0.33-0.57 s against 0.76-0.82 s at n = 65536)   *
-                          * when m <= 16; if the HODLR solve does not converge, or      *
-                          * m > 16, MAG_FP32_IR when its npad^2 factor fits in 3/4 of   *
-                          * the device memory, else MAG_ENOMEM                          */
+                          * 0.33-0.38 s against 0.27-0.45 s for HODLR at n = 49152),    *
+                          * MAG_HODLR above (max_rank 512, one subspace iteration,      *
+                          * GMRES(100), up to 400 inner iterations; 0.56-0.78 s against *
+                          * 0.77-0.83 s at n = 65536, 1.1-1.8 s against 2.5-2.6 s at    *
+                          * n = 98304, on tori, Gaussian and clustered clouds) when     *
+                          * m <= 16; if the HODLR solve does not converge, or m > 16,   *
+                          * MAG_FP32_IR when its npad^2 factor fits in 3/4 of the       *
+                          * device memory, else MAG_ENOMEM                              */
     MAG_FP64_DENSE = 1,  /* FP64 Z in HBM + rocSOLVER dpotrf/dpotrs (dense comparator)   */
     MAG_FP32_IR = 2,     /* FP32 MFMA Cholesky + FP64 GMRES iterative refinement         */
     MAG_HODLR = 3,       /* HODLR preconditioner + FP64 GMRES (largest sizes, Sec. 3.2): *
@@ -119,6 +121,12 @@ typedef struct {
                             * (Lanczos on Z and on Z^{-1} through the solve's own           *
                             * preconditioner, to 1e-3 relative; about 10 extra products     *
                             * and 10 extra refinement solves)                              */
+    int32_t power_iters;   /* HODLR range finder: subspace iterations after the first      *
+                            * sample, each replacing the sample Y_I of Z(I, J) by          *
+                            * Z(I, J) Z(J, I) orth(Y_I) (Halko, Martinsson and Tropp,      *
+                            * 2011, Sec. 4.5), default 0; 0..4 (else MAG_EINVAL); HSS      *
+                            * ignores it                                                   */
+    int32_t reserved_;     /* zero                                                        */
 } mag_opts;
 
 #define MAG_INNER_FP64 0

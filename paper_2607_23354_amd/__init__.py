@@ -108,7 +108,8 @@ def make_opts(solver: str = "auto", tol: float = 1e-12, max_outer: int | None = 
               gmres_restart: int | None = None, max_gmres: int | None = None,
               inner_tol: float | None = None, profile: bool = False, leaf: int | None = None,
               max_rank: int | None = None, oversample: int | None = None,
-              seed: int | None = None, inner_prec: str = "fp64", diag: int = 0) -> MagOpts:
+              seed: int | None = None, inner_prec: str = "fp64", diag: int = 0,
+              power_iters: int | None = None) -> MagOpts:
     o = MagOpts()
     _lib.load().mag_opts_default(ctypes.byref(o))
     o.solver = SOLVERS[solver]
@@ -134,6 +135,8 @@ def make_opts(solver: str = "auto", tol: float = 1e-12, max_outer: int | None = 
         raise ValueError(f"inner_prec must be 'fp64' or 'fp32', not {inner_prec!r}")
     o.inner_prec = 0 if inner_prec == "fp64" else 1
     o.diag = int(diag)
+    if power_iters is not None:
+        o.power_iters = power_iters
     return o
 
 

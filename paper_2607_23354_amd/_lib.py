@@ -42,6 +42,8 @@ class MagOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("inner_prec", ctypes.c_int32),
         ("diag", ctypes.c_int32),
+        ("power_iters", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
     ]
 
 

@@ -190,7 +190,9 @@ struct Vecs {
 int carve_vecs(mag_ctx *ctx, int64_t npad, int restart, Vecs &v)
 {
     const int nvec = restart + 1 + 7;
-    CHK(ensure(ctx, ctx->vecs, sizeof(double) * ((size_t)nvec * npad + 512)));
+    // tail: 16 scalars, then the Hessenberg column staging of 2 (restart + 1) + 1 doubles
+    const size_t tail = 16 + 2 * ((size_t)restart + 2) + 64;
+    CHK(ensure(ctx, ctx->vecs, sizeof(double) * ((size_t)nvec * npad + tail)));
     double *p = (double *)ctx->vecs.p;
     v.V = p;
     p += (size_t)(restart + 1) * npad;
@@ -649,7 +651,9 @@ int solve_hodlr(mag_ctx *ctx, const double *X, int64_t n, int m, double t, doubl
     tm.start(o.profile != 0, s);
     tm.mark(0);
     HodlrFactor H;
-    CHK(hodlr_factor(ctx, X, n, m, t, leaf, std::max(0, o.max_rank), std::max(0, o.oversample), o.seed, H));
+    if (o.power_iters < 0 || o.power_iters > 4) return MAG_EINVAL;
+    CHK(hodlr_factor(ctx, X, n, m, t, leaf, std::max(0, o.max_rank), std::max(0, o.oversample), o.power_iters,
+                     o.seed, H));
     tm.mark(1);
     tm.mark(2);
     Vecs v;
@@ -762,10 +766,12 @@ int solve_hss(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double 
 
 // MAG_AUTO takes the HODLR preconditioner above this size.  Measured on the
 // MI355X, whole solves (noisy torus at t = 0.5, 2, 8; Gaussian cloud at its
-// cutoff scale): n = 32768: dense FP32 factor + refinement 114-132 ms, HODLR
-// (max_rank 512) 143-213 ms; n = 65536: 757-822 ms against 333-570 ms;
-// n = 98304: 2.47-2.62 s against 0.81-1.24 s.  The crossover lies between the
-// first two sizes (nearer the upper for Gaussian clouds, which compress worse).
+// cutoff scale; mixture of five Gaussians at t = 30, 100): n = 49152: dense
+// FP32 factor + refinement 331-377 ms, HODLR 272-455 ms; n = 65536: 767-828 ms
+// against 558-784 ms (HODLR with max_rank 512 and one subspace iteration);
+// n = 98304: 2.47-2.62 s against 1.12-1.76 s.  The clustered clouds compress
+// worst and put the crossover near the upper sizes; without the subspace
+// iteration the HODLR solve of the mixture at t = 30 stalls at n = 131072.
 constexpr int64_t kAutoHodlrMinN = 49152;
 
 // Whether the dense FP32 factor's npad^2 floats fit in three quarters of the
@@ -1126,6 +1132,7 @@ void mag_opts_default(mag_opts *o)
     o->seed = 0x9E3779B97F4A7C15ull;
     o->inner_prec = MAG_INNER_FP64;
     o->diag = 0;
+    o->power_iters = 0;
 }
 
 int mag_create(mag_ctx **out, int device)
@@ -1355,6 +1362,7 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
             if (auto_hodlr) {
                 mag_opts oh = o;
                 oh.max_rank = std::max(oh.max_rank, 512);
+                oh.power_iters = std::max(oh.power_iters, 1);
                 oh.gmres_restart = std::max(oh.gmres_restart, 100);
                 oh.max_gmres = std::max(oh.max_gmres, 400);
                 oh.max_outer = std::max(oh.max_outer, 30);

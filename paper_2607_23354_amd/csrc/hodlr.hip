@@ -852,10 +852,10 @@ static int blas_handle(mag_ctx *ctx, rocblas_handle &h)
     } while (0)
 
 int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int leaf, int rank0,
-                 int oversample, uint64_t seed, HodlrFactor &H)
+                 int oversample, int power, uint64_t seed, HodlrFactor &H)
 {
     hipStream_t s = ctx->stream;
-    if (m > MMAXH || leaf < 2 || leaf > LMAX || rank0 < 0 || oversample < 0) return MAG_EINVAL;
+    if (m > MMAXH || leaf < 2 || leaf > LMAX || rank0 < 0 || oversample < 0 || power < 0) return MAG_EINVAL;
     const int L = hodlr_levels(n, leaf);
     const int64_t npad = round_up(n, kPad);
     rocblas_handle bh = nullptr;
@@ -941,7 +941,8 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
     };
     const double one = 1.0, mone = -1.0, zero = 0.0;
 
-    // 1. bases of every level: sample, orthonormalise (shifted CholeskyQR, three passes), project
+    // 1. bases of every level: sample, orthonormalise (shifted CholeskyQR, three
+    // passes), optionally iterate the subspace, project
     for (int l = 0; l < L; ++l) {
         const int k = pl.k[l];
         const int64_t tasks = (int64_t)1 << l;
@@ -952,20 +953,39 @@ int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int 
                            mix64(seed + 0x51ed2701ull * (uint64_t)(l + 1)));
         launch_zblock(s, H.Xp, m, t, bch, 0, tasks, rb, Om, Pl, k, k);
         double *src = Pl, *dst = W2;
-        for (int pass = 0; pass < 3; ++pass) {
-            gram(src, k, src, k, bch, 2, 0, tasks, l, G);
-            hipLaunchKernelGGL(k_gram_shift, dim3((unsigned)tasks), dim3(NT), 0, s, G, k, bch, 2, 0);
-            RBCHK(rocsolver_dpotrf_strided_batched(bh, rocblas_fill_upper, k, G, k, (rocblas_stride)k * k, rinfo,
-                                                   (rocblas_int)tasks));
-            RBCHK(rocsolver_dtrtri_strided_batched(bh, rocblas_fill_upper, rocblas_diagonal_non_unit, k, G, k,
-                                                   (rocblas_stride)k * k, rinfo, (rocblas_int)tasks));
-            hipLaunchKernelGGL(k_zero_lower, dim3(1024), dim3(NT), 0, s, G, k, tasks);
-            hipLaunchKernelGGL(k_rowmul, dim3((unsigned)(tasks * rb), (unsigned)(k / SL)), dim3(NT), 0, s, src, k,
-                               dst, k, G, (int64_t)k * k, bch, 2, 0, rb, 0);
-            std::swap(src, dst);
+        // orthonormalise the rows of the left (side 0) or right (side 1)
+        // children of src; the result ends in src (the buffers swap)
+        auto orth = [&](int side) -> int {
+            for (int pass = 0; pass < 3; ++pass) {
+                gram(src, k, src, k, bch, 2, side, tasks, l, G);
+                hipLaunchKernelGGL(k_gram_shift, dim3((unsigned)tasks), dim3(NT), 0, s, G, k, bch, 2, side);
+                RBCHK(rocsolver_dpotrf_strided_batched(bh, rocblas_fill_upper, k, G, k, (rocblas_stride)k * k,
+                                                       rinfo, (rocblas_int)tasks));
+                RBCHK(rocsolver_dtrtri_strided_batched(bh, rocblas_fill_upper, rocblas_diagonal_non_unit, k, G, k,
+                                                       (rocblas_stride)k * k, rinfo, (rocblas_int)tasks));
+                hipLaunchKernelGGL(k_zero_lower, dim3(1024), dim3(NT), 0, s, G, k, tasks);
+                hipLaunchKernelGGL(k_rowmul, dim3((unsigned)(tasks * rb), (unsigned)(k / SL)), dim3(NT), 0, s, src,
+                                   k, dst, k, G, (int64_t)k * k, bch, 2, side, rb, 0);
+                std::swap(src, dst);
+            }
+            return MAG_OK;
+        };
+        if (orth(0) != MAG_OK) return MAG_EHIP;
+        for (int q = 0; q < power; ++q) {
+            // subspace iteration with an orthonormalisation after every product:
+            // Q_J = orth(Z(J, I) Q_I), then Q_I = orth(Z(I, J) Q_J).  Each product
+            // reads one side's rows of src and writes the other side's (in place);
+            // the side an orthonormalisation leaves behind in the other buffer is
+            // the one the next product overwrites.
+            launch_zblock(s, H.Xp, m, t, bch, 1, tasks, rb, src, src, k, k);
+            if (orth(1) != MAG_OK) return MAG_EHIP;
+            launch_zblock(s, H.Xp, m, t, bch, 0, tasks, rb, src, src, k, k);
+            if (orth(0) != MAG_OK) return MAG_EHIP;
         }
-        // three passes end in W2: copy the left children's rows back
-        hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)(tasks * rb)), dim3(NT), 0, s, src, Pl, k, bch, 2, 0, rb);
+        // the basis of the left children into P_l (an odd number of passes ends in W2)
+        if (src != Pl)
+            hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)(tasks * rb)), dim3(NT), 0, s, src, Pl, k, bch, 2, 0,
+                               rb);
         launch_zblock(s, H.Xp, m, t, bch, 1, tasks, rb, Pl, Pl, k, k);
     }
 

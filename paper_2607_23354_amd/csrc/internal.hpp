@@ -455,10 +455,10 @@ int hodlr_max_cols();
 int hodlr_levels(int64_t n, int leaf);
 // Build the factor of Z(t) for the points X (device, n x m); rank0 is the
 // basis rank of the top level (halved every two levels), oversample the extra
-// sample columns.  Status words in ctx->ints.  MAG_ENOTPD when a leaf block
-// is not positive definite.
+// sample columns, power the subspace iterations of the range finder.  Status
+// words in ctx->ints.  MAG_ENOTPD when a leaf block is not positive definite.
 int hodlr_factor(mag_ctx *ctx, const double *X, int64_t n, int m, double t, int leaf, int rank0,
-                 int oversample, uint64_t seed, HodlrFactor &H);
+                 int oversample, int power, uint64_t seed, HodlrFactor &H);
 // z = H^{-1} r; r, z device vectors of length npad (z zero on [n, npad)).
 void hodlr_apply(hipStream_t s, const HodlrFactor &H, const double *r, double *z);
 

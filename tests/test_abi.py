@@ -56,15 +56,16 @@ def test_struct_layouts_match_c(tmp_path):
         " offsetof(mag_eig_info, iters_max), offsetof(mag_eig_info, solve_steps));\n"
         'printf("%zu %zu %zu\\n", sizeof(mag_tplus_opts), offsetof(mag_tplus_opts, method),'
         " offsetof(mag_tplus_opts, lo_factor));\n"
-        'printf("%zu %zu %zu %zu\\n", offsetof(mag_opts, diag), offsetof(mag_info, solver),'
-        " offsetof(mag_info, backward_err), offsetof(mag_info, cond_est));\n"
+        'printf("%zu %zu %zu %zu %zu\\n", offsetof(mag_opts, diag), offsetof(mag_info, solver),'
+        " offsetof(mag_info, backward_err), offsetof(mag_info, cond_est), offsetof(mag_opts, power_iters));\n"
         "return 0;}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     (so, si, o_tol, o_seed, o_ip, o_arg, o_nu, seo, sei, o_rt, o_im, o_ss, sto, o_me, o_lf,
-     o_dg, o_sv, o_be, o_ce) = map(int, out)
+     o_dg, o_sv, o_be, o_ce, o_pw) = map(int, out)
     assert o_dg == L.MagOpts.diag.offset and o_sv == L.MagInfo.solver.offset
+    assert o_pw == L.MagOpts.power_iters.offset
     assert o_be == L.MagInfo.backward_err.offset and o_ce == L.MagInfo.cond_est.offset
     assert sto == ctypes.sizeof(L.MagTplusOpts) and o_me == L.MagTplusOpts.method.offset
     assert o_lf == L.MagTplusOpts.lo_factor.offset
@@ -102,6 +103,7 @@ def test_host_only_entry_points():
     held = ctypes.c_uint64()
     assert lib.mag_workspace_bytes(None, ctypes.byref(held)) == L.MAG_EINVAL
     assert o.diag == 0  # no diagnostics unless asked
+    assert o.power_iters == 0 and o.reserved_ == 0  # one Gaussian sample per level unless asked
     to = L.MagTplusOpts()
     lib.mag_tplus_opts_default(ctypes.byref(to))
     assert to.method == 0 and to.newton == 1  # bisection with safeguarded Newton unless asked

@@ -63,6 +63,13 @@ CASES = [
      {"leaf": 256}),
     ("gauss1200_m8_leaf256_t1", lambda: W.gaussian(1200, 8, seed=12), 1.0, {"leaf": 256}),
     ("mixture2500_leaf160_t30", lambda: W.gaussian_mixture(2500, 3, seed=14), 30.0, {"leaf": 160}),
+    # range finder with subspace iterations
+    ("torus3000_power1_t05", lambda: W.noisy_torus(3000, seed=5), 0.5, {"power_iters": 1}),
+    ("torus3000_power1_rank64_t2", lambda: W.noisy_torus(3000, seed=5), 2.0,
+     {"power_iters": 1, "max_rank": 64, "oversample": 0, "gmres_restart": 100, "max_gmres": 400}),
+    ("gauss3001_power2_leaf256_tstar", lambda: W.gaussian(3001, 3, seed=11), W.gaussian_cutoff_estimate(3001, 3),
+     {"power_iters": 2, "leaf": 256}),
+    ("gauss1200_m8_power1_t1", lambda: W.gaussian(1200, 8, seed=12), 1.0, {"power_iters": 1}),
 ]
 
 
@@ -104,6 +111,10 @@ def test_hodlr_rejects_bad_options(mag):
         mag.weighting(X, 1.0, solver="hodlr", leaf=257)
     with pytest.raises(mag.MagError):
         mag.weighting(X, 1.0, solver="hodlr", leaf=1)
+    with pytest.raises(mag.MagError):
+        mag.weighting(X, 1.0, solver="hodlr", power_iters=5)
+    with pytest.raises(mag.MagError):
+        mag.weighting(X, 1.0, solver="hodlr", power_iters=-1)
     with pytest.raises(mag.MagError):
         mag.weighting(dev(W.gaussian(300, 17, seed=1)), 1.0, solver="hodlr")
 

@@ -6,7 +6,10 @@ handles that size:
   size here whose factor has more than 2^31 entries, so its 64-bit indexing is
   exercised) + FP64 matrix-free GMRES-IR;
 * MAG_HODLR and MAG_HSS: hierarchical preconditioners + the same FP64 GMRES,
-  with the top-level rank the benchmark uses (max_rank 512).
+  with the top-level rank the benchmark uses (max_rank 512);
+* MAG_HODLR with max_rank 256 and one subspace iteration of the range finder;
+* MAG_HODLR with leaves of 256 points and ranks of at most 64 (several hundred
+  GMRES iterations: a weaker preconditioner).
 
 The oracle cannot hold Z at this size (137 GB in FP64), so it checks the
 residual 1 - Z w on sampled rows one by one (Dot2).  The magnitudes of the
@@ -28,6 +31,15 @@ SOLVERS = {
     "fp32_ir": {},
     "hodlr": {"max_rank": 512, "gmres_restart": 100, "max_gmres": 400, "max_outer": 30},
     "hss": {"max_rank": 512, "gmres_restart": 100, "max_gmres": 400, "max_outer": 30},
+    # rank 256 with one subspace iteration of the range finder: the fastest
+    # HODLR setting measured on this cloud
+    "hodlr_rank256_power1": {"solver": "hodlr", "max_rank": 256, "power_iters": 1, "gmres_restart": 100,
+                             "max_gmres": 400, "max_outer": 30},
+    # the hierarchical setting of the large workload as stated: leaves of 256
+    # points, ranks of at most 64 (a weak preconditioner: several hundred GMRES
+    # iterations in cycles of 400)
+    "hodlr_leaf256_rank64": {"solver": "hodlr", "leaf": 256, "max_rank": 64, "oversample": 0, "power_iters": 1,
+                             "gmres_restart": 400, "max_gmres": 1600, "max_outer": 30},
 }
 
 
@@ -43,7 +55,8 @@ def test_torus_full_size_all_solvers(mag, torus, t):
     rows = np.random.default_rng(5).choice(N, size=256, replace=False)
     got = {}
     for name, kw in SOLVERS.items():
-        res = mag.weighting(Xd, t, solver=name, profile=True, **kw)
+        kw = dict(kw)
+        res = mag.weighting(Xd, t, solver=kw.pop("solver", name), profile=True, **kw)
         w = res.w.cpu().numpy()
         r = float(np.abs(oracle.residual(X, t, w, rows)).max())
         info = res.info
