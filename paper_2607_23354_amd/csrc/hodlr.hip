@@ -195,22 +195,30 @@ k_zblock(const double *__restrict__ Xp, int m_rt, double t, const int64_t *__res
 }
 
 // Launch k_zblock over `tasks` sibling pairs, `cols` columns (a multiple of 64)
-// of B and out, with as many slabs per workgroup as divide them (up to 4).
+// of B and out: groups of 4 slabs per workgroup, then the remainder in one
+// launch of 2 and/or 1 (5 slabs: 4 + 1, so each Z entry is formed twice, not
+// five times).  The sums do not depend on the grouping.
 void launch_zblock(hipStream_t s, const double *Xp, int m, double t, const int64_t *bnd, int mode, int64_t tasks,
                    int rbmax, const double *B, double *out, int ld, int cols)
 {
     const int slabs = cols / SL;
     const unsigned gx = (unsigned)(tasks * rbmax);
-    const int ns = (slabs % 4 == 0) ? 4 : (slabs % 2 == 0) ? 2 : 1;
-    const dim3 g(gx, (unsigned)(slabs / ns));
-    if (m == 3) {
-        if (ns == 4) hipLaunchKernelGGL((k_zblock<4, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
-        else if (ns == 2) hipLaunchKernelGGL((k_zblock<2, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
-        else hipLaunchKernelGGL((k_zblock<1, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
-    } else {
-        if (ns == 4) hipLaunchKernelGGL((k_zblock<4, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
-        else if (ns == 2) hipLaunchKernelGGL((k_zblock<2, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
-        else hipLaunchKernelGGL((k_zblock<1, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, B, out, ld);
+    for (int done = 0; done < slabs;) {
+        const int rem = slabs - done;
+        const int ns = rem >= 4 ? 4 : rem >= 2 ? 2 : 1;
+        const dim3 g(gx, (unsigned)(rem / ns));
+        const double *Bd = B + done * SL;
+        double *od = out + done * SL;
+        if (m == 3) {
+            if (ns == 4) hipLaunchKernelGGL((k_zblock<4, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, Bd, od, ld);
+            else if (ns == 2) hipLaunchKernelGGL((k_zblock<2, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, Bd, od, ld);
+            else hipLaunchKernelGGL((k_zblock<1, 3>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, Bd, od, ld);
+        } else {
+            if (ns == 4) hipLaunchKernelGGL((k_zblock<4, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, Bd, od, ld);
+            else if (ns == 2) hipLaunchKernelGGL((k_zblock<2, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, Bd, od, ld);
+            else hipLaunchKernelGGL((k_zblock<1, 0>), g, dim3(NT), 0, s, Xp, m, t, bnd, mode, rbmax, Bd, od, ld);
+        }
+        done += (rem / ns) * ns;
     }
 }
 
