@@ -14,20 +14,26 @@
 //     on how many workgroups fit on the device;
 //   * block b streams its off-diagonal tiles in order (forward: L(b, j) from
 //     the lower triangle; backward: L^T(b, j) from the upper triangle, where
-//     the factorisation keeps the transpose); tiles are loaded into registers
-//     two steps ahead of the wait for the solution block they multiply, and
-//     the band's own right-hand side and inner tile before the first wait, so
-//     the HBM stream stays off the dependency chain;
-//   * a "ready" count (blocks [0, ready) are final) replaces per-block flags,
-//     since block b can only finish after block b-1 has; a band publishes
-//     both of its blocks at once.  It is published in
-//     8 mirrored slots 256 bytes apart (each workgroup polls one);
-//   * every cross-workgroup exchange is done by wave 0 alone, since each
-//     fence a wave executes costs microseconds: wave 0 writes all of the
-//     band's solution entries, takes one agent-scope release fence and stores
-//     the counters; a poller's wave 0 takes one acquire fence per observed
-//     advance (an acquire per poll would invalidate the L2 on every spin) and
-//     reads the published blocks into LDS for the others;
+//     the factorisation keeps the transpose); the tiles of a pair of outside
+//     blocks are loaded into registers a whole pair-step ahead of the wait
+//     for the solution blocks they multiply, and the band's own right-hand
+//     side and inner tile before the first wait, so the HBM stream stays off
+//     the dependency chain.  What stays on it, per band (measured at
+//     n = 32768 with in-kernel clock stamps, 7.2 us per band): 2.9 us from a
+//     band's last store to the next band seeing it, 1.3 us for the four FP64
+//     tile products with the received blocks (FP64-FMA bound: 64 Ki products
+//     and conversions on one CU), 2.7 us for the two diagonal solves, the
+//     inner tile and the LDS reductions;
+//   * the solution vector is the flag: before a solve every entry holds an
+//     "unset" bit pattern (a signalling NaN no arithmetic produces); a band
+//     writes its solution entries with relaxed agent-scope atomic stores, and
+//     a waiting band's wave 0 reads the entries it needs with relaxed
+//     agent-scope atomic loads until none is unset.  Each entry is written
+//     once, so a value that is not the pattern is final: no counter, no
+//     release or acquire fence (each fence a wave executes costs microseconds
+//     of L2 write-back or invalidation) and no second read of the data;
+//   * wave 0 alone polls and copies the received blocks into LDS for the
+//     others;
 //   * spin-waits are bounded: on exhaustion the kernel sets a status word and
 //     finishes, and the host reports an error.
 // HBM traffic per apply: the lower triangle read twice (n^2 * 4 bytes).
@@ -38,40 +44,57 @@ namespace {
 
 constexpr int BS = 128;
 constexpr long kSpinLimit = 1L << 26;
-constexpr int kMirrors = 8;
-constexpr int kSlot = 64;  // ints between mirrored slots (256 bytes)
+constexpr int kSlot = 64;  // ints between the two tickets (256 bytes)
 
-// counter layout (ints): fwd ticket @0, bwd ticket @kSlot,
-// fwd ready mirrors @(2+q)*kSlot, bwd ready mirrors @(2+kMirrors+q)*kSlot
+// counter layout (ints): fwd ticket @0, bwd ticket @kSlot
 constexpr int kFwdTicket = 0;
 constexpr int kBwdTicket = kSlot;
-constexpr int kFwdReady = 2 * kSlot;
-constexpr int kBwdReady = (2 + kMirrors) * kSlot;
-constexpr int kCounterInts = (2 + 2 * kMirrors) * kSlot;
+constexpr int kCounterInts = 2 * kSlot;
 
-__device__ inline int wait_ready(int *ready, int need, int *status)
+// the "unset" entry: a signalling NaN payload (arithmetic yields quiet NaNs)
+constexpr uint64_t kUnset = 0x7ff4dead0badf00dull;
+
+__device__ inline uint64_t ld_entry(const double *x, int64_t i)
 {
-    int v;
+    return __hip_atomic_load(reinterpret_cast<const uint64_t *>(x) + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void st_entry(double *x, int64_t i, double v)
+{
+    __hip_atomic_store(reinterpret_cast<uint64_t *>(x) + i, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave 0 (lanes 0..63): wait until the entries of block j0 (and j1 if two) of
+// x are set, and copy them to xs[0] (xs[1]).  Bounded: on exhaustion the
+// status word is set and whatever was read is used.
+__device__ inline void wait_blocks(const double *x, int64_t j0, int64_t j1, bool two, double (&xs)[2][BS],
+                                   int *status)
+{
+    const int lane = threadIdx.x;
+    uint64_t a0, a1, c0 = 0, c1 = 0;
     long spins = 0;
-    while ((v = __hip_atomic_load(ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
+    for (;;) {
+        a0 = ld_entry(x, j0 * BS + lane);
+        a1 = ld_entry(x, j0 * BS + lane + 64);
+        if (two) {
+            c0 = ld_entry(x, j1 * BS + lane);
+            c1 = ld_entry(x, j1 * BS + lane + 64);
+        }
+        const bool miss = a0 == kUnset || a1 == kUnset || (two && (c0 == kUnset || c1 == kUnset));
+        if (__ballot(miss) == 0) break;
         if (++spins > kSpinLimit) {
-            status[kStSpinTimeout] = 1;
-            return 1 << 30;  // give up: treat everything as ready
+            if (lane == 0) status[kStSpinTimeout] = 1;
+            break;
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    return v;
-}
-
-// Called by wave 0, which wrote every published solution entry: one release
-// fence for the wave, then a relaxed atomic maximum on each mirrored counter
-// (a counter only grows, whatever order the bands' updates reach a mirror in).
-__device__ inline void publish(int *base, int value)
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (threadIdx.x < kMirrors)
-        (void)__hip_atomic_fetch_max(base + threadIdx.x * kSlot, value, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
+    xs[0][lane] = __builtin_bit_cast(double, a0);
+    xs[0][lane + 64] = __builtin_bit_cast(double, a1);
+    if (two) {
+        xs[1][lane] = __builtin_bit_cast(double, c0);
+        xs[1][lane + 64] = __builtin_bit_cast(double, c1);
+    }
 }
 
 // One triangular solve.  Forward (BWD = false): y = L^{-1} r, block b pulls
@@ -93,7 +116,7 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     __shared__ float Dl[2][BS * (BS + 1)];  // Dinv of the two blocks, row-major, padded stride
     __shared__ double xs[2][BS];
     __shared__ double part[8][BS];          // per column group partial sums of a block's rows
-    __shared__ int s_band, s_ready;
+    __shared__ int s_band;
     const int tid = threadIdx.x;
     const int nband = nblk / 2;
     if (tid == 0) {
@@ -111,7 +134,6 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     // block solves: thread (h, row) takes half h of row's dot product
     const int row = tid & (BS - 1);
     const int h = tid >> 7;
-    int *ready = counters + (BWD ? kBwdReady : kFwdReady) + (band % kMirrors) * kSlot;
 
     // tile (b, j): element (r, c) at L[(j BS + c) ld + b BS + r] -- forward L(b, j)
     // from the lower triangle, backward L^T(b, j) from the upper triangle
@@ -150,39 +172,16 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
         }
     }
     double acc0[4] = {0.0, 0.0, 0.0, 0.0}, acc1[4] = {0.0, 0.0, 0.0, 0.0};
-    int known = 0;
-    // blocks outside the band, in the order they finish, two at a time; ready
-    // counts finished blocks.  A pair's tiles are fetched before its wait, the
-    // next pair's right after it.
+    // blocks outside the band, in the order they finish, two at a time.  A
+    // pair's tiles are fetched before its wait, the next pair's right after it.
     const int nsteps = BWD ? (nblk - 2 - 2 * band) : 2 * band;
     float4 ta0[16], ta1[16], tb0[16], tb1[16];
     auto jof = [&](int st) { return BWD ? (nblk - 1 - st) : st; };
-    // steps st and st + 1 (if any): one wait, one read of both solution blocks
-    // (bands publish two blocks at a time, so both are ready together)
+    // steps st and st + 1 (if any): wave 0 waits for both solution blocks (a
+    // band writes its two blocks moments apart) and copies them to LDS
     auto consume2 = [&](int st, bool two) {
-        const int need = st + (two ? 2 : 1);
-        if (need > known && tid < 64) {
-            // wave 0 waits, takes the one acquire and reads the published blocks;
-            // the others learn the new count after the barrier below
-            int v = 0;
-            if (tid == 0) v = wait_ready(ready, need, status);
-            v = __builtin_amdgcn_readfirstlane(v);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (tid == 0) s_ready = v;
-        }
-        if (tid < 64) {
-            const int lane = tid;
-            const int64_t j0 = (int64_t)jof(st) * BS;
-            xs[0][lane] = x[j0 + lane];
-            xs[0][lane + 64] = x[j0 + lane + 64];
-            if (two) {
-                const int64_t j1 = (int64_t)jof(st + 1) * BS;
-                xs[1][lane] = x[j1 + lane];
-                xs[1][lane + 64] = x[j1 + lane + 64];
-            }
-        }
+        if (tid < 64) wait_blocks(x, jof(st), two ? jof(st + 1) : 0, two, xs, status);
         __syncthreads();
-        known = s_ready;
         gemv(ta0, xs[0], acc0);
         gemv(ta1, xs[0], acc1);
         if (two) {
@@ -197,16 +196,21 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
         load(b0, jof(0), ta0);
         load(b1, jof(0), ta1);
     }
+    if (nsteps > 1) {
+        load(b0, jof(1), tb0);
+        load(b1, jof(1), tb1);
+    }
     for (int st = 0; st < nsteps; st += 2) {
         const bool two = st + 1 < nsteps;
-        if (two) {
-            load(b0, jof(st + 1), tb0);
-            load(b1, jof(st + 1), tb1);
-        }
         consume2(st, two);
+        // both tiles of the next pair, a whole step ahead of their wait
         if (st + 2 < nsteps) {
             load(b0, jof(st + 2), ta0);
             load(b1, jof(st + 2), ta1);
+        }
+        if (st + 3 < nsteps) {
+            load(b0, jof(st + 3), tb0);
+            load(b1, jof(st + 3), tb1);
         }
     }
 
@@ -232,10 +236,10 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     __syncthreads();
     if (tid < BS) xs[1][tid] = part[0][tid] + part[1][tid];
     __syncthreads();
-    // wave 0 writes the band's solution entries and publishes them (one release)
+    // wave 0 writes the band's solution entries (each write releases that entry)
     if (tid < 64) {
-        x[(int64_t)b0 * BS + tid] = xs[1][tid];
-        x[(int64_t)b0 * BS + tid + 64] = xs[1][tid + 64];
+        st_entry(x, (int64_t)b0 * BS + tid, xs[1][tid]);
+        st_entry(x, (int64_t)b0 * BS + tid + 64, xs[1][tid + 64]);
     }
     // second block: acc1 += L(b1, b0) x_b0, then x_b1 = Dinv_b1 (rhs_b1 - acc1)
     gemv(ti, xs[1], acc1);
@@ -259,9 +263,8 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     part[h][row] = v;
     __syncthreads();
     if (tid < 64) {
-        x[(int64_t)b1 * BS + tid] = part[0][tid] + part[1][tid];
-        x[(int64_t)b1 * BS + tid + 64] = part[0][tid + 64] + part[1][tid + 64];
-        publish(counters + (BWD ? kBwdReady : kFwdReady), nsteps + 2);
+        st_entry(x, (int64_t)b1 * BS + tid, part[0][tid] + part[1][tid]);
+        st_entry(x, (int64_t)b1 * BS + tid + 64, part[0][tid + 64] + part[1][tid + 64]);
     }
 }
 
@@ -287,11 +290,24 @@ k_trsv_b(const BProb *__restrict__ P, BWork w, int rhs_slot, int x_slot)
                    q.vec + (int64_t)x_slot * q.npad, q.ints + 64, (int)(q.npad / BS), q.ints);
 }
 
-__global__ void k_zero_counters_b(const BProb *__restrict__ P, BWork w)
+// Tickets to zero and the vector in `slot` unset, one workgroup per problem
+// (tickets: only when `tickets`).
+__global__ void k_unset_b(const BProb *__restrict__ P, BWork w, int slot, int tickets)
 {
     const BProb &q = P[w.plist[blockIdx.x]];
     if (!q.active) return;
-    for (int e = threadIdx.x; e < kCounterInts; e += blockDim.x) q.ints[64 + e] = 0;
+    if (tickets)
+        for (int e = threadIdx.x; e < kCounterInts; e += blockDim.x) q.ints[64 + e] = 0;
+    uint64_t *a = reinterpret_cast<uint64_t *>(q.vec + (int64_t)slot * q.npad);
+    for (int64_t e = threadIdx.x; e < q.npad; e += blockDim.x) a[e] = kUnset;
+}
+
+// Every entry of a (n entries) unset.
+__global__ void k_unset(double *__restrict__ a, int64_t n)
+{
+    uint64_t *u = reinterpret_cast<uint64_t *>(a);
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        u[e] = kUnset;
 }
 
 }  // namespace
@@ -305,8 +321,9 @@ void launch_prec_apply_b(hipStream_t s, const BProb *P, const BWork &w, int rhs_
                          int x_slot)
 {
     if (w.na <= 0) return;
-    hipLaunchKernelGGL(k_zero_counters_b, dim3(w.na), dim3(256), 0, s, P, w);
+    hipLaunchKernelGGL(k_unset_b, dim3(w.na), dim3(256), 0, s, P, w, tmp_slot, 1);
     hipLaunchKernelGGL(k_trsv_b<false>, dim3((unsigned)w.total), dim3(256), 0, s, P, w, rhs_slot, tmp_slot);
+    hipLaunchKernelGGL(k_unset_b, dim3(w.na), dim3(256), 0, s, P, w, x_slot, 0);
     hipLaunchKernelGGL(k_trsv_b<true>, dim3((unsigned)w.total), dim3(256), 0, s, P, w, tmp_slot, x_slot);
 }
 
@@ -314,9 +331,13 @@ void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float 
                        const double *r, double *y_tmp, double *z, int *counters, int *status)
 {
     const int nblk = (int)(npad / BS);  // even: npad is a multiple of 256
+    const unsigned gu = (unsigned)std::min<int64_t>((npad + 255) / 256, 1024);
     launch_fill_ints(s, counters, kCounterInts, 0);
+    hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, y_tmp, npad);
     hipLaunchKernelGGL(k_trsv<false>, dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, r, y_tmp, counters,
                        nblk, status);
+    // z may be the caller's r: unset it only once the forward solve has read r
+    hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, z, npad);
     hipLaunchKernelGGL(k_trsv<true>, dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, y_tmp, z, counters,
                        nblk, status);
 }
