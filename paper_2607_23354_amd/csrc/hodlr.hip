@@ -62,7 +62,7 @@ constexpr int LMAX = 256;   // largest leaf
 constexpr int LSW = 128;    // largest leaf inverted inside LDS (sweep operator)
 constexpr int MMAXH = 16;   // largest point dimension
 constexpr int ZR = 64;      // rows per sampling workgroup
-constexpr int ZC = 64;      // points per sampling column chunk
+constexpr int ZC = 16;      // points per sampling column chunk
 constexpr int NT = 256;     // threads per workgroup
 
 __device__ inline double sq_acc(double s, double e)
@@ -106,9 +106,17 @@ __global__ void __launch_bounds__(NT) k_omega(double *__restrict__ Om, int64_t n
 //   out[r, slab] = sum_{c in C} Z(r, c) B[c, slab]   for r in R,
 // mode 0: R = left child, C = right child;  mode 1: R = right, C = left.
 // bnd: bounds of the children level (2 * tasks + 1 entries).  One workgroup
-// per 64-row block of R and NS slabs; Z is formed 64 x (64 / NS) at a time in
-// LDS and applied to all NS slabs, so each entry's exp is evaluated once per
-// NS slabs.  Every output sums over c in ascending order whatever NS is.
+// per 64-row block of R and NS slabs.  Per chunk of ZC points the Z tile
+// (64 x ZC, FP64 exp of exact distances) is formed in LDS by the VALU and
+// applied to all NS slabs on the FP64 matrix cores (v_mfma_f64_16x16x4: on
+// gfx950 twice the FP64 rate of VALU FMAs, and its operands come one double
+// per lane per 16x16x4 step, so LDS traffic stays small): wave w owns the
+// 16 NS columns [16 NS w, 16 NS (w + 1)) of the workgroup's output, all 64
+// rows, as 4 x NS accumulator blocks of 16 x 16.  The chunk's B rows go
+// through registers, loaded while the previous chunk is applied.  Every
+// output sums the same chunks in the same order whatever NS is.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <int NS, int M>
 __global__ void __launch_bounds__(NT)
 k_zblock(const double *__restrict__ Xp, int m_rt, double t, const int64_t *__restrict__ bnd, int mode,
@@ -117,12 +125,13 @@ k_zblock(const double *__restrict__ Xp, int m_rt, double t, const int64_t *__res
     // M > 0: compile-time dimension (straight-line distance code); M = 0: m_rt <= MMAXH
     constexpr int MM = (M > 0) ? M : MMAXH;
     const int m = (M > 0) ? M : m_rt;
-    constexpr int CC = ZC / NS;  // points per chunk
-    __shared__ double Bs[CC][NS * SL];
+    constexpr int CC = ZC;       // points per chunk (16)
+    constexpr int W = NS * SL;   // output columns of the workgroup
+    __shared__ double Bs[CC][W];
     __shared__ double Zs[ZR][CC + 1];
     __shared__ double Xc[MM][CC];
     const int task = blockIdx.x / rbmax, rb = blockIdx.x % rbmax;
-    const int col0 = blockIdx.y * NS * SL;
+    const int col0 = blockIdx.y * W;
     const int64_t a = bnd[2 * task], b = bnd[2 * task + 1], c = bnd[2 * task + 2];
     const int64_t rlo = mode ? b : a, rhi = mode ? c : b;
     const int64_t clo = mode ? a : b, chi = mode ? b : c;
@@ -131,30 +140,46 @@ k_zblock(const double *__restrict__ Xp, int m_rt, double t, const int64_t *__res
     const int nr = (int)min((int64_t)ZR, rhi - r0);
     const int tid = threadIdx.x;
     const int gr = tid & 63, gp = tid >> 6;  // Z-tile generation: row, group of CC / 4 points
-    const int ty = tid >> 4, tx = tid & 15;  // accumulation: rows 4ty.., columns 4tx.. of each slab
+    const int lane = tid & 63, wv = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;  // MFMA operand lane roles
+    const int cbase = wv * 16 * NS;            // this wave's first output column
     double xr[MM];
 #pragma unroll
     for (int l = 0; l < MM; ++l) xr[l] = (l < m && gr < nr) ? Xp[(r0 + gr) * m + l] : 0.0;
-    double acc[NS][4][4];
+    v4d acc[4][NS];
 #pragma unroll
-    for (int u = 0; u < NS; ++u)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[u][i][j] = 0.0;
+        for (int u = 0; u < NS; ++u) acc[i][u] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    // the B rows of a chunk go through registers: the next chunk's are loaded
+    // while this one's Z tile is formed and applied
+    constexpr int PER = CC * W / NT;
+    double breg[PER];
+    auto fetch = [&](int64_t cb) {
+        const int cn = (int)min((int64_t)CC, chi - cb);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + i * NT;
+            const int p = e / W, q = e % W;
+            breg[i] = (p < cn) ? B[(cb + p) * ld + col0 + q] : 0.0;
+        }
+    };
+    if (clo < chi) fetch(clo);
     for (int64_t c0 = clo; c0 < chi; c0 += CC) {
         const int cnt = (int)min((int64_t)CC, chi - c0);
         __syncthreads();
-        for (int e = tid; e < CC * NS * SL; e += NT) {
-            const int p = e / (NS * SL), q = e % (NS * SL);
-            Bs[p][q] = (p < cnt) ? B[(c0 + p) * ld + col0 + q] : 0.0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + i * NT;
+            Bs[e / W][e % W] = breg[i];
         }
         for (int e = tid; e < m * CC; e += NT) {
             const int l = e / CC, p = e % CC;
             Xc[l][p] = (p < cnt) ? Xp[(c0 + p) * m + l] : 0.0;
         }
         __syncthreads();
+        if (c0 + CC < chi) fetch(c0 + CC);
         for (int q = 0; q < CC / 4; ++q) {
             const int p = gp * (CC / 4) + q;
             double s = 0.0;
@@ -165,33 +190,33 @@ k_zblock(const double *__restrict__ Xp, int m_rt, double t, const int64_t *__res
             Zs[gr][p] = (p < cnt && gr < nr) ? z : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int p = 0; p < CC; ++p) {
+#pragma unroll
+        for (int kk = 0; kk < CC / 4; ++kk) {
+            // A(row, k) = Z(16 i + row, 4 kk + k) for row block i: lane (row = li, k = lk)
             double av[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = Zs[4 * ty + i][p];
+            for (int i = 0; i < 4; ++i) av[i] = Zs[16 * i + li][4 * kk + lk];
 #pragma unroll
             for (int u = 0; u < NS; ++u) {
-                double bv[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bv[j] = Bs[p][u * SL + 4 * tx + j];
+                // B(k, j) = Bs(4 kk + k, cbase + 16 u + j): lane (k = lk, j = li)
+                const double bv = Bs[4 * kk + lk][cbase + 16 * u + li];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[u][i][j] = fma(av[i], bv[j], acc[u][i][j]);
+                    acc[i][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv, acc[i][u], 0, 0, 0);
             }
         }
     }
+    // D(lane, v) = C(lk + 4 v, li) of each 16 x 16 block
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int r = 4 * ty + i;
-        if (r < nr) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int u = 0; u < NS; ++u)
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * i + lk + 4 * v;
+            if (r < nr) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) out[(r0 + r) * ld + col0 + u * SL + 4 * tx + j] = acc[u][i][j];
+                for (int u = 0; u < NS; ++u) out[(r0 + r) * ld + col0 + cbase + 16 * u + li] = acc[i][u][v];
+            }
         }
-    }
 }
 
 // Launch k_zblock over `tasks` sibling pairs, `cols` columns (a multiple of 64)
