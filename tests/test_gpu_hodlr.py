@@ -70,6 +70,14 @@ CASES = [
     ("gauss3001_power2_leaf256_tstar", lambda: W.gaussian(3001, 3, seed=11), W.gaussian_cutoff_estimate(3001, 3),
      {"power_iters": 2, "leaf": 256}),
     ("gauss1200_m8_power1_t1", lambda: W.gaussian(1200, 8, seed=12), 1.0, {"power_iters": 1}),
+    # edges of the new paths: two leaves of 128 and 129 points (the 256 stride for a
+    # 129-point leaf), the largest dimension with 256-point leaves, the most
+    # subspace iterations, a 5-slab basis (320 columns: a 4-slab and a 1-slab launch)
+    ("two_leaves257_leaf256", lambda: W.gaussian(257, 3, seed=19), 2.0, {"leaf": 256}),
+    ("gauss2000_m16_leaf256_t1", lambda: W.gaussian(2000, 16, seed=20), 1.0, {"leaf": 256}),
+    ("torus2500_power4", lambda: W.noisy_torus(2500, seed=21), 2.0, {"power_iters": 4}),
+    ("torus4000_rank256_p16_power1", lambda: W.noisy_torus(4000, seed=22), 2.0,
+     {"max_rank": 256, "oversample": 16, "power_iters": 1}),
 ]
 
 

@@ -80,6 +80,7 @@ CASES = [
      {"leaf": 256, "max_rank": 64, "oversample": 0, "gmres_restart": 100, "max_gmres": 400}),
     ("gauss3001_leaf256_tstar", lambda: W.gaussian(3001, 3, seed=11), W.gaussian_cutoff_estimate(3001, 3),
      {"leaf": 256}),
+    ("gauss2000_m16_leaf256_t1", lambda: W.gaussian(2000, 16, seed=20), 1.0, {"leaf": 256}),
 ]
 
 
