@@ -7,7 +7,8 @@ handles that size:
   exercised) + FP64 matrix-free GMRES-IR;
 * MAG_HODLR and MAG_HSS: hierarchical preconditioners + the same FP64 GMRES,
   with the top-level rank the benchmark uses (max_rank 512);
-* MAG_HODLR with max_rank 256 and one subspace iteration of the range finder;
+* MAG_HODLR with max_rank 224, oversample 32 and one subspace iteration of the
+  range finder;
 * MAG_HODLR with leaves of 256 points and ranks of at most 64 (several hundred
   GMRES iterations: a weaker preconditioner).
 
@@ -31,10 +32,11 @@ SOLVERS = {
     "fp32_ir": {},
     "hodlr": {"max_rank": 512, "gmres_restart": 100, "max_gmres": 400, "max_outer": 30},
     "hss": {"max_rank": 512, "gmres_restart": 100, "max_gmres": 400, "max_outer": 30},
-    # rank 256 with one subspace iteration of the range finder: the fastest
-    # HODLR setting measured on this cloud
-    "hodlr_rank256_power1": {"solver": "hodlr", "max_rank": 256, "power_iters": 1, "gmres_restart": 100,
-                             "max_gmres": 400, "max_outer": 30},
+    # rank 224 + 32 oversampling with one subspace iteration of the range finder
+    # (widths 256, 192, 192, 128, 128, 128, 64, ...): the fastest HODLR setting
+    # measured on this cloud
+    "hodlr_rank224_p32_power1": {"solver": "hodlr", "max_rank": 224, "oversample": 32, "power_iters": 1,
+                                 "gmres_restart": 100, "max_gmres": 400, "max_outer": 30},
     # the hierarchical setting of the large workload as stated: leaves of 256
     # points, ranks of at most 64 (a weak preconditioner: several hundred GMRES
     # iterations in cycles of 400)
