@@ -34,6 +34,24 @@ def test_weighting_batch_uneven(mag):
         assert infos[b]["argmin_w"] == int(np.argmin(wb))
 
 
+@pytest.mark.parametrize("m", [2, 7, 16, 17, 30])
+def test_weighting_batch_tile_edges(mag, m):
+    # clouds on and around the 128/256 tile edges in one batch, several dimensions
+    # (the batched products' generic paths above 16)
+    sizes = [127, 128, 129, 255, 256, 257, 511, 513, 3]
+    clouds = [W.gaussian(n, m, seed=60 + i) for i, n in enumerate(sizes)]
+    X, offs = W.pack_clouds(clouds)
+    ts = [float(W.gaussian_cutoff_estimate(n, m)) * f for n, f in zip(sizes, [0.3, 1, 3, 0.5, 2, 1, 0.7, 1.5, 1])]
+    w, Ms, infos = mag.weighting_batch(dev(X), offs, ts)
+    w = w.cpu().numpy()
+    for b, (Xb, t) in enumerate(zip(clouds, ts)):
+        wb = w[offs[b]:offs[b + 1]]
+        assert infos[b]["status"] == 0, b
+        assert np.abs(oracle.residual(Xb, t, wb)).max() <= 1e-12, (m, b)
+        ref = oracle.weighting(Xb, t)
+        assert abs(Ms[b] - ref.M) / abs(ref.M) <= 1e-10, (m, b)
+
+
 def test_weighting_batch_t_sweep_shared_rows(mag):
     # several scales of one cloud: items may share rows of X
     Xc = W.gaussian(900, 3, seed=2)
