@@ -73,8 +73,8 @@ enum {
                           * factor's n^3/3 flops on MFMA are the cheaper solve there:   *
                           * 0.33-0.38 s against 0.27-0.45 s for HODLR at n = 49152),    *
                           * MAG_HODLR above (max_rank 512, one subspace iteration,      *
-                          * GMRES(100), up to 400 inner iterations; 0.56-0.78 s against *
-                          * 0.77-0.83 s at n = 65536, 1.1-1.8 s against 2.5-2.6 s at    *
+                          * GMRES(100), up to 400 inner iterations; 0.43-0.65 s against *
+                          * 0.77-0.83 s at n = 65536, 0.8-1.5 s against 2.5-2.6 s at    *
                           * n = 98304, on tori, Gaussian and clustered clouds) when     *
                           * m <= 16; if the HODLR solve does not converge, or m > 16,   *
                           * MAG_FP32_IR when its npad^2 factor fits in 3/4 of the       *

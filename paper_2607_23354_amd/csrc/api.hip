@@ -767,9 +767,9 @@ int solve_hss(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double 
 // MAG_AUTO takes the HODLR preconditioner above this size.  Measured on the
 // MI355X, whole solves (noisy torus at t = 0.5, 2, 8; Gaussian cloud at its
 // cutoff scale; mixture of five Gaussians at t = 30, 100): n = 49152: dense
-// FP32 factor + refinement 331-377 ms, HODLR 272-455 ms; n = 65536: 767-828 ms
-// against 558-784 ms (HODLR with max_rank 512 and one subspace iteration);
-// n = 98304: 2.47-2.62 s against 1.12-1.76 s.  The clustered clouds compress
+// FP32 factor + refinement 330-376 ms, HODLR 272-455 ms; n = 65536: 767-828 ms
+// against 425-647 ms (HODLR with max_rank 512 and one subspace iteration);
+// n = 98304: 2.47-2.62 s against 0.82-1.45 s.  The clustered clouds compress
 // worst and put the crossover near the upper sizes; without the subspace
 // iteration the HODLR solve of the mixture at t = 30 stalls at n = 131072.
 constexpr int64_t kAutoHodlrMinN = 49152;
