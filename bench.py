@@ -5,9 +5,10 @@ One step = one complete weighting solve (tile generation, FP32 MFMA Cholesky,
 FP64 GMRES iterative refinement to ||1 - Z w||_inf <= 1e-12, magnitude) of a
 seeded Gaussian cloud x ~ N(0, I_3), n = 32768, at the scale
 t = 2^(7/8) m^(-2/3) n^(1/4) ~ 11.86 (the Gaussian cutoff law, Appendix C.2),
-with the coordinates already resident in HBM.  The FP64 dense comparator
-(FP64 Z + rocSOLVER dpotrf/dpotrs) is timed on the same GPU beside it, and
-the CPU oracle is timed on a bounded sample on the host cores.
+with the coordinates already resident in HBM.  Two FP64 dense comparators are
+timed on the same GPU beside it: FP64 Z + rocSOLVER dpotrf/dpotrs, and FP64 Z +
+this library's FP64 MFMA blocked Cholesky and FP64 substitution.  The CPU
+oracle is timed on a bounded sample on the host cores.
 
 Prints one JSON line (rank 0).
 """
@@ -209,6 +210,43 @@ def main():
         except Exception as e:  # report, do not hide
             dense = {"error": repr(e)}
 
+    # this library's FP64 MFMA blocked Cholesky + FP64 substitution on the same
+    # cloud: the plain FP64 dense solve on the matrix cores
+    chol64 = None
+    if not args.no_dense:
+        try:
+            step(profile=True, solver="fp64_chol")
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            cinfos = []
+            for _ in range(args.dense_steps):
+                cinfos.append(step(profile=True, solver="fp64_chol").info)
+            torch.cuda.synchronize()
+            c1 = time.perf_counter()
+            cms = (c1 - c0) * 1e3 / args.dense_steps
+            ci = cinfos[-1]
+            upd_ms = sum(i["ms_update"] for i in cinfos)
+            upd_fl = sum(i["flop_update"] for i in cinfos)
+            syrk64 = upd_fl / (upd_ms * 1e-3) / 1e12 if upd_ms > 0 else None
+            w64 = w.cpu().numpy()
+            chol64 = {
+                "ms_per_solve": cms,
+                "ms_tilegen": ci["ms_tilegen"],
+                "ms_factor": ci["ms_factor"],
+                "ms_substitution": ci["ms_refine"],
+                "factor_frac_fp64_peak": factor_flops / (ci["ms_factor"] * 1e-3) / 1e12 / FP64_MFMA_PEAK_TFLOPS,
+                "syrk64_tflops": syrk64,
+                "syrk64_frac_fp64_peak": (syrk64 / FP64_MFMA_PEAK_TFLOPS) if syrk64 else None,
+                "syrk64_launches": sum(i["n_update"] for i in cinfos) // len(cinfos),
+                "resid_inf_device": ci["resid_inf"],
+                "resid_inf_sampled_oracle": float(np.abs(oracle.residual(X, t, w64, rows)).max()),
+                "magnitude": ci["magnitude"],
+                "relerr_M_vs_fp32_ir": abs(ci["magnitude"] - last["magnitude"]) / abs(ci["magnitude"]),
+            }
+            print(f"[bench] fp64_chol {cms:.2f} ms/solve", file=sys.stderr, flush=True)
+        except Exception as e:  # report, do not hide
+            chol64 = {"error": repr(e)}
+
     # error of w and of M = 1^T w against the oracle at every scale of the metric
     # cloud (expected values written by tests/golden/make_full_size.py from the
     # oracle alone; one untimed solve per scale)
@@ -305,6 +343,9 @@ def main():
                   "min_w": last["min_w"], "shifted": last["shifted"]},
         "fp64_dense": dense,
         "speedup_vs_fp64_dense": (dense["ms_per_solve"] / ms_per_step) if dense and "ms_per_solve" in dense else None,
+        "fp64_mfma_chol": chol64,
+        "speedup_vs_fp64_mfma_chol": (chol64["ms_per_solve"] / ms_per_step) if chol64 and "ms_per_solve" in chol64
+        else None,
         "speedup_vs_fp64_peak_floor": (factor_flops / (FP64_MFMA_PEAK_TFLOPS * 1e12) * 1e3) / ms_per_step,
         "per_scale_vs_oracle": scales,
         "eig_extremes": eig,

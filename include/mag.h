@@ -85,6 +85,12 @@ enum {
                           * points reordered by recursive coordinate bisection, leaf    *
                           * blocks exact, sibling blocks Z(I,J) ~ U_I V_J^T sampled     *
                           * with a Gaussian test matrix; m <= 16                        */
+    MAG_FP64_CHOL = 5,   /* FP64 Z in HBM + this library's FP64 MFMA blocked Cholesky    *
+                          * (64-column diagonal blocks, 256-column panels in pairs, the  *
+                          * trailing updates on v_mfma_f64_16x16x4) + the sync-free     *
+                          * substitution with that factor: the plain FP64 dense solve    *
+                          * on the matrix cores (Sec. 3.2's direct method), no          *
+                          * refinement; the dense comparator beside MAG_FP64_DENSE      */
     MAG_HSS = 4          /* HSS preconditioner with nested bases, factored by ULV, + FP64 *
                           * GMRES (Sec. 3.2's hierarchical solver): the same tree; each *
                           * node's basis spans its whole off-diagonal block row (one    *
@@ -429,6 +435,18 @@ int mag_factor32(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
  * r, z: device, n. */
 int mag_prec_apply(mag_ctx *ctx, const float *L, const float *dinv, int64_t n,
                    const double *r, double *z);
+
+/* FP64 Cholesky factor of Z (the MAG_FP64_CHOL factor) into L (device, npad x
+ * npad FP64 column-major: L in the lower triangle and L^T in the upper one,
+ * identity padding) and the inverses of its 64 x 64 diagonal blocks into dinv
+ * (device, npad/64 blocks of 64 x 64 column-major).  *breakdown (HOST, may be
+ * NULL) receives 0, or 1 + the index of the first non-positive pivot. */
+int mag_factor64(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
+                 double *L, double *dinv, int32_t *breakdown);
+
+/* z = (L L^T)^{-1} r with the factor from mag_factor64; r, z: device, n. */
+int mag_chol64_solve(mag_ctx *ctx, const double *L, const double *dinv, int64_t n,
+                     const double *r, double *z);
 
 /* y = (D o Z) v in FP64, matrix-free (device, n); any m. */
 int mag_dzmatvec(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,

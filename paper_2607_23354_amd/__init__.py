@@ -20,12 +20,13 @@ from . import _lib
 from ._lib import MagError, MagInfo, MagOpts, MagTplusInfo, MagTplusOpts  # noqa: F401
 
 __all__ = ["Context", "weighting", "magnitude", "dmin", "zmatvec", "residual", "tile32",
-           "factor32", "prec_apply", "padded_size", "tplus", "dwdt", "dzmatvec",
+           "factor32", "prec_apply", "factor64", "chol64_solve", "padded_size", "tplus", "dwdt", "dzmatvec",
            "MagnitudeFn", "weighting_and_magnitude", "weighting_batch", "tplus_batch",
            "eig_extremes", "weighting_zero", "MagError", "SOLVERS"]
 
 SOLVERS = {"auto": _lib.MAG_AUTO, "fp64_dense": _lib.MAG_FP64_DENSE,
-           "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR, "hss": _lib.MAG_HSS}
+           "fp32_ir": _lib.MAG_FP32_IR, "hodlr": _lib.MAG_HODLR, "hss": _lib.MAG_HSS,
+           "fp64_chol": _lib.MAG_FP64_CHOL}
 SOLVER_NAMES = {v: k for k, v in SOLVERS.items()}
 DIAG_BACKWARD = 1
 DIAG_COND = 2
@@ -264,6 +265,32 @@ def prec_apply(L: torch.Tensor, dinv: torch.Tensor, n: int, r: torch.Tensor, *,
     r = r.contiguous()
     z = torch.empty(n, dtype=torch.float64, device=r.device)
     _lib.check(c.lib.mag_prec_apply(c.handle, _ptr(L), _ptr(dinv), n, _ptr(r), _ptr(z)), "mag_prec_apply")
+    return z
+
+
+def factor64(X: torch.Tensor, t: float, *, ctx: Context | None = None):
+    """FP64 Cholesky factor of the fp64_chol solver (column-major npad x npad
+    buffer: L in the lower triangle, L^T in the upper one) and the inverses of
+    its 64-diagonal blocks."""
+    X = _points(X)
+    n, m = X.shape
+    c = _ctx(ctx, X)
+    npad = padded_size(n)
+    L = torch.zeros((npad, npad), dtype=torch.float64, device=X.device)
+    dinv = torch.zeros((npad // 64, 64, 64), dtype=torch.float64, device=X.device)
+    bd = ctypes.c_int32()
+    _lib.check(c.lib.mag_factor64(c.handle, _ptr(X), n, m, float(t), _ptr(L), _ptr(dinv), ctypes.byref(bd)),
+               "mag_factor64")
+    return L, dinv, int(bd.value)
+
+
+def chol64_solve(L: torch.Tensor, dinv: torch.Tensor, n: int, r: torch.Tensor, *,
+                 ctx: Context | None = None) -> torch.Tensor:
+    """z = (L L^T)^{-1} r with the factor of factor64."""
+    c = _ctx(ctx, r)
+    r = r.contiguous()
+    z = torch.empty(n, dtype=torch.float64, device=r.device)
+    _lib.check(c.lib.mag_chol64_solve(c.handle, _ptr(L), _ptr(dinv), n, _ptr(r), _ptr(z)), "mag_chol64_solve")
     return z
 
 

@@ -25,6 +25,7 @@ MAG_FP64_DENSE = 1
 MAG_FP32_IR = 2
 MAG_HODLR = 3
 MAG_HSS = 4
+MAG_FP64_CHOL = 5
 
 
 class MagOpts(ctypes.Structure):
@@ -164,6 +165,8 @@ SIGNATURES = {
     "mag_tile32": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp]),
     "mag_factor32": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _d, _vp, _vp, ctypes.POINTER(_i32)]),
     "mag_prec_apply": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "mag_factor64": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp, ctypes.POINTER(_i32)]),
+    "mag_chol64_solve": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "mag_dzmatvec": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp]),
     "mag_residual_noalloc": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, _vp, ctypes.POINTER(_d)]),
     "mag_residual_noalloc_max_doubles": (ctypes.c_size_t, []),

@@ -638,6 +638,94 @@ int solve_fp64_dense(mag_ctx *ctx, const double *X, int64_t n, int m, double t, 
 }
 
 
+// FP64 Z in HBM in the padded layout + this library's FP64 MFMA blocked
+// Cholesky + the sync-free substitution with the FP64 factor: the plain dense
+// FP64 solve on the matrix cores (no refinement).
+int solve_fp64_chol(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double *w, const mag_opts &o,
+                    mag_info *info)
+{
+    hipStream_t s = ctx->stream;
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure_common(ctx, n, 1));
+    CHK(ensure(ctx, ctx->factor, sizeof(double) * (size_t)npad * (size_t)npad));
+    CHK(ensure(ctx, ctx->dinv, sizeof(double) * (size_t)npad * 64));
+    CHK(ensure(ctx, ctx->vecs, sizeof(double) * ((size_t)npad * 3 + 256)));
+    double *A = (double *)ctx->factor.p;
+    double *dinv = (double *)ctx->dinv.p;
+    double *rhs = (double *)ctx->vecs.p;
+    double *ytmp = rhs + npad;
+    double *z = ytmp + npad;
+    double *dsc = z + npad;
+    int *ints = (int *)ctx->ints.p;
+    int *status = ints + kIntStatus;
+    double *partial = (double *)ctx->partial.p;
+    double *hs = ctx->host_scalars;
+    FactorTimer ft;
+    Timer tm;
+    tm.start(o.profile != 0, s);
+    tm.mark(0);
+    launch_fill_ints(s, status, 8, 0);
+    launch_tilegen64p(s, X, n, m, t, A, npad, status);
+    tm.mark(1);
+    chol64_factor(s, A, npad, n, dinv, status, o.profile ? &ft : nullptr);
+    tm.mark(2);
+    launch_affine_ones(s, nullptr, 1.0, rhs, n, npad);
+    launch_chol64_solve(s, A, npad, dinv, rhs, ytmp, z, ints + kIntCounters, status);
+    HIPCHK(hipMemcpyAsync(w, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    tm.mark(3);
+    HIPCHK(hipMemcpyAsync(hs + 16, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int rc = MAG_OK;
+    {
+        const int *st = (const int *)(hs + 16);
+        if (st[kStSpinTimeout]) rc = MAG_EINTERNAL;
+        else if (st[kStDuplicate] || st[kStBreakdown]) rc = MAG_ENOTPD;
+    }
+    if (rc == MAG_OK && info) {
+        // diagnostics: residual (FP64 matrix-free) and magnitude
+        launch_zmv(s, X, n, m, t, w, z, nullptr, 1, partial, dsc + 4);
+        HIPCHK(hipMemcpyAsync(hs + 5, dsc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+        launch_sum_min(s, w, n, partial, dsc);
+        HIPCHK(hipMemcpyAsync(hs + 2, dsc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        info->magnitude = hs[2];
+        info->min_w = hs[3];
+        info->argmin_w = (int64_t)hs[4];
+        info->resid_inf = hs[5];
+        info->outer_iters = 0;
+        info->gmres_iters = 0;
+        if (o.profile) {
+            info->ms_tilegen = tm.ms(0, 1);
+            info->ms_factor = tm.ms(1, 2);
+            info->ms_refine = tm.ms(2, 3);
+            info->ms_total = tm.ms(0, 3);
+            double msu = 0.0, fl = 0.0;
+            for (size_t q = 0; q + 1 < ft.used; q += 2) {
+                float f = 0.f;
+                hipEventElapsedTime(&f, ft.ev[q], ft.ev[q + 1]);
+                msu += f;
+                fl += ft.flops[q / 2];
+            }
+            info->ms_update = msu;
+            info->flop_update = fl;
+            info->n_update = (int32_t)(ft.used / 2);
+        }
+        info->solver = MAG_FP64_CHOL;
+        if (o.diag & MAG_DIAG_BACKWARD) CHK(diag_backward(ctx, X, n, m, t, w, info->resid_inf, info->backward_err));
+        if (o.diag & MAG_DIAG_COND) {
+            const SolveOp inv = [&](const double *in, double *out) -> int {
+                // in, out: npad vectors zero in the padding
+                launch_chol64_solve(s, A, npad, dinv, in, ytmp, out, ints + kIntCounters, status);
+                return MAG_OK;
+            };
+            CHK(diag_cond(ctx, X, n, m, t, inv, info->cond_est));
+        }
+    }
+    for (auto e : ft.ev) hipEventDestroy(e);
+    return rc;
+}
+
+
 // HODLR preconditioner (hodlr.hip) + FP64 GMRES-IR with matrix-free Z v.
 int solve_hodlr(mag_ctx *ctx, const double *X, int64_t n, int m, double t, double *w,
                 const mag_opts &o, mag_info *info)
@@ -1356,6 +1444,7 @@ int mag_weighting(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, d
     } else if (rc == MAG_OK) {
         switch (o.solver) {
         case MAG_FP64_DENSE: rc = solve_fp64_dense(c, X, n, m, t, w, o, info); break;
+        case MAG_FP64_CHOL: rc = solve_fp64_chol(c, X, n, m, t, w, o, info); break;
         case MAG_HODLR: rc = solve_hodlr(c, X, n, m, t, w, o, info); break;
         case MAG_HSS: rc = solve_hss(c, X, n, m, t, w, o, info); break;
         case MAG_AUTO:
@@ -1485,6 +1574,45 @@ int mag_prec_apply(mag_ctx *c, const float *L, const float *dinv, int64_t n, con
     launch_fill(c->stream, rb, npad, 0.0);
     HIPCHK(hipMemcpyAsync(rb, r, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     launch_prec_apply(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints);
+    HIPCHK(hipMemcpyAsync(z, zb, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->host_scalars, ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (((const int *)c->host_scalars)[kStSpinTimeout]) return MAG_EINTERNAL;
+    return MAG_OK;
+}
+
+int mag_factor64(mag_ctx *c, const double *X, int64_t n, int32_t m, double t, double *L, double *dinv,
+                 int32_t *breakdown)
+{
+    if (!c || !L || !dinv || !valid_args(X, n, m, t)) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    CHK(ensure(c, c->ints, sizeof(int) * kIntsTotal));
+    const int64_t npad = round_up(n, kPad);
+    int *status = (int *)c->ints.p;
+    launch_fill_ints(c->stream, status, 8, 0);
+    launch_tilegen64p(c->stream, X, n, m, t, L, npad, nullptr);
+    chol64_factor(c->stream, L, npad, n, dinv, status, nullptr);
+    HIPCHK(hipMemcpyAsync(c->host_scalars, status, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (breakdown) *breakdown = ((const int *)c->host_scalars)[kStBreakdown];
+    return MAG_OK;
+}
+
+int mag_chol64_solve(mag_ctx *c, const double *L, const double *dinv, int64_t n, const double *r, double *z)
+{
+    if (!c || !L || !dinv || !r || !z || n < 1) return MAG_EINVAL;
+    HIPCHK(hipSetDevice(c->device));
+    CHK(ensure(c, c->ints, sizeof(int) * kIntsTotal));
+    const int64_t npad = round_up(n, kPad);
+    CHK(ensure(c, c->vecs, sizeof(double) * ((size_t)npad * 3 + 256)));
+    double *rb = (double *)c->vecs.p;
+    double *yt = rb + npad;
+    double *zb = yt + npad;
+    int *ints = (int *)c->ints.p;
+    launch_fill_ints(c->stream, ints, 8, 0);
+    launch_fill(c->stream, rb, npad, 0.0);
+    HIPCHK(hipMemcpyAsync(rb, r, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    launch_chol64_solve(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints);
     HIPCHK(hipMemcpyAsync(z, zb, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->host_scalars, ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -345,6 +345,10 @@ void launch_gradx(hipStream_t s, const double *X, int64_t n, int m, double t, co
 void launch_tilegen32(hipStream_t s, const double *X, int64_t n, int m, double t,
                       float *A, int64_t npad, float shift, int *status = nullptr, int kernel = kKernExp);
 void launch_tilegen64(hipStream_t s, const double *X, int64_t n, int m, double t, double *A);
+// FP64 Z in the padded layout (npad x npad, lower triangle and the 128-diagonal
+// tiles, identity padding); status[kStDuplicate] as launch_tilegen32.
+void launch_tilegen64p(hipStream_t s, const double *X, int64_t n, int m, double t, double *A, int64_t npad,
+                       int *status);
 // Writes min squared distance partials; returns number of partials in *np.
 void launch_dmin2(hipStream_t s, const double *X, int64_t n, int m, double *partial,
                   int64_t *np, double *out_min2);
@@ -361,6 +365,24 @@ void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_
 // C (N x N, lower 128-tiles only) -= P P^T with P N x K; N multiple of 128.
 void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                        int64_t N, int64_t K);
+
+// gemm64.hip: the FP64 factor's contractions, C (M x N) -= P Q^T (kGemmSub) or
+// C = P Q^T with C^T into CT (kGemmSetT); operands column-major as for
+// launch_gemm_nt.  tile 128: M, N multiples of 128, kGemmSub only; tile 64: M, N
+// multiples of 64.  K a multiple of 16; operand pointers 16-byte aligned and
+// leading dimensions even.
+void launch_gemm64(hipStream_t s, int tile, double *C, int64_t ldc, const double *P, int64_t ldp, const double *Q,
+                   int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode, double *CT);
+// C (N x N, lower 128-tiles only) -= P P^T with P N x K; N multiple of 128.
+void launch_syrk64_lower(hipStream_t s, double *C, int64_t ldc, const double *P, int64_t ldp, int64_t N, int64_t K);
+// potrf64.hip: factor the 64 x 64 diagonal block at (k0, k0) of the FP64 A in
+// place (L below and on the diagonal, L^T above) and write its inverse to Linv
+// (64 x 64 column-major).  Breakdown -> status.
+void launch_potrf64(hipStream_t s, double *A, int64_t ld, int64_t k0, double *Linv, int *status);
+// chol64.hip: FP64 factor of the padded npad x npad A (layout of the FP32
+// factor) in place; dinv receives the inverses of the 64-diagonal blocks
+// (npad / 64 blocks of 64 x 64).
+void chol64_factor(hipStream_t s, double *A, int64_t npad, int64_t n, double *dinv, int *status, FactorTimer *timer);
 
 // potrf.hip: factor the 128 x 128 diagonal block at (k0, k0) of A in place and
 // write its inverse to Linv (128 x 128 column-major).  Breakdown -> status.
@@ -391,6 +413,9 @@ int noalloc_setup(int device);
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
                        const double *r, double *y_tmp, double *z, int *counters, int *status);
 size_t prec_counter_ints();
+// z = L^{-T} L^{-1} r with the FP64 factor of chol64_factor (64-blocks).
+void launch_chol64_solve(hipStream_t s, const double *L, int64_t npad, const double *dinv, const double *r,
+                         double *y_tmp, double *z, int *counters, int *status);
 
 // blas1.hip: deterministic FP64 vector kernels (length npad, two-pass).
 void launch_fill(hipStream_t s, double *x, int64_t len, double v);

@@ -154,6 +154,39 @@ k_tilegen64(const double *__restrict__ X, int64_t n, int m, double t, double *__
     }
 }
 
+// FP64 Z into the padded layout of the FP32 factor (npad x npad column-major,
+// lower triangle and the 128 x 128 diagonal tiles, identity padding), for the
+// FP64 blocked factor; the entries are those of k_tilegen64.
+__global__ void __launch_bounds__(kThreads)
+k_tilegen64p(const double *__restrict__ X, int64_t n, int m, double t, double *__restrict__ A, int64_t npad,
+             int *__restrict__ status)
+{
+    __shared__ double Sr[kLC * kRows];
+    __shared__ double Sc[kLC * kCols];
+    int64_t I, Jc;
+    lower_block(blockIdx.x, I, Jc);
+    const int64_t row0 = I * kRows, col0 = Jc * kCols;
+    double s[kPerThread];
+    block_sqdist(s, X, n, m, row0, col0, Sr, Sc);
+    const int r = threadIdx.x & (kRows - 1);
+    const int h = threadIdx.x >> 7;
+    const int64_t j = row0 + r;
+#pragma unroll
+    for (int c = 0; c < kPerThread; ++c) {
+        const int64_t k = col0 + 2 * c + h;
+        double v;
+        if (j == k)
+            v = 1.0;
+        else if (j >= n || k >= n)
+            v = 0.0;
+        else {
+            if (status && s[c] == 0.0) status[kStDuplicate] = 1;  // Z singular
+            v = exp(-(t * sqrt(s[c])));
+        }
+        A[k * npad + j] = v;
+    }
+}
+
 // Per-block minimum of d_jk^2 over j > k inside the block.
 __global__ void __launch_bounds__(kThreads)
 k_dmin2_partial(const double *__restrict__ X, int64_t n, int m, double *__restrict__ partial)
@@ -233,6 +266,13 @@ void launch_tilegen64(hipStream_t s, const double *X, int64_t n, int m, double t
 {
     hipLaunchKernelGGL(k_tilegen64, dim3((unsigned)lower_blocks(n)), dim3(kThreads), 0, s, X, n, m,
                        t, A);
+}
+
+void launch_tilegen64p(hipStream_t s, const double *X, int64_t n, int m, double t, double *A, int64_t npad,
+                       int *status)
+{
+    hipLaunchKernelGGL(k_tilegen64p, dim3((unsigned)lower_blocks(npad)), dim3(kThreads), 0, s, X, n, m, t, A, npad,
+                       status);
 }
 
 void launch_dmin2(hipStream_t s, const double *X, int64_t n, int m, double *partial, int64_t *np,

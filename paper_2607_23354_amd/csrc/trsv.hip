@@ -1,11 +1,14 @@
-// trsv.hip -- preconditioner apply z = L^{-T} L^{-1} r of the refinement.
+// trsv.hip -- preconditioner apply z = L^{-T} L^{-1} r of the refinement, and
+// the substitution of the FP64 dense factor.
 //
 // L is the FP32 Cholesky factor (column-major, leading dimension npad, lower
 // triangle), r and z are FP64 and all arithmetic is FP64.  The diagonal
 // 128 x 128 blocks are applied through their explicit inverses (FP32, from the
-// factorisation), so a block step is a small matrix-vector product.
+// factorisation), so a block step is a small matrix-vector product.  The same
+// kernel, instantiated for the FP64 factor, works on 64 x 64 blocks (whose
+// FP64 inverses fit LDS).  The figures below are those of the FP32 factor.
 //
-// Each triangular solve is ONE launch with one workgroup per 128-row block
+// Each triangular solve is ONE launch with one workgroup per two blocks
 // and no host round trips ("sync-free" substitution):
 //   * a workgroup owns a band of two consecutive blocks and takes a ticket
 //     from an atomic counter; ticket order is the band order of the
@@ -42,7 +45,6 @@
 namespace mag {
 namespace {
 
-constexpr int BS = 128;
 constexpr long kSpinLimit = 1L << 26;
 constexpr int kSlot = 64;  // ints between the two tickets (256 bytes)
 
@@ -65,23 +67,26 @@ __device__ inline void st_entry(double *x, int64_t i, double v)
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Wave 0 (lanes 0..63): wait until the entries of block j0 (and j1 if two) of
-// x are set, and copy them to xs[0] (xs[1]).  Bounded: on exhaustion the
+// Wave 0 (lanes 0..63): wait until the BS entries of block j0 (and j1 if two)
+// of x are set, and copy them to xs[0] (xs[1]).  Bounded: on exhaustion the
 // status word is set and whatever was read is used.
+template <int BS>
 __device__ inline void wait_blocks(const double *x, int64_t j0, int64_t j1, bool two, double (&xs)[2][BS],
                                    int *status)
 {
+    static_assert(BS == 64 || BS == 128, "one or two entries per lane and block");
+    constexpr bool E2 = BS == 128;
     const int lane = threadIdx.x;
-    uint64_t a0, a1, c0 = 0, c1 = 0;
+    uint64_t a0, a1 = 0, c0 = 0, c1 = 0;
     long spins = 0;
     for (;;) {
         a0 = ld_entry(x, j0 * BS + lane);
-        a1 = ld_entry(x, j0 * BS + lane + 64);
+        if (E2) a1 = ld_entry(x, j0 * BS + lane + 64);
         if (two) {
             c0 = ld_entry(x, j1 * BS + lane);
-            c1 = ld_entry(x, j1 * BS + lane + 64);
+            if (E2) c1 = ld_entry(x, j1 * BS + lane + 64);
         }
-        const bool miss = a0 == kUnset || a1 == kUnset || (two && (c0 == kUnset || c1 == kUnset));
+        const bool miss = a0 == kUnset || (E2 && a1 == kUnset) || (two && (c0 == kUnset || (E2 && c1 == kUnset)));
         if (__ballot(miss) == 0) break;
         if (++spins > kSpinLimit) {
             if (lane == 0) status[kStSpinTimeout] = 1;
@@ -90,32 +95,62 @@ __device__ inline void wait_blocks(const double *x, int64_t j0, int64_t j1, bool
         __builtin_amdgcn_s_sleep(1);
     }
     xs[0][lane] = __builtin_bit_cast(double, a0);
-    xs[0][lane + 64] = __builtin_bit_cast(double, a1);
+    if (E2) xs[0][lane + 64] = __builtin_bit_cast(double, a1);
     if (two) {
         xs[1][lane] = __builtin_bit_cast(double, c0);
-        xs[1][lane + 64] = __builtin_bit_cast(double, c1);
+        if (E2) xs[1][lane + 64] = __builtin_bit_cast(double, c1);
     }
+}
+
+// Four consecutive factor entries (one row group of a tile column).
+template <typename T>
+struct Quad {
+    T v[4];
+};
+__device__ inline void load_quad(const float *p, Quad<float> &q)
+{
+    const float4 f = *reinterpret_cast<const float4 *>(p);
+    q.v[0] = f.x;
+    q.v[1] = f.y;
+    q.v[2] = f.z;
+    q.v[3] = f.w;
+}
+__device__ inline void load_quad(const double *p, Quad<double> &q)
+{
+    const double2 a = *reinterpret_cast<const double2 *>(p);
+    const double2 b = *reinterpret_cast<const double2 *>(p + 2);
+    q.v[0] = a.x;
+    q.v[1] = a.y;
+    q.v[2] = b.x;
+    q.v[3] = b.y;
 }
 
 // One triangular solve.  Forward (BWD = false): y = L^{-1} r, block b pulls
 // tiles L(b, j), j < b, from the lower triangle.  Backward (BWD = true):
 // z = L^{-T} y, block b pulls tiles L^T(b, j), j > b, from the upper
-// triangle, where the factorisation stored L^T.  Both read a 128-row band of
-// 512-byte column segments per step, the same HBM access pattern.
+// triangle, where the factorisation stored L^T.  Both read a BS-row band of
+// column segments per step, the same HBM access pattern.
 //
-// A workgroup owns two consecutive blocks (a 256-row band): it streams both
+// A workgroup owns two consecutive blocks (a 2 BS-row band): it streams both
 // blocks' tiles against every finished block outside the band, then solves
 // the first block, applies the band's inner tile and solves the second, so
-// the dependency chain crosses workgroups once per 256 rows.
-template <bool BWD>
-__device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t ld,
-                                          const float *__restrict__ dinv,
+// the dependency chain crosses workgroups once per 2 BS rows.
+// T, BS: the FP32 factor with 128-blocks, or the FP64 factor with 64-blocks.
+template <bool BWD, typename T, int BS>
+__device__ __forceinline__ void trsv_body(const T *__restrict__ L, int64_t ld,
+                                          const T *__restrict__ dinv,
                                           const double *__restrict__ rhs, double *__restrict__ x,
                                           int *counters, int nblk, int *status)
 {
-    __shared__ float Dl[2][BS * (BS + 1)];  // Dinv of the two blocks, row-major, padded stride
+    constexpr int RG = BS / 4;      // row groups of a tile (4 rows each)
+    constexpr int CG = 256 / RG;    // column groups
+    constexpr int CPG = BS / CG;    // columns per group
+    constexpr int H = 256 / BS;     // parts of a diagonal-block row's product
+    constexpr int HC = BS / H;      // columns per part
+    static_assert(RG * CG == 256 && CG * CPG == BS && H <= CG, "tile mapping");
+    __shared__ T Dl[2][BS * (BS + 1)];  // Dinv of the two blocks, row-major, padded stride
     __shared__ double xs[2][BS];
-    __shared__ double part[8][BS];          // per column group partial sums of a block's rows
+    __shared__ double part[CG][BS];     // per column group partial sums of a block's rows
     __shared__ int s_band;
     const int tid = threadIdx.x;
     const int nband = nblk / 2;
@@ -129,27 +164,28 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     const int b0 = BWD ? 2 * band + 1 : 2 * band;
     const int b1 = BWD ? 2 * band : 2 * band + 1;
     // tile products: thread (rg, cg) owns rows 4 rg .. 4 rg + 3 and columns
-    // 16 cg .. 16 cg + 15 of a 128 x 128 tile (one float4 per column)
-    const int rg = tid & 31, cg = tid >> 5;
-    // block solves: thread (h, row) takes half h of row's dot product
-    const int row = tid & (BS - 1);
-    const int h = tid >> 7;
+    // CPG cg .. CPG cg + CPG - 1 of a BS x BS tile (four entries per column)
+    const int rg = tid % RG, cg = tid / RG;
+    // block solves: thread (h, row) takes part h of row's dot product
+    const int row = tid % BS;
+    const int h = tid / BS;
 
     // tile (b, j): element (r, c) at L[(j BS + c) ld + b BS + r] -- forward L(b, j)
     // from the lower triangle, backward L^T(b, j) from the upper triangle
-    auto load = [&](int b, int j, float4 (&t)[16]) {
-        const float *p = L + ((int64_t)j * BS + 16 * cg) * ld + (int64_t)b * BS + 4 * rg;
+    using Tile = Quad<T>[CPG];
+    auto load = [&](int b, int j, Tile &t) {
+        const T *p = L + ((int64_t)j * BS + CPG * cg) * ld + (int64_t)b * BS + 4 * rg;
 #pragma unroll
-        for (int c = 0; c < 16; ++c) t[c] = *reinterpret_cast<const float4 *>(p + (int64_t)c * ld);
+        for (int c = 0; c < CPG; ++c) load_quad(p + (int64_t)c * ld, t[c]);
     };
-    auto gemv = [&](const float4 (&t)[16], const double *xv, double (&acc)[4]) {
+    auto gemv = [&](const Tile &t, const double *xv, double (&acc)[4]) {
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const double v = xv[16 * cg + c];
-            acc[0] += (double)t[c].x * v;
-            acc[1] += (double)t[c].y * v;
-            acc[2] += (double)t[c].z * v;
-            acc[3] += (double)t[c].w * v;
+        for (int c = 0; c < CPG; ++c) {
+            const double v = xv[CPG * cg + c];
+            acc[0] += (double)t[c].v[0] * v;
+            acc[1] += (double)t[c].v[1] * v;
+            acc[2] += (double)t[c].v[2] * v;
+            acc[3] += (double)t[c].v[3] * v;
         }
     };
 
@@ -160,14 +196,14 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
         rhs0 = rhs[(int64_t)b0 * BS + tid];
         rhs1 = rhs[(int64_t)b1 * BS + tid];
     }
-    float4 ti[16];
+    Tile ti;
     load(b1, b0, ti);
 
     // Dinv (column-major in memory) into row-major padded LDS
     for (int q = 0; q < 2; ++q) {
-        const float *src = dinv + (int64_t)(q == 0 ? b0 : b1) * BS * BS;
+        const T *src = dinv + (int64_t)(q == 0 ? b0 : b1) * BS * BS;
         for (int e = tid; e < BS * BS; e += 256) {
-            const int rr = e & (BS - 1), cc = e >> 7;
+            const int rr = e % BS, cc = e / BS;
             Dl[q][rr * (BS + 1) + cc] = src[e];
         }
     }
@@ -175,12 +211,12 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     // blocks outside the band, in the order they finish, two at a time.  A
     // pair's tiles are fetched before its wait, the next pair's right after it.
     const int nsteps = BWD ? (nblk - 2 - 2 * band) : 2 * band;
-    float4 ta0[16], ta1[16], tb0[16], tb1[16];
+    Tile ta0, ta1, tb0, tb1;
     auto jof = [&](int st) { return BWD ? (nblk - 1 - st) : st; };
     // steps st and st + 1 (if any): wave 0 waits for both solution blocks (a
     // band writes its two blocks moments apart) and copies them to LDS
     auto consume2 = [&](int st, bool two) {
-        if (tid < 64) wait_blocks(x, jof(st), two ? jof(st + 1) : 0, two, xs, status);
+        if (tid < 64) wait_blocks<BS>(x, jof(st), two ? jof(st + 1) : 0, two, xs, status);
         __syncthreads();
         gemv(ta0, xs[0], acc0);
         gemv(ta1, xs[0], acc1);
@@ -221,25 +257,30 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     if (tid < BS) {
         double sacc = 0.0;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) sacc += part[g][tid];
+        for (int g = 0; g < CG; ++g) sacc += part[g][tid];
         xs[0][tid] = rhs0 - sacc;
     }
     __syncthreads();
     double v = 0.0;
 #pragma unroll 16
-    for (int c = 0; c < 64; ++c) {
-        const int cc = h * 64 + c;
-        const float d = BWD ? Dl[0][cc * (BS + 1) + row] : Dl[0][row * (BS + 1) + cc];
+    for (int c = 0; c < HC; ++c) {
+        const int cc = h * HC + c;
+        const T d = BWD ? Dl[0][cc * (BS + 1) + row] : Dl[0][row * (BS + 1) + cc];
         v += (double)d * xs[0][cc];
     }
     part[h][row] = v;
     __syncthreads();
-    if (tid < BS) xs[1][tid] = part[0][tid] + part[1][tid];
+    if (tid < BS) {
+        double sv = part[0][tid];
+#pragma unroll
+        for (int g = 1; g < H; ++g) sv += part[g][tid];
+        xs[1][tid] = sv;
+    }
     __syncthreads();
     // wave 0 writes the band's solution entries (each write releases that entry)
     if (tid < 64) {
-        st_entry(x, (int64_t)b0 * BS + tid, xs[1][tid]);
-        st_entry(x, (int64_t)b0 * BS + tid + 64, xs[1][tid + 64]);
+#pragma unroll
+        for (int e = 0; e < BS / 64; ++e) st_entry(x, (int64_t)b0 * BS + tid + 64 * e, xs[1][tid + 64 * e]);
     }
     // second block: acc1 += L(b1, b0) x_b0, then x_b1 = Dinv_b1 (rhs_b1 - acc1)
     gemv(ti, xs[1], acc1);
@@ -249,32 +290,38 @@ __device__ __forceinline__ void trsv_body(const float *__restrict__ L, int64_t l
     if (tid < BS) {
         double sacc = 0.0;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) sacc += part[g][tid];
+        for (int g = 0; g < CG; ++g) sacc += part[g][tid];
         xs[0][tid] = rhs1 - sacc;
     }
     __syncthreads();
     v = 0.0;
 #pragma unroll 16
-    for (int c = 0; c < 64; ++c) {
-        const int cc = h * 64 + c;
-        const float d = BWD ? Dl[1][cc * (BS + 1) + row] : Dl[1][row * (BS + 1) + cc];
+    for (int c = 0; c < HC; ++c) {
+        const int cc = h * HC + c;
+        const T d = BWD ? Dl[1][cc * (BS + 1) + row] : Dl[1][row * (BS + 1) + cc];
         v += (double)d * xs[0][cc];
     }
     part[h][row] = v;
     __syncthreads();
     if (tid < 64) {
-        st_entry(x, (int64_t)b1 * BS + tid, part[0][tid] + part[1][tid]);
-        st_entry(x, (int64_t)b1 * BS + tid + 64, part[0][tid + 64] + part[1][tid + 64]);
+#pragma unroll
+        for (int e = 0; e < BS / 64; ++e) {
+            const int rr = tid + 64 * e;
+            double sv = part[0][rr];
+#pragma unroll
+            for (int g = 1; g < H; ++g) sv += part[g][rr];
+            st_entry(x, (int64_t)b1 * BS + rr, sv);
+        }
     }
 }
 
-template <bool BWD>
+template <bool BWD, typename T, int BS>
 __global__ void __launch_bounds__(256)
-k_trsv(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv,
+k_trsv(const T *__restrict__ L, int64_t ld, const T *__restrict__ dinv,
        const double *__restrict__ rhs, double *__restrict__ x, int *counters, int nblk,
        int *status)
 {
-    trsv_body<BWD>(L, ld, dinv, rhs, x, counters, nblk, status);
+    trsv_body<BWD, T, BS>(L, ld, dinv, rhs, x, counters, nblk, status);
 }
 
 // Batched: workgroups of problem p take tickets from p's own counters, so the
@@ -286,8 +333,8 @@ k_trsv_b(const BProb *__restrict__ P, BWork w, int rhs_slot, int x_slot)
     const int i = bfind(w.pref, w.na, blockIdx.x);
     const BProb &q = P[w.plist[i]];
     if (!q.active) return;
-    trsv_body<BWD>(q.A, q.npad, q.dinv, q.vec + (int64_t)rhs_slot * q.npad,
-                   q.vec + (int64_t)x_slot * q.npad, q.ints + 64, (int)(q.npad / BS), q.ints);
+    trsv_body<BWD, float, 128>(q.A, q.npad, q.dinv, q.vec + (int64_t)rhs_slot * q.npad,
+                               q.vec + (int64_t)x_slot * q.npad, q.ints + 64, (int)(q.npad / 128), q.ints);
 }
 
 // Tickets to zero and the vector in `slot` unset, one workgroup per problem
@@ -314,7 +361,7 @@ __global__ void k_unset(double *__restrict__ a, int64_t n)
 
 size_t prec_counter_ints() { return kCounterInts; }
 
-int64_t prec_b_units(int64_t npad) { return npad / (2 * BS); }
+int64_t prec_b_units(int64_t npad) { return npad / 256; }
 
 // x_slot = (L L^T)^{-1} rhs_slot for every problem of the work list (units = npad/128 each)
 void launch_prec_apply_b(hipStream_t s, const BProb *P, const BWork &w, int rhs_slot, int tmp_slot,
@@ -327,19 +374,32 @@ void launch_prec_apply_b(hipStream_t s, const BProb *P, const BWork &w, int rhs_
     hipLaunchKernelGGL(k_trsv_b<true>, dim3((unsigned)w.total), dim3(256), 0, s, P, w, tmp_slot, x_slot);
 }
 
-void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
-                       const double *r, double *y_tmp, double *z, int *counters, int *status)
+template <typename T, int BS>
+void prec_apply(hipStream_t s, const T *L, int64_t npad, const T *dinv, const double *r, double *y_tmp, double *z,
+                int *counters, int *status)
 {
     const int nblk = (int)(npad / BS);  // even: npad is a multiple of 256
     const unsigned gu = (unsigned)std::min<int64_t>((npad + 255) / 256, 1024);
     launch_fill_ints(s, counters, kCounterInts, 0);
     hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, y_tmp, npad);
-    hipLaunchKernelGGL(k_trsv<false>, dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, r, y_tmp, counters,
+    hipLaunchKernelGGL((k_trsv<false, T, BS>), dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, r, y_tmp, counters,
                        nblk, status);
     // z may be the caller's r: unset it only once the forward solve has read r
     hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, z, npad);
-    hipLaunchKernelGGL(k_trsv<true>, dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, y_tmp, z, counters,
+    hipLaunchKernelGGL((k_trsv<true, T, BS>), dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, y_tmp, z, counters,
                        nblk, status);
+}
+
+void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
+                       const double *r, double *y_tmp, double *z, int *counters, int *status)
+{
+    prec_apply<float, 128>(s, L, npad, dinv, r, y_tmp, z, counters, status);
+}
+
+void launch_chol64_solve(hipStream_t s, const double *L, int64_t npad, const double *dinv, const double *r,
+                         double *y_tmp, double *z, int *counters, int *status)
+{
+    prec_apply<double, 64>(s, L, npad, dinv, r, y_tmp, z, counters, status);
 }
 
 }  // namespace mag

@@ -43,6 +43,14 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert set(L.SIGNATURES) <= set(declared_functions())
 
 
+def test_enum_values_match_binding():
+    L = _lib()
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    found = dict(re.findall(r"\b(MAG_[A-Z0-9_]+)\s*=\s*(-?\d+)", src))
+    for name in ["MAG_AUTO", "MAG_FP64_DENSE", "MAG_FP32_IR", "MAG_HODLR", "MAG_HSS", "MAG_FP64_CHOL"]:
+        assert int(found[name]) == getattr(L, name), name
+
+
 def test_struct_layouts_match_c(tmp_path):
     L = _lib()
     prog = tmp_path / "layout.c"

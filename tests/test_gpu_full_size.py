@@ -5,8 +5,9 @@ benchmark times, checked against the CPU oracle.
   t*/2, 2 t* and t_b: w elementwise and M against the oracle's weighting
   (``tests/golden/full_size``, written by ``tests/golden/make_full_size.py``
   from the oracle alone), the oracle's Dot2 residual on every row, the
-  device's own residual; at t* also the FP64 dense comparator;
-* the Z^2 rectangle workload (n = 8192) at its five scales, the same checks;
+  device's own residual; at t* also both FP64 dense comparators;
+* the Z^2 rectangle workload (n = 8192) at its five scales, the same checks,
+  for the FP32 + refinement solve and both FP64 dense comparators;
 * the anisotropic cloud with covariance diag(1, 1/2, 1/4): sampled oracle rows;
 * the FP64 matrix-free product Z v: sampled rows against the oracle's row
   products, to the rounding bound of an n-term FP64 sum;
@@ -104,9 +105,11 @@ def test_metric_vs_oracle(mag, workload, scale):
         # t_+ <= t_b (the elementary bound of Sections 1 and 2), so w >= 0 there
         assert res.info["min_w"] >= 0
     if scale == "tstar":
-        # the FP64 dense comparator reaches the same weighting
-        dense = mag.weighting(Xd, rec["t"], solver="fp64_dense")
-        check_vs_golden(X, rec, wg, dense, f"metric n={N} {scale} fp64_dense")
+        # the FP64 dense comparators (rocSOLVER's and this library's FP64 MFMA
+        # factor) reach the same weighting
+        for solver in ("fp64_dense", "fp64_chol"):
+            dense = mag.weighting(Xd, rec["t"], solver=solver)
+            check_vs_golden(X, rec, wg, dense, f"metric n={N} {scale} {solver}")
 
 
 Z2_SCALES = ["0.25", "0.5", "1", "2", "4"]
@@ -119,7 +122,7 @@ def z2_workload():
 
 
 @pytest.mark.parametrize("f", Z2_SCALES)
-@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_dense"])
+@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_dense", "fp64_chol"])
 def test_z2_rectangles_vs_oracle(mag, z2_workload, f, solver):
     # the lattice workload (n = 8192 unique points of Z^2) at t = f * log(n - 1)/d_min
     X, Xd = z2_workload

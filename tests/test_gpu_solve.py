@@ -51,7 +51,7 @@ SOLVE_CASES = [
 
 
 @pytest.mark.parametrize("name,mkX,mkt", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
-@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_dense"])
+@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_dense", "fp64_chol"])
 def test_weighting_parity(mag, name, mkX, mkt, solver):
     X = mkX()
     t = float(mkt(X))
