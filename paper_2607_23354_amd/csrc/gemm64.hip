@@ -20,9 +20,11 @@
 // Workgroup tile BM x BN (128 x 128 for the trailing updates, 64 x 64 for the
 // panel's short-K products), 4 waves in a 2 x 2 arrangement, each wave a
 // (BM/2) x (BN/2) sub-tile of 16 x 16 MFMA blocks.  K is staged through LDS
-// in chunks of 16 by direct global-to-LDS loads, double-buffered, one barrier
-// per stage.  A 128-wide stage row is padded to 144 doubles, so the four
-// k-rows one MFMA operand read touches fall on disjoint bank halves.
+// by direct global-to-LDS loads: the long-K updates in chunks of 16,
+// double-buffered, one barrier per stage; the panel's K = 64 products in one
+// stage (all loads in flight at once: these launches are latency bound).  A
+// 128-wide stage row is padded to 144 doubles, so the four k-rows one MFMA
+// operand read touches fall on disjoint bank halves.
 #include "internal.hpp"
 
 namespace mag {
@@ -32,7 +34,8 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) void *gptr;  // global operand of a direct LDS load
 typedef __attribute__((address_space(3))) void *lptr;        // its LDS destination
 
-constexpr int KC = 16;   // K per LDS stage
+constexpr int KC = 16;   // K per LDS stage of the long-K updates
+constexpr int KP = 64;   // K of the panel's products (one stage)
 constexpr int NT = 256;  // threads per workgroup
 constexpr int kXcds = 8;
 
@@ -40,11 +43,11 @@ constexpr int kXcds = 8;
 template <int B>
 constexpr int stage_ld() { return B == 128 ? 144 : B; }
 
-template <int BM, int BN, int MODE>
+template <int BM, int BN, int MODE, int KS, int NBUF>
 constexpr int lds_doubles()
 {
-    // two buffers of P and Q stages; the SetT epilogue's transposed tile reuses them
-    constexpr int st = 2 * KC * (stage_ld<BM>() + stage_ld<BN>());
+    // NBUF buffers of P and Q stages; the SetT epilogue's transposed tile reuses them
+    constexpr int st = NBUF * KS * (stage_ld<BM>() + stage_ld<BN>());
     constexpr int tr = (MODE == kGemmSetT) ? BN * (BM + 1) : 0;
     return st > tr ? st : tr;
 }
@@ -58,32 +61,35 @@ __device__ inline void tri_index(int64_t idx, int64_t &ti, int64_t &tj)
     tj = idx - r * (r + 1) / 2;
 }
 
-// Stage KC rows of B entries (a column-major operand X, rows x0.., k = k0..)
+// Stage KS rows of B entries (a column-major operand X, rows x0.., k = k0..)
 // into S (row stride stage_ld<B>()) by direct loads: one wave instruction moves
-// 64 x 16 bytes, a 128-entry row or two 64-entry rows.
-template <int B>
+// 64 x 16 bytes, a 128-entry row or two 64-entry rows; wave w moves rows
+// [w KS/4, (w + 1) KS/4).
+template <int B, int KS>
 __device__ __forceinline__ void stage_rows(const double *X, int64_t ldx, int64_t x0, double *S, int wave, int lane)
 {
     constexpr int SL = stage_ld<B>();
     if constexpr (B == 128) {
 #pragma unroll
-        for (int u = 0; u < KC / 4; ++u) {
-            const int p = 4 * wave + u;
+        for (int u = 0; u < KS / 4; ++u) {
+            const int p = wave * (KS / 4) + u;
             __builtin_amdgcn_global_load_lds((gptr)(X + (int64_t)p * ldx + x0 + 2 * lane), (lptr)(S + p * SL), 16, 0,
                                              0);
         }
     } else {
         static_assert(B == 64, "tile edge 64 or 128");
 #pragma unroll
-        for (int u = 0; u < KC / 8; ++u) {
-            const int p = 2 * (2 * wave + u);
+        for (int u = 0; u < KS / 8; ++u) {
+            const int p = 2 * (wave * (KS / 8) + u);
             __builtin_amdgcn_global_load_lds((gptr)(X + (int64_t)(p + (lane >> 5)) * ldx + x0 + 2 * (lane & 31)),
                                              (lptr)(S + p * SL), 16, 0, 0);
         }
     }
 }
 
-template <int BM, int BN, int MODE>
+// KS: K per stage; NBUF = 2 double-buffers stages of a long K, NBUF = 1 takes
+// K = KS in one stage.
+template <int BM, int BN, int MODE, int KS = KC, int NBUF = 2>
 __device__ __forceinline__ void gemm64_tile(double *__restrict__ C, int64_t ldc, const double *__restrict__ P,
                                             int64_t ldp, const double *__restrict__ Q, int64_t ldq, int64_t ti,
                                             int64_t tj, int64_t K, double *__restrict__ CT)
@@ -91,9 +97,9 @@ __device__ __forceinline__ void gemm64_tile(double *__restrict__ C, int64_t ldc,
     static_assert(MODE == kGemmSub || MODE == kGemmSetT, "modes of the FP64 factor");
     constexpr int SM = stage_ld<BM>(), SN = stage_ld<BN>();
     constexpr int MI = BM / 32, MJ = BN / 32;  // 16 x 16 blocks per wave in i and j
-    __shared__ double lds[lds_doubles<BM, BN, MODE>()];
-    double *Ps = lds;                  // [2][KC][SM]
-    double *Qs = lds + 2 * KC * SM;    // [2][KC][SN]
+    __shared__ double lds[lds_doubles<BM, BN, MODE, KS, NBUF>()];
+    double *Ps = lds;                     // [NBUF][KS][SM]
+    double *Qs = lds + NBUF * KS * SM;    // [NBUF][KS][SN]
     const int64_t i0 = ti * BM, j0 = tj * BN;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -107,22 +113,22 @@ __device__ __forceinline__ void gemm64_tile(double *__restrict__ C, int64_t ldc,
 #pragma unroll
         for (int jb = 0; jb < MJ; ++jb) acc[ib][jb] = v4d{0.0, 0.0, 0.0, 0.0};
 
-    stage_rows<BM>(P, ldp, i0, Ps, wave, lane);
-    stage_rows<BN>(Q, ldq, j0, Qs, wave, lane);
+    stage_rows<BM, KS>(P, ldp, i0, Ps, wave, lane);
+    stage_rows<BN, KS>(Q, ldq, j0, Qs, wave, lane);
     __syncthreads();
-    const int nst = (int)(K / KC);
+    const int nst = (NBUF == 1) ? 1 : (int)(K / KS);
     for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst) {
+        const int buf = (NBUF == 1) ? 0 : (st & 1);
+        if (NBUF > 1 && st + 1 < nst) {
             // the other buffer was last read before the previous barrier
-            const int64_t k1 = (int64_t)(st + 1) * KC;
-            stage_rows<BM>(P + k1 * ldp, ldp, i0, Ps + (buf ^ 1) * KC * SM, wave, lane);
-            stage_rows<BN>(Q + k1 * ldq, ldq, j0, Qs + (buf ^ 1) * KC * SN, wave, lane);
+            const int64_t k1 = (int64_t)(st + 1) * KS;
+            stage_rows<BM, KS>(P + k1 * ldp, ldp, i0, Ps + (buf ^ 1) * KS * SM, wave, lane);
+            stage_rows<BN, KS>(Q + k1 * ldq, ldq, j0, Qs + (buf ^ 1) * KS * SN, wave, lane);
         }
-        const double *pb = Ps + buf * KC * SM + kq * SM + wi + q;
-        const double *qb = Qs + buf * KC * SN + kq * SN + wj + q;
+        const double *pb = Ps + buf * KS * SM + kq * SM + wi + q;
+        const double *qb = Qs + buf * KS * SN + kq * SN + wj + q;
 #pragma unroll
-        for (int kk = 0; kk < KC / 4; ++kk) {
+        for (int kk = 0; kk < KS / 4; ++kk) {
             double av[MJ], bv[MI];
 #pragma unroll
             for (int jb = 0; jb < MJ; ++jb) av[jb] = qb[4 * kk * SN + 16 * jb];
@@ -175,12 +181,12 @@ __device__ __forceinline__ void gemm64_tile(double *__restrict__ C, int64_t ldc,
     }
 }
 
-template <int BM, int BN, int MODE>
+template <int BM, int BN, int MODE, int KS, int NBUF>
 __global__ void __launch_bounds__(NT, 2)
 k_gemm64(double *__restrict__ C, int64_t ldc, const double *__restrict__ P, int64_t ldp,
          const double *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, double *__restrict__ CT)
 {
-    gemm64_tile<BM, BN, MODE>(C, ldc, P, ldp, Q, ldq, blockIdx.x % tilesM, blockIdx.x / tilesM, K, CT);
+    gemm64_tile<BM, BN, MODE, KS, NBUF>(C, ldc, P, ldp, Q, ldq, blockIdx.x % tilesM, blockIdx.x / tilesM, K, CT);
 }
 
 // Trailing symmetric update C -= P P^T on the lower 128-tiles of C only, in
@@ -200,7 +206,7 @@ k_syrk64_lower(double *__restrict__ C, int64_t ldc, const double *__restrict__ P
     const int64_t ti = si * se + within / se;
     const int64_t tj = sj * se + within % se;
     if (tj > ti || ti >= tilesM) return;  // padding slot (uniform per workgroup)
-    gemm64_tile<128, 128, kGemmSub>(C, ldc, P, ldp, P, ldp, ti, tj, K, nullptr);
+    gemm64_tile<128, 128, kGemmSub, KC, 2>(C, ldc, P, ldp, P, ldp, ti, tj, K, nullptr);
 }
 
 }  // namespace
@@ -212,11 +218,15 @@ void launch_gemm64(hipStream_t s, int tile, double *C, int64_t ldc, const double
     if (tm <= 0 || tn <= 0 || K <= 0) return;
     const dim3 g((unsigned)(tm * tn));
     if (tile == 128)
-        hipLaunchKernelGGL((k_gemm64<128, 128, kGemmSub>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+        hipLaunchKernelGGL((k_gemm64<128, 128, kGemmSub, KC, 2>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K,
+                           CT);
+    else if (K != KP)  // a 64-tile product of another depth: double-buffered stages
+        hipLaunchKernelGGL((k_gemm64<64, 64, kGemmSub, KC, 2>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
     else if (mode == kGemmSub)
-        hipLaunchKernelGGL((k_gemm64<64, 64, kGemmSub>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+        hipLaunchKernelGGL((k_gemm64<64, 64, kGemmSub, KP, 1>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
     else
-        hipLaunchKernelGGL((k_gemm64<64, 64, kGemmSetT>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+        hipLaunchKernelGGL((k_gemm64<64, 64, kGemmSetT, KP, 1>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K,
+                           CT);
 }
 
 void launch_syrk64_lower(hipStream_t s, double *C, int64_t ldc, const double *P, int64_t ldp, int64_t N, int64_t K)

@@ -12,7 +12,9 @@
 //     2. the blocks below are solved against it, L_IJ = A_IJ inv(L_JJ)^T,
 //        and block row J of the inverse is scaled, Inv_JK = inv(L_JJ) Inv_JK;
 //     3. the trailing blocks are updated, A_IK -= L_IJ L_KJ^T, and so are
-//        the inverse's rows below, Inv_IK -= L_IJ Inv_JK.
+//        the inverse's rows below, Inv_IK -= L_IJ Inv_JK: wave 0 updates the
+//        block (J+1, J+1) and goes straight on to its factor (step 1 of J+1)
+//        while waves 1..3 update the rest.
 //   Steps 2 and 3 apply, block by block, L^{-1} = L_3^{-1} ... L_0^{-1}, where
 //   L_J is the identity with block column J of L; they are 16 x 16 x 16
 //   products on v_mfma_f64_16x16x4 (one product per wave at a time).
@@ -110,9 +112,39 @@ k_potrf64(double *__restrict__ A, int64_t ld, int64_t k0, double *__restrict__ L
     if (tid == 0) bad = 0;
     __syncthreads();
 
+    // Step J's products of stage 3 are items; item 0, the trailing block (J+1, J+1),
+    // is the one the next factor needs, so wave 0 takes it and goes on to that
+    // factor while waves 1..3 take the others.
+    auto item = [&](int J, int it) {
+        const int j0 = JB * J;
+        const int rem = 3 - J;
+        const int npair = rem * (rem + 1) / 2;
+        if (it < npair) {
+            int Kr = 0;
+            while ((Kr + 1) * (Kr + 2) / 2 <= it) ++Kr;
+            const int Kc = it - Kr * (Kr + 1) / 2;
+            const int I = J + 1 + Kr, K = J + 1 + Kc;
+            // A_IK -= L_IJ L_KJ^T, W(k, c) = L_KJ(c, k) = S[(j0 + k) LD + 16 K + c]
+            const v4d d = blk16<true>(S + j0 * LD + JB * I, LD, S + j0 * LD + JB * K, LD, q, kq);
+            blk16_store(S + (JB * K) * LD + JB * I, LD, d, q, kq, -1.0, true);
+        } else {
+            const int u = it - npair;
+            const int I = J + 1 + u / (J + 1), K = u % (J + 1);
+            // Inv_IK -= L_IJ Inv_JK; block (I, J) of the inverse is first written here (from zero)
+            const v4d d = blk16<false>(S + j0 * LD + JB * I, LD, V + (JB * K) * LD + j0, LD, q, kq);
+            blk16_store(V + (JB * K) * LD + JB * I, LD, d, q, kq, -1.0, K < J);
+        }
+    };
+    auto nitems = [](int J) {
+        const int rem = 3 - J;
+        return rem * (rem + 1) / 2 + rem * (J + 1);
+    };
+
     for (int J = 0; J < NB / JB; ++J) {
         const int j0 = JB * J;
-        // 1. the diagonal block on wave 0.  The symmetric A_JJ is held whole in an
+        // 1. the diagonal block on wave 0 (after the trailing block it needs, from
+        //    the previous step's products); the previous step's other products on
+        //    waves 1..3.  The symmetric A_JJ is held whole in an
         //    accumulator (lane (q, kq), register v: A(kq + 4 v, q)), so row c of A
         //    (= column c) is register c / 4 of the lanes with kq = c % 4.  Step c:
         //    m = A(:, c) / sqrt(A(c, c)) below the diagonal (zero elsewhere and in
@@ -121,6 +153,7 @@ k_potrf64(double *__restrict__ A, int64_t ld, int64_t k0, double *__restrict__ L
         //    by 1/sqrt(A(c, c)), then Y -= m Y(c, :).  Column c of L stays in the
         //    lanes that computed it (register c / 4) until the sweep ends.
         if (wave == 0) {
+            if (J > 0) item(J - 1, 0);
             v4d a, y;
             double Lc[4];
 #pragma unroll
@@ -157,6 +190,8 @@ k_potrf64(double *__restrict__ A, int64_t ld, int64_t k0, double *__restrict__ L
                 Ys[q * JB + c] = y[v];
             }
             if (firstbad >= 0 && lane == 0 && bad == 0) bad = (int)(k0 + j0 + firstbad + 1);
+        } else if (J > 0) {
+            for (int it = wave; it < nitems(J - 1); it += 3) item(J - 1, it);
         }
         __syncthreads();
         // 2. three independent 16 x 16 products, one per wave, each in place on its
@@ -178,31 +213,6 @@ k_potrf64(double *__restrict__ A, int64_t ld, int64_t k0, double *__restrict__ L
             for (int e = lane; e < JB * JB; e += 64) {
                 const int r = e & 15, c = e >> 4;
                 V[(j0 + c) * LD + j0 + r] = Ys[c * JB + r];
-            }
-        }
-        __syncthreads();
-        // 3. trailing blocks A_IK -= L_IJ L_KJ^T (J < K <= I) and the inverse's rows
-        //    below, Inv_IK -= L_IJ Inv_JK (K <= J), as independent items over the waves
-        if (J + 1 < NB / JB) {
-            const int rem = 3 - J;
-            const int npair = rem * (rem + 1) / 2;
-            const int nitems = npair + rem * (J + 1);
-            for (int it = wave; it < nitems; it += 4) {
-                if (it < npair) {
-                    int Kr = 0;
-                    while ((Kr + 1) * (Kr + 2) / 2 <= it) ++Kr;
-                    const int Kc = it - Kr * (Kr + 1) / 2;
-                    const int I = J + 1 + Kr, K = J + 1 + Kc;
-                    // W(k, c) = L_KJ(c, k) = S[(j0 + k) LD + 16 K + c]
-                    const v4d d = blk16<true>(S + j0 * LD + JB * I, LD, S + j0 * LD + JB * K, LD, q, kq);
-                    blk16_store(S + (JB * K) * LD + JB * I, LD, d, q, kq, -1.0, true);
-                } else {
-                    const int u = it - npair;
-                    const int I = J + 1 + u / (J + 1), K = u % (J + 1);
-                    const v4d d = blk16<false>(S + j0 * LD + JB * I, LD, V + (JB * K) * LD + j0, LD, q, kq);
-                    // block (I, J) of the inverse is first written here (from zero)
-                    blk16_store(V + (JB * K) * LD + JB * I, LD, d, q, kq, -1.0, K < J);
-                }
             }
         }
         __syncthreads();
