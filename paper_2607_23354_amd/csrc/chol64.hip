@@ -11,8 +11,9 @@
 //                with L21^T written into the upper triangle
 //   3. update    the panel's later sub-panels by this one (K = 64)
 // and, per pair of panels, 4. a strip update of the second panel's columns by
-// the first (K = 256), then one trailing update A22 -= L21 L21^T of both
-// panels at once (K = 512, lower 128-tiles only).  The inverses of the
+// the first (K = 256, 64-tiles: four tile columns fill the device where two
+// 128-tile columns would occupy half of it), then one trailing update
+// A22 -= L21 L21^T of both panels at once (K = 512, lower 128-tiles only).  The inverses of the
 // diagonal 64-blocks are kept (dinv) for the triangular solves.
 #include "internal.hpp"
 
@@ -63,7 +64,7 @@ void chol64_factor(hipStream_t s, double *A, int64_t npad, int64_t n, double *di
             // the diagonal blocks are rewritten by the second panel's own trsm
             double *C = A + k2 * npad + k2;
             const double *P = A + k * npad + k2;
-            launch_gemm64(s, 128, C, npad, P, npad, P, npad, npad - k2, nb2, nb, kGemmSub, nullptr);
+            launch_gemm64(s, 64, C, npad, P, npad, P, npad, npad - k2, nb2, nb, kGemmSub, nullptr);
         }
         factor_panel64(s, A, npad, k2, nb2, dinv, status);
         const int64_t k3 = k2 + nb2;

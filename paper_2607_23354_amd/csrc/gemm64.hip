@@ -113,6 +113,19 @@ __device__ __forceinline__ void gemm64_tile(double *__restrict__ C, int64_t ldc,
 #pragma unroll
         for (int jb = 0; jb < MJ; ++jb) acc[ib][jb] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    // a one-stage update reads its C tile at once too, so every load of the
+    // workgroup is in flight before the first wait
+    constexpr bool kPreC = MODE == kGemmSub && NBUF == 1;
+    double cpre[kPreC ? MI : 1][kPreC ? MJ : 1][4];
+    if constexpr (kPreC) {
+#pragma unroll
+        for (int ib = 0; ib < MI; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < MJ; ++jb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    cpre[ib][jb][v] = C[(j0 + wj + 16 * jb + kq + 4 * v) * ldc + i0 + wi + 16 * ib + q];
+    }
     stage_rows<BM, KS>(P, ldp, i0, Ps, wave, lane);
     stage_rows<BN, KS>(Q, ldq, j0, Qs, wave, lane);
     __syncthreads();
@@ -153,7 +166,7 @@ __device__ __forceinline__ void gemm64_tile(double *__restrict__ C, int64_t ldc,
             if (MODE == kGemmSub) {
                 double cv[4];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) cv[v] = cp[4 * v * ldc];
+                for (int v = 0; v < 4; ++v) cv[v] = kPreC ? cpre[kPreC ? ib : 0][kPreC ? jb : 0][v] : cp[4 * v * ldc];
 #pragma unroll
                 for (int v = 0; v < 4; ++v) cp[4 * v * ldc] = cv[v] - acc[ib][jb][v];
             } else {
