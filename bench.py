@@ -102,7 +102,9 @@ def main():
     ap.add_argument("--no-scales", action="store_true",
                     help="skip the per-scale comparison with the oracle's expected weightings")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-dense", action="store_true", help="skip both FP64 dense comparators")
+    ap.add_argument("--no-rocsolver", action="store_true",
+                    help="skip the rocSOLVER FP64 comparator (keep this library's FP64 MFMA one)")
     ap.add_argument("--check-rows", type=int, default=512)
     ap.add_argument("--eig-steps", type=int, default=1,
                     help="timed runs of the extreme-eigenvalue estimator on the same workload (0: skip)")
@@ -183,7 +185,7 @@ def main():
     resid_sampled = float(np.abs(r_s).max())
 
     dense = None
-    if not args.no_dense:
+    if not args.no_dense and not args.no_rocsolver:
         try:
             step(profile=True, solver="fp64_dense")
             torch.cuda.synchronize()

@@ -110,7 +110,7 @@ def test_duplicates_rejected(mag):
     assert e.value.code == -2
 
 
-@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_dense", "auto"])
+@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_dense", "fp64_chol", "auto"])
 @pytest.mark.parametrize("pair", [(3, 4), (5, 1000), (1299, 0)])
 def test_duplicates_rejected_every_solver(mag, solver, pair):
     # the FP32 path finds coincident points inside its tile generator: same tile,
@@ -143,10 +143,12 @@ def test_noconv_reported(mag):
     assert res.info["status"] == -3
 
 
-def test_repeat_is_deterministic(mag):
+@pytest.mark.parametrize("solver", ["fp32_ir", "fp64_chol"])
+def test_repeat_is_deterministic(mag, solver):
+    # fixed-order reductions and no atomics in any sum: bit-identical reruns
     X = W.gaussian(900, 3, seed=4)
-    a = mag.weighting(dev(X), 3.0).w.cpu().numpy()
-    b = mag.weighting(dev(X), 3.0).w.cpu().numpy()
+    a = mag.weighting(dev(X), 3.0, solver=solver).w.cpu().numpy()
+    b = mag.weighting(dev(X), 3.0, solver=solver).w.cpu().numpy()
     assert np.array_equal(a, b)
 
 
