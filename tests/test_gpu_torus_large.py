@@ -10,7 +10,9 @@ handles that size:
 * MAG_HODLR with max_rank 224, oversample 32 and one subspace iteration of the
   range finder;
 * MAG_HODLR with leaves of 256 points and ranks of at most 64 (several hundred
-  GMRES iterations: a weaker preconditioner).
+  GMRES iterations: a weaker preconditioner);
+* at t = 8, MAG_FP64_CHOL: this library's FP64 MFMA Cholesky of the whole FP64
+  Z (137 GB) and its FP64 substitution.
 
 The oracle cannot hold Z at this size (137 GB in FP64), so it checks the
 residual 1 - Z w on sampled rows one by one (Dot2).  The magnitudes of the
@@ -77,3 +79,25 @@ def test_torus_full_size_all_solvers(mag, torus, t):
             Mb, rb, _ = got[names[j]]
             bound = 2.0 * w1 * (ra + rb) + 1e-13 * abs(Ma)
             assert abs(Ma - Mb) <= bound, (names[i], names[j], Ma, Mb, bound)
+
+
+def test_torus_full_size_fp64_chol(mag, torus):
+    # this library's FP64 MFMA Cholesky at n = 131072 (a 137 GB FP64 factor,
+    # npad^2 > 2^31: the 64-bit indexing of its GEMM, diagonal and substitution
+    # kernels), against the sampled oracle residual and the FP32 + refinement
+    # solve's magnitude through the identity of the module docstring
+    X, Xd = torus
+    t = 8.0
+    rows = np.random.default_rng(6).choice(N, size=256, replace=False)
+    res = mag.weighting(Xd, t, solver="fp64_chol", profile=True)
+    w = res.w.cpu().numpy()
+    r = float(np.abs(oracle.residual(X, t, w, rows)).max())
+    ref = mag.weighting(Xd, t, solver="fp32_ir")
+    Ma, Mb = res.info["magnitude"], ref.info["magnitude"]
+    bound = 2.0 * float(np.abs(w).sum()) * (res.info["resid_inf"] + ref.info["resid_inf"]) + 1e-13 * abs(Mb)
+    print(f"torus n={N} t={t} fp64_chol: sampled oracle residual {r:.3e} device {res.info['resid_inf']:.3e} "
+          f"factor {res.info['ms_factor']:.0f} ms substitution {res.info['ms_refine']:.1f} ms M={Ma:.13g} "
+          f"(fp32_ir {Mb:.13g})")
+    assert r <= 1e-12
+    assert res.info["resid_inf"] <= 1e-12
+    assert abs(Ma - Mb) <= bound
