@@ -177,6 +177,7 @@ struct Gmres {
 struct Factor32 {
     float *A = nullptr;
     float *dinv = nullptr;
+    float *nq = nullptr;  // the substitution's near tiles (launch_near_q), or NULL
     int64_t npad = 0;
     double shift = 0.0;
     int shifted = 0;
@@ -246,6 +247,7 @@ int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Facto
         F.shift = (F.shift == 0.0) ? 1e-6 * std::max<double>(1.0, std::sqrt((double)n)) : F.shift * 10.0;
         F.shifted = 1;
     }
+    if (F.nq) launch_near_q(s, F.A, F.npad, F.dinv, F.nq);
     return MAG_OK;
 }
 
@@ -421,7 +423,7 @@ int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, cons
     int *counters = ints + kIntCounters;
     hipStream_t s = ctx->stream;
     const PrecFn prec = [&](const double *in, double *out, double *tmp) {
-        launch_prec_apply(s, F.A, F.npad, F.dinv, in, tmp, out, counters, status);
+        launch_prec_apply(s, F.A, F.npad, F.dinv, in, tmp, out, counters, status, F.nq);
     };
     return refine_core(ctx, X, n, m, t, F.npad, prec, b, bnorm, xout, o, st, kernel);
 }
@@ -446,6 +448,7 @@ Factor32 ctx_factor(mag_ctx *ctx, int64_t n)
     F.npad = round_up(n, kPad);
     F.A = (float *)ctx->factor.p;
     F.dinv = (float *)ctx->dinv.p;
+    F.nq = F.dinv + (size_t)F.npad * kTile;  // ensure_ctx_factor sizes dinv for both
     return F;
 }
 
@@ -453,7 +456,7 @@ int ensure_ctx_factor(mag_ctx *ctx, int64_t n)
 {
     const int64_t npad = round_up(n, kPad);
     CHK(ensure(ctx, ctx->factor, sizeof(float) * (size_t)npad * (size_t)npad));
-    CHK(ensure(ctx, ctx->dinv, sizeof(float) * (size_t)npad * kTile));
+    CHK(ensure(ctx, ctx->dinv, sizeof(float) * ((size_t)npad * kTile + near_q_floats(npad))));
     return MAG_OK;
 }
 
@@ -2043,7 +2046,7 @@ int mag_weighting_fwd(mag_ctx *c, const double *X, int64_t n, int32_t m, double 
     CHK(check_points(c, X, n, m));
     {
         const size_t np = (size_t)round_up(n, kPad);
-        CHK(ctx_may_allocate(c, sizeof(float) * (np * np + np * kTile)));
+        CHK(ctx_may_allocate(c, sizeof(float) * (np * np + np * kTile + near_q_floats(np))));
     }
     mag_factor *f = new mag_factor();
     f->device = c->device;
@@ -2052,11 +2055,13 @@ int mag_weighting_fwd(mag_ctx *c, const double *X, int64_t n, int32_t m, double 
     f->t = t;
     f->F.npad = round_up(n, kPad);
     if (hipMalloc((void **)&f->F.A, sizeof(float) * (size_t)f->F.npad * f->F.npad) != hipSuccess ||
-        hipMalloc((void **)&f->F.dinv, sizeof(float) * (size_t)f->F.npad * kTile) != hipSuccess) {
+        hipMalloc((void **)&f->F.dinv,
+                  sizeof(float) * ((size_t)f->F.npad * kTile + near_q_floats(f->F.npad))) != hipSuccess) {
         (void)hipGetLastError();
         mag_factor_free(f);
         return MAG_ENOMEM;
     }
+    f->F.nq = f->F.dinv + (size_t)f->F.npad * kTile;
     int rc;
     if (n == 1) {
         launch_fill(c->stream, w, 1, 1.0);

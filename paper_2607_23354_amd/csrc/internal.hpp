@@ -409,9 +409,17 @@ size_t zmv_split_partial_doubles(int64_t n);
 // once per device (with that device current) by mag_create.
 int noalloc_setup(int device);
 
-// trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.
+// trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.  Q (may be
+// NULL): the near tiles of launch_near_q for this factor, which take the
+// one-block-per-workgroup substitution with a composite near step (a shorter
+// dependency chain); NULL takes the two-block bands.
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
-                       const double *r, double *y_tmp, double *z, int *counters, int *status);
+                       const double *r, double *y_tmp, double *z, int *counters, int *status,
+                       const float *Q = nullptr);
+// The near tiles D_b T(b, b -/+ 1) of every 128-block of the FP32 factor, both
+// directions (near_q_floats(npad) floats), from the factor and its inverses.
+size_t near_q_floats(int64_t npad);
+void launch_near_q(hipStream_t s, const float *A, int64_t npad, const float *dinv, float *Q);
 size_t prec_counter_ints();
 // z = L^{-T} L^{-1} r with the FP64 factor of chol64_factor (64-blocks).
 void launch_chol64_solve(hipStream_t s, const double *L, int64_t npad, const double *dinv, const double *r,

@@ -324,6 +324,184 @@ k_trsv(const T *__restrict__ L, int64_t ld, const T *__restrict__ dinv,
     trsv_body<BWD, T, BS>(L, ld, dinv, rhs, x, counters, nblk, status);
 }
 
+// One triangular solve of the FP32 factor with one 128-row block per
+// workgroup and a composite near step.  With the solve's block b, its
+// predecessor n (b - 1 forward, b + 1 backward) and the blocks before that
+// ("far", streamed two at a time as in trsv_body):
+//   x_b = y - Q_b x_n,   y = D_b (rhs_b - sum_far T(b, j) x_j),   Q_b = D_b T(b, n),
+// with D_b the block's inverse (transposed backward) and T the streamed tile
+// (forward L(b, j) from the lower triangle, backward L^T(b, j) from the upper
+// one).  Q_b (k_near_q) and D_b stay resident from the workgroup's start, y is
+// formed once the far blocks are in, so after its predecessor's block arrives
+// a workgroup applies one resident tile and one reduction: the dependency
+// chain costs one hand-off and one 128 x 128 product per block.
+template <bool BWD>
+__device__ __forceinline__ void trsv1_body(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv,
+                                           const float *__restrict__ Qb, const double *__restrict__ rhs,
+                                           double *__restrict__ x, int *counters, int nblk, int *status)
+{
+    constexpr int BS = 128;
+    __shared__ float Dl[BS * (BS + 1)];  // D_b, row-major, padded stride
+    __shared__ double xs[2][BS];
+    __shared__ double part[8][BS];
+    __shared__ int s_blk;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        const int ticket = atomicAdd(&counters[BWD ? kBwdTicket : kFwdTicket], 1);
+        s_blk = BWD ? nblk - 1 - ticket : ticket;
+    }
+    __syncthreads();
+    const int b = s_blk;
+    const int rg = tid & 31, cg = tid >> 5;     // tile products: rows 4 rg .., columns 16 cg ..
+    const int row = tid & (BS - 1), h = tid >> 7;  // block product: half h of row's sum
+    using Tile = Quad<float>[16];
+    auto load = [&](const float *base, int64_t ldb, Tile &t) {
+        const float *p = base + (int64_t)(16 * cg) * ldb + 4 * rg;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) load_quad(p + (int64_t)c * ldb, t[c]);
+    };
+    auto tile = [&](int j) { return L + (int64_t)j * BS * ld + (int64_t)b * BS; };
+    auto gemv = [&](const Tile &t, const double *xv, double (&acc)[4]) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const double v = xv[16 * cg + c];
+            acc[0] += (double)t[c].v[0] * v;
+            acc[1] += (double)t[c].v[1] * v;
+            acc[2] += (double)t[c].v[2] * v;
+            acc[3] += (double)t[c].v[3] * v;
+        }
+    };
+    auto jof = [&](int st) { return BWD ? (nblk - 1 - st) : st; };
+    const int nsteps = BWD ? (nblk - 1 - b) : b;  // blocks solved before this one
+    const bool has_near = nsteps >= 1;
+    const int nfar = has_near ? nsteps - 1 : 0;
+
+    // resident from the start: the right-hand side, D_b and the near tile Q_b
+    double r0 = 0.0;
+    if (tid < BS) r0 = rhs[(int64_t)b * BS + tid];
+    Tile tq;
+    if (has_near) load(Qb + (int64_t)b * BS * BS, BS, tq);
+    {
+        const float *src = dinv + (int64_t)b * BS * BS;
+        for (int e = tid; e < BS * BS; e += 256) {
+            const int rr = e & (BS - 1), cc = e >> 7;
+            Dl[rr * (BS + 1) + cc] = src[e];
+        }
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    Tile ta, tb;
+    if (nfar > 0) load(tile(jof(0)), ld, ta);
+    if (nfar > 1) load(tile(jof(1)), ld, tb);
+    for (int st = 0; st < nfar; st += 2) {
+        const bool two = st + 1 < nfar;
+        if (tid < 64) wait_blocks<BS>(x, jof(st), two ? jof(st + 1) : 0, two, xs, status);
+        __syncthreads();
+        gemv(ta, xs[0], acc);
+        if (two) gemv(tb, xs[1], acc);
+        __syncthreads();  // xs is rewritten by the next wait (or the block product below)
+        if (st + 2 < nfar) load(tile(jof(st + 2)), ld, ta);
+        if (st + 3 < nfar) load(tile(jof(st + 3)), ld, tb);
+    }
+    // y = D_b (rhs_b - acc)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[cg][4 * rg + i] = acc[i];
+    __syncthreads();
+    if (tid < BS) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) sacc += part[g][tid];
+        xs[0][tid] = r0 - sacc;
+    }
+    __syncthreads();
+    double v = 0.0;
+#pragma unroll 16
+    for (int c = 0; c < 64; ++c) {
+        const int cc = h * 64 + c;
+        const float d = BWD ? Dl[cc * (BS + 1) + row] : Dl[row * (BS + 1) + cc];
+        v += (double)d * xs[0][cc];
+    }
+    part[h][row] = v;
+    __syncthreads();
+    double y = 0.0;
+    if (tid < BS) y = part[0][tid] + part[1][tid];
+    if (!has_near) {
+        if (tid < BS) st_entry(x, (int64_t)b * BS + tid, y);
+        return;
+    }
+    // the predecessor's block: x_b = y - Q_b x_n
+    __syncthreads();  // part is rewritten below
+    if (tid < 64) wait_blocks<BS>(x, jof(nsteps - 1), 0, false, xs, status);
+    __syncthreads();
+    double aq[4] = {0.0, 0.0, 0.0, 0.0};
+    gemv(tq, xs[0], aq);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[cg][4 * rg + i] = aq[i];
+    __syncthreads();
+    if (tid < BS) {
+        double sq = 0.0;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) sq += part[g][tid];
+        st_entry(x, (int64_t)b * BS + tid, y - sq);
+    }
+}
+
+template <bool BWD>
+__global__ void __launch_bounds__(256)
+k_trsv1(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv, const float *__restrict__ Qb,
+        const double *__restrict__ rhs, double *__restrict__ x, int *counters, int nblk, int *status)
+{
+    trsv1_body<BWD>(L, ld, dinv, Qb, rhs, x, counters, nblk, status);
+}
+
+// The near tiles of k_trsv1 for every 128-block of the FP32 factor, both
+// directions: workgroup (b, d) forms Q = D_b T(b, n) (forward: D_b L(b, b - 1);
+// backward: D_b^T L^T(b, b + 1)) with FP64 accumulation of the FP32 entries,
+// stored in FP32, column-major, at Q + (d nblk + b) 128^2.  The first block in
+// solve order has none.
+__global__ void __launch_bounds__(256)
+k_near_q(const float *__restrict__ A, int64_t npad, const float *__restrict__ dinv, float *__restrict__ Q, int nblk)
+{
+    constexpr int B = 128;
+    __shared__ float Xs[B * B];  // X(i, k) at Xs[k B + i]
+    __shared__ float Ys[B * B];  // Y(k, j) at Ys[k B + j]
+    const int b = blockIdx.x, d = blockIdx.y;
+    const bool bwd = d == 1;
+    if (bwd ? (b >= nblk - 1) : (b == 0)) return;  // uniform per workgroup
+    const int jn = bwd ? b + 1 : b - 1;
+    const int tid = threadIdx.x;
+    const int ti = tid & 15, tj = tid >> 4;  // output rows 8 ti .., columns 8 tj ..
+    const float *D = dinv + (int64_t)b * B * B;  // column-major inverse
+    for (int e = tid; e < B * B; e += 256) {
+        const int i = e & (B - 1), k = e >> 7;
+        Xs[k * B + i] = bwd ? D[i * B + k] : D[k * B + i];
+        // tile T(b, jn): element (r, c) at A[(jn B + c) npad + b B + r], as Y(k = r, j = c)
+        Ys[i * B + k] = A[((int64_t)jn * B + k) * npad + (int64_t)b * B + i];
+    }
+    __syncthreads();
+    double acc[8][8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[a][c] = 0.0;
+    for (int k = 0; k < B; ++k) {
+        const float4 xa = *reinterpret_cast<const float4 *>(&Xs[k * B + 8 * ti]);
+        const float4 xb = *reinterpret_cast<const float4 *>(&Xs[k * B + 8 * ti + 4]);
+        const float4 ya = *reinterpret_cast<const float4 *>(&Ys[k * B + 8 * tj]);
+        const float4 yb = *reinterpret_cast<const float4 *>(&Ys[k * B + 8 * tj + 4]);
+        const double xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+        const double yv[8] = {ya.x, ya.y, ya.z, ya.w, yb.x, yb.y, yb.z, yb.w};
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[a][c] = fma(xv[a], yv[c], acc[a][c]);
+    }
+    float *dst = Q + ((int64_t)d * nblk + b) * B * B;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int a = 0; a < 8; ++a) dst[(8 * tj + c) * B + 8 * ti + a] = (float)acc[a][c];
+}
+
 // Batched: workgroups of problem p take tickets from p's own counters, so the
 // forward-progress argument holds per problem; problems never wait on each other.
 template <bool BWD>
@@ -391,9 +569,32 @@ void prec_apply(hipStream_t s, const T *L, int64_t npad, const T *dinv, const do
 }
 
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
-                       const double *r, double *y_tmp, double *z, int *counters, int *status)
+                       const double *r, double *y_tmp, double *z, int *counters, int *status, const float *Q)
 {
-    prec_apply<float, 128>(s, L, npad, dinv, r, y_tmp, z, counters, status);
+    if (!Q) {
+        prec_apply<float, 128>(s, L, npad, dinv, r, y_tmp, z, counters, status);
+        return;
+    }
+    const int nblk = (int)(npad / 128);
+    const float *Qb = Q + (int64_t)nblk * 128 * 128;  // the backward direction's tiles
+    const unsigned gu = (unsigned)std::min<int64_t>((npad + 255) / 256, 1024);
+    launch_fill_ints(s, counters, kCounterInts, 0);
+    hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, y_tmp, npad);
+    hipLaunchKernelGGL(k_trsv1<false>, dim3(nblk), dim3(256), 0, s, L, npad, dinv, Q, r, y_tmp, counters, nblk,
+                       status);
+    // z may be the caller's r: unset it only once the forward solve has read r
+    hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, z, npad);
+    hipLaunchKernelGGL(k_trsv1<true>, dim3(nblk), dim3(256), 0, s, L, npad, dinv, Qb, y_tmp, z, counters, nblk,
+                       status);
+}
+
+size_t near_q_floats(int64_t npad) { return (size_t)npad * 256; }
+
+void launch_near_q(hipStream_t s, const float *A, int64_t npad, const float *dinv, float *Q)
+{
+    const int nblk = (int)(npad / 128);
+    if (nblk < 2) return;
+    hipLaunchKernelGGL(k_near_q, dim3((unsigned)nblk, 2), dim3(256), 0, s, A, npad, dinv, Q, nblk);
 }
 
 void launch_chol64_solve(hipStream_t s, const double *L, int64_t npad, const double *dinv, const double *r,
