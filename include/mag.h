@@ -432,7 +432,9 @@ int mag_factor32(mag_ctx *ctx, const double *X, int64_t n, int32_t m, double t,
                  double shift, float *L, float *dinv, int32_t *breakdown);
 
 /* z = (L L^T)^{-1} r with the factor from mag_factor32, FP64 arithmetic;
- * r, z: device, n. */
+ * r, z: device, n.  Each call forms the substitution's near tiles
+ * (D_b L(b, b-1) and D_b^T L^T(b, b+1) per 128-block, npad * 256 floats of
+ * context workspace) from L and dinv, then runs the two triangular solves. */
 int mag_prec_apply(mag_ctx *ctx, const float *L, const float *dinv, int64_t n,
                    const double *r, double *z);
 

@@ -177,7 +177,7 @@ struct Gmres {
 struct Factor32 {
     float *A = nullptr;
     float *dinv = nullptr;
-    float *nq = nullptr;  // the substitution's near tiles (launch_near_q), or NULL
+    float *nq = nullptr;  // the substitution's near tiles (launch_near_q, near_q_floats(npad))
     int64_t npad = 0;
     double shift = 0.0;
     int shifted = 0;
@@ -247,7 +247,7 @@ int factor_fp32(mag_ctx *ctx, const double *X, int64_t n, int m, double t, Facto
         F.shift = (F.shift == 0.0) ? 1e-6 * std::max<double>(1.0, std::sqrt((double)n)) : F.shift * 10.0;
         F.shifted = 1;
     }
-    if (F.nq) launch_near_q(s, F.A, F.npad, F.dinv, F.nq);
+    launch_near_q(s, F.A, F.npad, F.dinv, F.nq);
     return MAG_OK;
 }
 
@@ -1568,15 +1568,19 @@ int mag_prec_apply(mag_ctx *c, const float *L, const float *dinv, int64_t n, con
     HIPCHK(hipSetDevice(c->device));
     CHK(ensure(c, c->ints, sizeof(int) * kIntsTotal));
     const int64_t npad = round_up(n, kPad);
-    CHK(ensure(c, c->vecs, sizeof(double) * ((size_t)npad * 3 + 256)));
+    // three vectors, then the substitution's near tiles (formed from L and dinv per call)
+    const size_t vec_doubles = (size_t)npad * 3 + 256;
+    CHK(ensure(c, c->vecs, sizeof(double) * vec_doubles + sizeof(float) * near_q_floats(npad)));
     double *rb = (double *)c->vecs.p;
     double *yt = rb + npad;
     double *zb = yt + npad;
+    float *nq = (float *)(rb + vec_doubles);
     int *ints = (int *)c->ints.p;
     launch_fill_ints(c->stream, ints, 8, 0);
     launch_fill(c->stream, rb, npad, 0.0);
     HIPCHK(hipMemcpyAsync(rb, r, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-    launch_prec_apply(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints);
+    launch_near_q(c->stream, L, npad, dinv, nq);
+    launch_prec_apply(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints, nq);
     HIPCHK(hipMemcpyAsync(z, zb, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->host_scalars, ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

@@ -409,13 +409,12 @@ size_t zmv_split_partial_doubles(int64_t n);
 // once per device (with that device current) by mag_create.
 int noalloc_setup(int device);
 
-// trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic.  Q (may be
-// NULL): the near tiles of launch_near_q for this factor, which take the
-// one-block-per-workgroup substitution with a composite near step (a shorter
-// dependency chain); NULL takes the two-block bands.
+// trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic, by the
+// one-block-per-workgroup substitution with a composite near step.  Q: the near
+// tiles of launch_near_q for this factor (required).
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
                        const double *r, double *y_tmp, double *z, int *counters, int *status,
-                       const float *Q = nullptr);
+                       const float *Q);
 // The near tiles D_b T(b, b -/+ 1) of every 128-block of the FP32 factor, both
 // directions (near_q_floats(npad) floats), from the factor and its inverses.
 size_t near_q_floats(int64_t npad);

@@ -4,12 +4,18 @@
 // L is the FP32 Cholesky factor (column-major, leading dimension npad, lower
 // triangle), r and z are FP64 and all arithmetic is FP64.  The diagonal
 // 128 x 128 blocks are applied through their explicit inverses (FP32, from the
-// factorisation), so a block step is a small matrix-vector product.  The same
-// kernel, instantiated for the FP64 factor, works on 64 x 64 blocks (whose
-// FP64 inverses fit LDS).  The figures below are those of the FP32 factor.
+// factorisation), so a block step is a small matrix-vector product.  Two
+// kernels share the hand-off protocol below:
+//   * the band kernel (trsv_body, one workgroup per two blocks) serves the
+//     batched solves and, instantiated for the FP64 factor, its 64 x 64 blocks
+//     (whose FP64 inverses fit LDS); the figures below are those of the FP32
+//     factor at n = 32768;
+//   * k_trsv1 (one workgroup per block, composite near step, further down)
+//     serves the single FP32 solves: 0.58 ms per direction at n = 32768
+//     against the band kernel's 0.97 ms.
 //
-// Each triangular solve is ONE launch with one workgroup per two blocks
-// and no host round trips ("sync-free" substitution):
+// Each triangular solve is ONE launch and no host round trips ("sync-free"
+// substitution).  For the band kernel:
 //   * a workgroup owns a band of two consecutive blocks and takes a ticket
 //     from an atomic counter; ticket order is the band order of the
 //     substitution, so every block a workgroup waits for belongs to a
@@ -571,10 +577,6 @@ void prec_apply(hipStream_t s, const T *L, int64_t npad, const T *dinv, const do
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
                        const double *r, double *y_tmp, double *z, int *counters, int *status, const float *Q)
 {
-    if (!Q) {
-        prec_apply<float, 128>(s, L, npad, dinv, r, y_tmp, z, counters, status);
-        return;
-    }
     const int nblk = (int)(npad / 128);
     const float *Qb = Q + (int64_t)nblk * 128 * 128;  // the backward direction's tiles
     const unsigned gu = (unsigned)std::min<int64_t>((npad + 255) / 256, 1024);
