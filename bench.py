@@ -353,6 +353,15 @@ def main():
         "eig_extremes": eig,
         "weighting_zero": zero,
         "cpu_baseline": cpu,
+        # the paper's own timing of this computation (section "Current scaling"): context on
+        # other hardware with another solver, not the target
+        "paper_context": {
+            "value_s": 60.0,
+            "what": "about one minute per cutoff-search iteration (one Zw=1 solve with HSS "
+                    "compression and ULV factorisation, plus Lanczos), n about 30000 Gaussian points",
+            "hardware": "16-core Apple M4 Max laptop CPU (Docker capped at 16 CPUs)",
+            "method": "FP64 HSS + ULV (STRUMPACK), OpenBLAS",
+        },
     }
     print(json.dumps(out))
 
