@@ -38,14 +38,14 @@ void factor_panel(hipStream_t s, float *A, int64_t npad, int64_t k, int64_t nb, 
         if (below > 0) {
             float *A21 = A + kk * npad + kk + T;
             float *A12 = A + (kk + T) * npad + kk;  // upper triangle: L21^T
-            launch_gemm_nt(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSetT, A12);
+            launch_gemm_rows64(s, A21, npad, A21, npad, Linv, T, below, T, T, kGemmSetT, A12);
         }
         if (sub + 1 < nsub) {
             // the panel's remaining sub-panels (rows kk+T ..) by this sub-panel;
             // tiles above their diagonal are rewritten later by their own trsm
             float *C = A + (kk + T) * npad + kk + T;
             const float *P = A + kk * npad + kk + T;
-            launch_gemm_nt(s, C, npad, P, npad, P, npad, below, (nsub - sub - 1) * T, T, kGemmSub);
+            launch_gemm_rows64(s, C, npad, P, npad, P, npad, below, (nsub - sub - 1) * T, T, kGemmSub);
         }
     }
 }

@@ -217,6 +217,125 @@ k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64
     gemm_tile_body<MODE, LDS_EPI>(C, ldc, P, ldp, Q, ldq, ti, tj, K, CT);
 }
 
+// The panel path's short-K contractions (K = 128: the panel solve against the
+// diagonal block's inverse and the sub-panel updates) on tiles of 64 rows x 128
+// columns: twice the workgroups of the 128 x 128 tile for the same rows, so the
+// later panels, whose few row tiles leave most CUs idle, finish in about half
+// the MFMA time per workgroup.  A workgroup still owns whole 128-column rows of
+// C, so the in-place panel solve (C = P) reads its rows before it rewrites them.
+// Waves in 2 x 2: rows wi .. wi + 31, columns wj .. wj + 63 (two 32 x 32
+// accumulators).  K staged through LDS in double-buffered chunks of 16 by direct
+// loads, as in gemm_tile_body.
+constexpr int BR = 64;
+constexpr int LDS_R64 = 2 * KC * BR + 2 * KC * BT;  // P and Q stages (24 KB)
+
+template <int MODE>
+__global__ void __launch_bounds__(NT, 2)
+k_gemm_rows64(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
+              const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K, float *__restrict__ CT)
+{
+    __shared__ float lds[LDS_R64];
+    float (*Ps)[KC][BR] = reinterpret_cast<float (*)[KC][BR]>(lds);
+    float (*Qs)[KC][BT] = reinterpret_cast<float (*)[KC][BT]>(lds + 2 * KC * BR);
+    const int64_t ti = blockIdx.x % tilesM, tj = blockIdx.x / tilesM;
+    const int64_t i0 = ti * BR, j0 = tj * BT;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wi = (wave & 1) * 32;
+    const int wj = (wave >> 1) * 64;
+    const int l32 = lane & 31;
+    const int hi = lane >> 5;
+
+    v16f acc[2];
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[jb][r] = 0.0f;
+
+    // P stage (64 rows x 16 k): thread t fetches the float4 at row 4 (t % 16),
+    // k = t / 16, so wave w fills k-rows 4 w .. 4 w + 3 (1 KB, contiguous);
+    // Q stage (128 rows x 16 k) as in gemm_tile_body
+    const float *pg = P + (threadIdx.x >> 4) * ldp + i0 + 4 * (threadIdx.x & 15);
+    const int lr = 4 * (threadIdx.x & 31);
+    const int lp = threadIdx.x >> 5;
+    const float *qg0 = Q + lp * ldq + j0 + lr, *qg1 = Q + (lp + 8) * ldq + j0 + lr;
+    const int64_t stepP = KC * ldp, stepQ = KC * ldq;
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    auto stage_in = [&](int b) {
+        __builtin_amdgcn_global_load_lds((gptr)pg, (lptr)&Ps[b][4 * wu][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gptr)qg0, (lptr)&Qs[b][2 * wu][0], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((gptr)qg1, (lptr)&Qs[b][2 * wu + 8][0], 16, 0, 0);
+    };
+    stage_in(0);
+    __syncthreads();
+
+    const int nst = (int)(K / KC);
+    for (int st = 0; st < nst; ++st) {
+        const int buf = st & 1;
+        if (st + 1 < nst) {
+            pg += stepP;
+            qg0 += stepQ;
+            qg1 += stepQ;
+            stage_in(buf ^ 1);
+        }
+#pragma unroll
+        for (int kp = 0; kp < KC / 2; ++kp) {
+            const int p = 2 * kp + hi;
+            const float pv = Ps[buf][p][wi + l32];
+            const float q0 = Qs[buf][p][wj + l32];
+            const float q1 = Qs[buf][p][wj + 32 + l32];
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(q0, pv, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(q1, pv, acc[1], 0, 0, 0);
+        }
+        __syncthreads();  // waits for the direct loads of the next stage too
+    }
+
+    const int64_t i = i0 + wi + l32;
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+        if (MODE == kGemmSub) {
+            float cv[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                cv[r] = C[j * ldc + i];
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                C[j * ldc + i] = cv[r] - acc[jb][r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t j = j0 + wj + jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                C[j * ldc + i] = acc[jb][r];
+            }
+        }
+    }
+    if (MODE == kGemmSetT) {
+        // transposed copy, 64 columns of the tile at a time through LDS (T[jl][il])
+        float *T = lds;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            __syncthreads();
+            if ((wave >> 1) == half) {
+#pragma unroll
+                for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int jl = jb * 32 + 8 * (r >> 2) + 4 * hi + (r & 3);
+                        T[jl * (BR + 1) + wi + l32] = acc[jb][r];
+                    }
+            }
+            __syncthreads();
+            const int jl = threadIdx.x & 63;
+            for (int il = threadIdx.x >> 6; il < BR; il += NT / 64)
+                CT[(i0 + il) * ldc + j0 + half * 64 + jl] = T[jl * (BR + 1) + il];
+        }
+    }
+}
+
 // Trailing symmetric update C -= P P^T on the lower tiles of C only.
 // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin by id, so
 // id % 8 picks the XCD and consecutive ids of one XCD walk the se x se tiles
@@ -341,6 +460,20 @@ void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_
         hipLaunchKernelGGL(k_gemm_nt<kGemmSet>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
     else
         hipLaunchKernelGGL(k_gemm_nt<kGemmSetT>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+}
+
+void launch_gemm_rows64(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp, const float *Q,
+                        int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode, float *CT)
+{
+    const int64_t tm = M / BR, tn = N / BT;
+    if (tm <= 0 || tn <= 0 || K <= 0) return;
+    const dim3 g((unsigned)(tm * tn));
+    if (mode == kGemmSub)
+        hipLaunchKernelGGL(k_gemm_rows64<kGemmSub>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+    else if (mode == kGemmSet)
+        hipLaunchKernelGGL(k_gemm_rows64<kGemmSet>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
+    else
+        hipLaunchKernelGGL(k_gemm_rows64<kGemmSetT>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
 }
 
 void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,

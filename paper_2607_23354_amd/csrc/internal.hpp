@@ -362,6 +362,11 @@ enum GemmMode { kGemmSub = 0, kGemmSet = 1, kGemmSetT = 2 };
 void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                     const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K,
                     GemmMode mode, float *CT = nullptr, bool deep = false);
+// The same contractions on 64-row x 128-column tiles (the panel path's short-K
+// products): M a multiple of 64, N of 128, K of 16.  A workgroup owns whole
+// 128-column row blocks of C, so C may alias P when N = 128 (the in-place panel solve).
+void launch_gemm_rows64(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp, const float *Q,
+                        int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode, float *CT = nullptr);
 // C (N x N, lower 128-tiles only) -= P P^T with P N x K; N multiple of 128.
 void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
                        int64_t N, int64_t K);
