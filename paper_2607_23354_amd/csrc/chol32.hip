@@ -75,7 +75,7 @@ void chol32_factor(hipStream_t s, float *A, int64_t npad, int64_t n, float *dinv
             // the 128-diagonal of its diagonal block are rewritten by its own trsm
             float *C = A + k2 * npad + k2;
             const float *P = A + k * npad + k2;
-            launch_gemm_nt(s, C, npad, P, npad, P, npad, npad - k2, nb2, nb, kGemmSub, nullptr, true);
+            launch_gemm_rows64(s, C, npad, P, npad, P, npad, npad - k2, nb2, nb, kGemmSub);
         }
         factor_panel(s, A, npad, k2, nb2, dinv, status);
         const int64_t k3 = k2 + nb2;
