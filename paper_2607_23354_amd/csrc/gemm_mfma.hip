@@ -206,17 +206,6 @@ __device__ __forceinline__ void gemm_tile_body(float *__restrict__ C, int64_t ld
     }
 }
 
-template <int MODE, bool LDS_EPI = false>
-__global__ void __launch_bounds__(NT, 2)
-k_gemm_nt(float *__restrict__ C, int64_t ldc, const float *__restrict__ P, int64_t ldp,
-          const float *__restrict__ Q, int64_t ldq, int64_t tilesM, int64_t K,
-          float *__restrict__ CT)
-{
-    const int64_t ti = blockIdx.x % tilesM;
-    const int64_t tj = blockIdx.x / tilesM;
-    gemm_tile_body<MODE, LDS_EPI>(C, ldc, P, ldp, Q, ldq, ti, tj, K, CT);
-}
-
 // The panel path's short-K contractions (K = 128: the panel solve against the
 // diagonal block's inverse and the sub-panel updates) on tiles of 64 rows x 128
 // columns: twice the workgroups of the 128 x 128 tile for the same rows, so the
@@ -443,23 +432,6 @@ void launch_gemm_b(hipStream_t s, int kind, const BProb *P, const BWork &w, int6
         hipLaunchKernelGGL(k_gemm_b<4>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
     else
         hipLaunchKernelGGL(k_gemm_b<3>, dim3((unsigned)w.total), dim3(NT), 0, s, P, w, kk);
-}
-
-void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
-                    const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode,
-                    float *CT, bool deep)
-{
-    const int64_t tm = M / BT, tn = N / BT;
-    if (tm <= 0 || tn <= 0 || K <= 0) return;
-    const dim3 g((unsigned)(tm * tn));
-    if (mode == kGemmSub && deep)
-        hipLaunchKernelGGL((k_gemm_nt<kGemmSub, true>), g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
-    else if (mode == kGemmSub)
-        hipLaunchKernelGGL(k_gemm_nt<kGemmSub>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
-    else if (mode == kGemmSet)
-        hipLaunchKernelGGL(k_gemm_nt<kGemmSet>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
-    else
-        hipLaunchKernelGGL(k_gemm_nt<kGemmSetT>, g, dim3(NT), 0, s, C, ldc, P, ldp, Q, ldq, tm, K, CT);
 }
 
 void launch_gemm_rows64(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp, const float *Q,

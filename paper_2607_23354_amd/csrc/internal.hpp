@@ -354,17 +354,13 @@ void launch_dmin2(hipStream_t s, const double *X, int64_t n, int m, double *part
                   int64_t *np, double *out_min2);
 void launch_check_finite(hipStream_t s, const double *X, int64_t count, int *status);
 
-// gemm_mfma.hip: C (M x N) = [C] - P * Q^T or C = P * Q^T, column-major operands.
-// P is M x K (P[p*ldp + i]), Q is N x K (Q[p*ldq + j]); M, N multiples of 128,
-// K multiple of 16.  kGemmSetT also writes C^T to CT (CT(j, i) at CT[i * ldc + j]).
+// gemm_mfma.hip: C (M x N) = [C] - P * Q^T (kGemmSub) or C = P * Q^T (kGemmSet),
+// column-major operands: P is M x K (P[p*ldp + i]), Q is N x K (Q[p*ldq + j]).
+// kGemmSetT also writes C^T to CT (CT(j, i) at CT[i * ldc + j]).
 enum GemmMode { kGemmSub = 0, kGemmSet = 1, kGemmSetT = 2 };
-// deep: a kGemmSub with a deep K (takes the LDS-staged epilogue).
-void launch_gemm_nt(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp,
-                    const float *Q, int64_t ldq, int64_t M, int64_t N, int64_t K,
-                    GemmMode mode, float *CT = nullptr, bool deep = false);
-// The same contractions on 64-row x 128-column tiles (the panel path's short-K
-// products): M a multiple of 64, N of 128, K of 16.  A workgroup owns whole
-// 128-column row blocks of C, so C may alias P when N = 128 (the in-place panel solve).
+// The panel path's contractions on 64-row x 128-column tiles: M a multiple of
+// 64, N of 128, K of 16.  A workgroup owns whole 128-column row blocks of C, so
+// C may alias P when N = 128 (the in-place panel solve).
 void launch_gemm_rows64(hipStream_t s, float *C, int64_t ldc, const float *P, int64_t ldp, const float *Q,
                         int64_t ldq, int64_t M, int64_t N, int64_t K, GemmMode mode, float *CT = nullptr);
 // C (N x N, lower 128-tiles only) -= P P^T with P N x K; N multiple of 128.
@@ -373,7 +369,7 @@ void launch_syrk_lower(hipStream_t s, float *C, int64_t ldc, const float *P, int
 
 // gemm64.hip: the FP64 factor's contractions, C (M x N) -= P Q^T (kGemmSub) or
 // C = P Q^T with C^T into CT (kGemmSetT); operands column-major as for
-// launch_gemm_nt.  tile 128: M, N multiples of 128, kGemmSub only; tile 64: M, N
+// launch_gemm_rows64.  tile 128: M, N multiples of 128, kGemmSub only; tile 64: M, N
 // multiples of 64.  K a multiple of 16; operand pointers 16-byte aligned and
 // leading dimensions even.
 void launch_gemm64(hipStream_t s, int tile, double *C, int64_t ldc, const double *P, int64_t ldp, const double *Q,
