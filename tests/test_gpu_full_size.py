@@ -12,7 +12,9 @@ benchmark times, checked against the CPU oracle.
 * the FP64 matrix-free product Z v: sampled rows against the oracle's row
   products, to the rounding bound of an n-term FP64 sum;
 * the FP32 tile generator: every entry among 384 sampled points against the
-  oracle's FP64 Z, to a few FP32 ulps.
+  oracle's FP64 Z, to a few FP32 ulps;
+* the preconditioner apply of the refinement at n = 32768: backward error of
+  L L^T z = r against its FP32 rounding bound.
 
 Tolerance on w.  Both weightings solve Z w = 1 up to their residuals, so
 w_gpu - w_gold = Z^{-1} (r_gold - r_gpu) and
@@ -188,3 +190,35 @@ def test_metric_tile32_sampled_block(mag, workload):
     assert not bad.any(), (f"{bad.sum()} entries off; worst: Z={Z[bad][:4]} got={got[bad][:4]} "
                            f"t*d={t * D[bad][:4]}")
     assert np.all(np.diag(got) == 1.0)
+
+
+def test_metric_prec_apply_backward_error(mag, workload):
+    # the refinement's preconditioner apply z = (L L^T)^{-1} r at the metric size, in
+    # the launch configuration the solve uses (one workgroup per 128-row block, near
+    # tiles D_b L(b, b -/+ 1) formed from the factor): L L^T z reproduces r to the
+    # rounding of FP32 block inverses and near tiles.  Per block the substitution
+    # applies D_b = L_bb^{-1} + E with |E| <~ kappa_b u32 |L_bb^{-1}| (kappa_b the
+    # block's condition number) and near tiles rounded to FP32, so every row of
+    # L L^T z - r is bounded by a small multiple of 128 kappa_b u32 (|L| |L^T| |z|)
+    X, t, Xd = workload
+    L, dinv, bd = mag.factor32(Xd, t)
+    assert bd == 0
+    r = np.random.default_rng(11).standard_normal(N)
+    z = mag.prec_apply(L, dinv, N, dev(r))
+    U = torch.triu(L[:N, :N]).double()  # the upper triangle holds L^T
+    del L
+    torch.cuda.empty_cache()
+    # kappa_b = max_b ||L_bb||_inf ||D_b||_inf over the 256 diagonal blocks
+    kb = 0.0
+    for b in range(N // 128):
+        Lbb = U[128 * b:128 * (b + 1), 128 * b:128 * (b + 1)].T
+        Db = dinv[b].double().T  # dinv[b] holds D_b column-major
+        kb = max(kb, float(Lbb.abs().sum(1).max() * Db.abs().sum(1).max()))
+    rr = U.T @ (U @ z.unsqueeze(1))
+    scale = U.abs().T @ (U.abs() @ z.abs().unsqueeze(1))
+    err = (rr.squeeze(1) - dev(r)).abs()
+    tol = 16 * 128 * kb * U32 * scale.squeeze(1)
+    worst = float((err / scale.squeeze(1)).max())
+    print(f"prec apply n={N}: kappa_b={kb:.3g} max |L L^T z - r| / (|L||L^T||z|) = {worst:.3e} "
+          f"(bound {16 * 128 * kb * U32:.3e})")
+    assert bool((err <= tol).all())
