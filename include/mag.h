@@ -61,6 +61,15 @@ void mag_destroy(mag_ctx *ctx);
 int mag_set_workspace_limit(mag_ctx *ctx, uint64_t bytes);
 int mag_workspace_bytes(const mag_ctx *ctx, uint64_t *held);
 
+/* Bound the waits of the sync-free triangular solves (the preconditioner
+ * apply of MAG_FP32_IR and mag_prec_apply, the substitution of MAG_FP64_CHOL
+ * and mag_chol64_solve) on this context: a workgroup that has polled `polls`
+ * times for the block it needs gives up, the kernel finishes, and the call
+ * returns MAG_EINTERNAL.  0 (the default) = 2^26 polls, about a minute, far
+ * beyond any wait of a correct launch; a small value forces that error path
+ * (tests use it).  The batched solves keep the default.  MAG_EINVAL for polls < 0. */
+int mag_set_spin_limit(mag_ctx *ctx, int64_t polls);
+
 /* Enqueue subsequent work on `hip_stream` (a hipStream_t; NULL = the
  * context's own stream, a blocking stream: it is ordered with the device's
  * null stream, so work a caller enqueues there -- e.g. PyTorch's default

@@ -61,6 +61,11 @@ class Context:
         would exceed it fail with MAG_ENOMEM."""
         _lib.check(self.lib.mag_set_workspace_limit(self.handle, int(nbytes)), "mag_set_workspace_limit")
 
+    def set_spin_limit(self, polls: int) -> None:
+        """Bound the sync-free triangular solves' waits (0 = the default); a
+        call whose waits run out fails with MAG_EINTERNAL."""
+        _lib.check(self.lib.mag_set_spin_limit(self.handle, int(polls)), "mag_set_spin_limit")
+
     def workspace_bytes(self) -> int:
         held = ctypes.c_uint64()
         _lib.check(self.lib.mag_workspace_bytes(self.handle, ctypes.byref(held)), "mag_workspace_bytes")

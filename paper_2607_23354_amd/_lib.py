@@ -144,6 +144,7 @@ SIGNATURES = {
     "mag_destroy": (None, [_vp]),
     "mag_set_stream": (ctypes.c_int, [_vp, _vp]),
     "mag_set_workspace_limit": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "mag_set_spin_limit": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "mag_workspace_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint64)]),
     "mag_opts_default": (None, [ctypes.POINTER(MagOpts)]),
     "mag_weighting": (ctypes.c_int, [_vp, _vp, _i64, _i32, _d, _vp, ctypes.POINTER(MagOpts),

@@ -80,6 +80,12 @@ using namespace mag;
     } while (0)
 
 namespace mag {
+// Polls of one wait of the sync-free substitutions on this context.
+long spin_limit_of(const mag_ctx *ctx)
+{
+    return ctx->spin_limit > 0 ? (long)ctx->spin_limit : kSpinLimitDefault;
+}
+
 // Validate the coordinates: finite, and no duplicate points (Z would be
 // singular).  One host sync.
 int check_points(mag_ctx *ctx, const double *X, int64_t n, int m, bool pairs)
@@ -423,7 +429,7 @@ int refine_solve(mag_ctx *ctx, const double *X, int64_t n, int m, double t, cons
     int *counters = ints + kIntCounters;
     hipStream_t s = ctx->stream;
     const PrecFn prec = [&](const double *in, double *out, double *tmp) {
-        launch_prec_apply(s, F.A, F.npad, F.dinv, in, tmp, out, counters, status, F.nq);
+        launch_prec_apply(s, F.A, F.npad, F.dinv, in, tmp, out, counters, status, F.nq, spin_limit_of(ctx));
     };
     return refine_core(ctx, X, n, m, t, F.npad, prec, b, bnorm, xout, o, st, kernel);
 }
@@ -673,7 +679,7 @@ int solve_fp64_chol(mag_ctx *ctx, const double *X, int64_t n, int m, double t, d
     chol64_factor(s, A, npad, n, dinv, status, o.profile ? &ft : nullptr);
     tm.mark(2);
     launch_affine_ones(s, nullptr, 1.0, rhs, n, npad);
-    launch_chol64_solve(s, A, npad, dinv, rhs, ytmp, z, ints + kIntCounters, status);
+    launch_chol64_solve(s, A, npad, dinv, rhs, ytmp, z, ints + kIntCounters, status, spin_limit_of(ctx));
     HIPCHK(hipMemcpyAsync(w, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     tm.mark(3);
     HIPCHK(hipMemcpyAsync(hs + 16, status, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -718,7 +724,8 @@ int solve_fp64_chol(mag_ctx *ctx, const double *X, int64_t n, int m, double t, d
         if (o.diag & MAG_DIAG_COND) {
             const SolveOp inv = [&](const double *in, double *out) -> int {
                 // in, out: npad vectors zero in the padding
-                launch_chol64_solve(s, A, npad, dinv, in, ytmp, out, ints + kIntCounters, status);
+                launch_chol64_solve(s, A, npad, dinv, in, ytmp, out, ints + kIntCounters, status,
+                                    spin_limit_of(ctx));
                 return MAG_OK;
             };
             CHK(diag_cond(ctx, X, n, m, t, inv, info->cond_est));
@@ -1287,6 +1294,13 @@ int mag_set_workspace_limit(mag_ctx *c, uint64_t bytes)
     return MAG_OK;
 }
 
+int mag_set_spin_limit(mag_ctx *c, int64_t polls)
+{
+    if (!c || polls < 0) return MAG_EINVAL;
+    c->spin_limit = polls;
+    return MAG_OK;
+}
+
 int mag_workspace_bytes(const mag_ctx *c, uint64_t *held)
 {
     if (!c || !held) return MAG_EINVAL;
@@ -1580,7 +1594,7 @@ int mag_prec_apply(mag_ctx *c, const float *L, const float *dinv, int64_t n, con
     launch_fill(c->stream, rb, npad, 0.0);
     HIPCHK(hipMemcpyAsync(rb, r, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     launch_near_q(c->stream, L, npad, dinv, nq);
-    launch_prec_apply(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints, nq);
+    launch_prec_apply(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints, nq, spin_limit_of(c));
     HIPCHK(hipMemcpyAsync(z, zb, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->host_scalars, ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1619,7 +1633,7 @@ int mag_chol64_solve(mag_ctx *c, const double *L, const double *dinv, int64_t n,
     launch_fill_ints(c->stream, ints, 8, 0);
     launch_fill(c->stream, rb, npad, 0.0);
     HIPCHK(hipMemcpyAsync(rb, r, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-    launch_chol64_solve(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints);
+    launch_chol64_solve(c->stream, L, npad, dinv, rb, yt, zb, ints + kIntCounters, ints, spin_limit_of(c));
     HIPCHK(hipMemcpyAsync(z, zb, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->host_scalars, ints, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));

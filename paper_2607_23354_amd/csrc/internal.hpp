@@ -296,6 +296,8 @@ struct mag_ctx {
     int tune_bgroup[64] = {};
     // cap on the device bytes held by the buffers above (0: none)
     size_t ws_limit = 0;
+    // polls of one substitution wait before MAG_EINTERNAL (0: kSpinLimitDefault)
+    int64_t spin_limit = 0;
 };
 
 namespace mag {
@@ -410,12 +412,15 @@ size_t zmv_split_partial_doubles(int64_t n);
 // once per device (with that device current) by mag_create.
 int noalloc_setup(int device);
 
+// Polls of one wait of the sync-free substitutions before they give up and
+// report MAG_EINTERNAL (mag_set_spin_limit overrides it per context).
+constexpr long kSpinLimitDefault = 1L << 26;
 // trsv.hip: z = L^{-T} L^{-1} r with the FP32 factor, FP64 arithmetic, by the
 // one-block-per-workgroup substitution with a composite near step.  Q: the near
 // tiles of launch_near_q for this factor (required).
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
                        const double *r, double *y_tmp, double *z, int *counters, int *status,
-                       const float *Q);
+                       const float *Q, long spin_limit);
 // The near tiles D_b T(b, b -/+ 1) of every 128-block of the FP32 factor, both
 // directions (near_q_floats(npad) floats), from the factor and its inverses.
 size_t near_q_floats(int64_t npad);
@@ -423,7 +428,8 @@ void launch_near_q(hipStream_t s, const float *A, int64_t npad, const float *din
 size_t prec_counter_ints();
 // z = L^{-T} L^{-1} r with the FP64 factor of chol64_factor (64-blocks).
 void launch_chol64_solve(hipStream_t s, const double *L, int64_t npad, const double *dinv, const double *r,
-                         double *y_tmp, double *z, int *counters, int *status);
+                         double *y_tmp, double *z, int *counters, int *status,
+                         long spin_limit);
 
 // blas1.hip: deterministic FP64 vector kernels (length npad, two-pass).
 void launch_fill(hipStream_t s, double *x, int64_t len, double v);

@@ -51,7 +51,6 @@
 namespace mag {
 namespace {
 
-constexpr long kSpinLimit = 1L << 26;
 constexpr int kSlot = 64;  // ints between the two tickets (256 bytes)
 
 // counter layout (ints): fwd ticket @0, bwd ticket @kSlot
@@ -74,11 +73,11 @@ __device__ inline void st_entry(double *x, int64_t i, double v)
 }
 
 // Wave 0 (lanes 0..63): wait until the BS entries of block j0 (and j1 if two)
-// of x are set, and copy them to xs[0] (xs[1]).  Bounded: on exhaustion the
-// status word is set and whatever was read is used.
+// of x are set, and copy them to xs[0] (xs[1]).  Bounded: after spin_limit
+// polls the status word is set and whatever was read is used.
 template <int BS>
 __device__ inline void wait_blocks(const double *x, int64_t j0, int64_t j1, bool two, double (&xs)[2][BS],
-                                   int *status)
+                                   int *status, long spin_limit)
 {
     static_assert(BS == 64 || BS == 128, "one or two entries per lane and block");
     constexpr bool E2 = BS == 128;
@@ -94,7 +93,7 @@ __device__ inline void wait_blocks(const double *x, int64_t j0, int64_t j1, bool
         }
         const bool miss = a0 == kUnset || (E2 && a1 == kUnset) || (two && (c0 == kUnset || (E2 && c1 == kUnset)));
         if (__ballot(miss) == 0) break;
-        if (++spins > kSpinLimit) {
+        if (++spins > spin_limit) {
             if (lane == 0) status[kStSpinTimeout] = 1;
             break;
         }
@@ -146,7 +145,7 @@ template <bool BWD, typename T, int BS>
 __device__ __forceinline__ void trsv_body(const T *__restrict__ L, int64_t ld,
                                           const T *__restrict__ dinv,
                                           const double *__restrict__ rhs, double *__restrict__ x,
-                                          int *counters, int nblk, int *status)
+                                          int *counters, int nblk, int *status, long spin_limit)
 {
     constexpr int RG = BS / 4;      // row groups of a tile (4 rows each)
     constexpr int CG = 256 / RG;    // column groups
@@ -222,7 +221,7 @@ __device__ __forceinline__ void trsv_body(const T *__restrict__ L, int64_t ld,
     // steps st and st + 1 (if any): wave 0 waits for both solution blocks (a
     // band writes its two blocks moments apart) and copies them to LDS
     auto consume2 = [&](int st, bool two) {
-        if (tid < 64) wait_blocks<BS>(x, jof(st), two ? jof(st + 1) : 0, two, xs, status);
+        if (tid < 64) wait_blocks<BS>(x, jof(st), two ? jof(st + 1) : 0, two, xs, status, spin_limit);
         __syncthreads();
         gemv(ta0, xs[0], acc0);
         gemv(ta1, xs[0], acc1);
@@ -325,9 +324,9 @@ template <bool BWD, typename T, int BS>
 __global__ void __launch_bounds__(256)
 k_trsv(const T *__restrict__ L, int64_t ld, const T *__restrict__ dinv,
        const double *__restrict__ rhs, double *__restrict__ x, int *counters, int nblk,
-       int *status)
+       int *status, long spin_limit)
 {
-    trsv_body<BWD, T, BS>(L, ld, dinv, rhs, x, counters, nblk, status);
+    trsv_body<BWD, T, BS>(L, ld, dinv, rhs, x, counters, nblk, status, spin_limit);
 }
 
 // One triangular solve of the FP32 factor with one 128-row block per
@@ -344,7 +343,8 @@ k_trsv(const T *__restrict__ L, int64_t ld, const T *__restrict__ dinv,
 template <bool BWD>
 __device__ __forceinline__ void trsv1_body(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv,
                                            const float *__restrict__ Qb, const double *__restrict__ rhs,
-                                           double *__restrict__ x, int *counters, int nblk, int *status)
+                                           double *__restrict__ x, int *counters, int nblk, int *status,
+                                           long spin_limit)
 {
     constexpr int BS = 128;
     __shared__ float Dl[BS * (BS + 1)];  // D_b, row-major, padded stride
@@ -400,7 +400,7 @@ __device__ __forceinline__ void trsv1_body(const float *__restrict__ L, int64_t 
     if (nfar > 1) load(tile(jof(1)), ld, tb);
     for (int st = 0; st < nfar; st += 2) {
         const bool two = st + 1 < nfar;
-        if (tid < 64) wait_blocks<BS>(x, jof(st), two ? jof(st + 1) : 0, two, xs, status);
+        if (tid < 64) wait_blocks<BS>(x, jof(st), two ? jof(st + 1) : 0, two, xs, status, spin_limit);
         __syncthreads();
         gemv(ta, xs[0], acc);
         if (two) gemv(tb, xs[1], acc);
@@ -436,7 +436,7 @@ __device__ __forceinline__ void trsv1_body(const float *__restrict__ L, int64_t 
     }
     // the predecessor's block: x_b = y - Q_b x_n
     __syncthreads();  // part is rewritten below
-    if (tid < 64) wait_blocks<BS>(x, jof(nsteps - 1), 0, false, xs, status);
+    if (tid < 64) wait_blocks<BS>(x, jof(nsteps - 1), 0, false, xs, status, spin_limit);
     __syncthreads();
     double aq[4] = {0.0, 0.0, 0.0, 0.0};
     gemv(tq, xs[0], aq);
@@ -454,9 +454,10 @@ __device__ __forceinline__ void trsv1_body(const float *__restrict__ L, int64_t 
 template <bool BWD>
 __global__ void __launch_bounds__(256)
 k_trsv1(const float *__restrict__ L, int64_t ld, const float *__restrict__ dinv, const float *__restrict__ Qb,
-        const double *__restrict__ rhs, double *__restrict__ x, int *counters, int nblk, int *status)
+        const double *__restrict__ rhs, double *__restrict__ x, int *counters, int nblk, int *status,
+        long spin_limit)
 {
-    trsv1_body<BWD>(L, ld, dinv, Qb, rhs, x, counters, nblk, status);
+    trsv1_body<BWD>(L, ld, dinv, Qb, rhs, x, counters, nblk, status, spin_limit);
 }
 
 // The near tiles of k_trsv1 for every 128-block of the FP32 factor, both
@@ -518,7 +519,8 @@ k_trsv_b(const BProb *__restrict__ P, BWork w, int rhs_slot, int x_slot)
     const BProb &q = P[w.plist[i]];
     if (!q.active) return;
     trsv_body<BWD, float, 128>(q.A, q.npad, q.dinv, q.vec + (int64_t)rhs_slot * q.npad,
-                               q.vec + (int64_t)x_slot * q.npad, q.ints + 64, (int)(q.npad / 128), q.ints);
+                               q.vec + (int64_t)x_slot * q.npad, q.ints + 64, (int)(q.npad / 128), q.ints,
+                               kSpinLimitDefault);
 }
 
 // Tickets to zero and the vector in `slot` unset, one workgroup per problem
@@ -560,22 +562,23 @@ void launch_prec_apply_b(hipStream_t s, const BProb *P, const BWork &w, int rhs_
 
 template <typename T, int BS>
 void prec_apply(hipStream_t s, const T *L, int64_t npad, const T *dinv, const double *r, double *y_tmp, double *z,
-                int *counters, int *status)
+                int *counters, int *status, long spin_limit)
 {
     const int nblk = (int)(npad / BS);  // even: npad is a multiple of 256
     const unsigned gu = (unsigned)std::min<int64_t>((npad + 255) / 256, 1024);
     launch_fill_ints(s, counters, kCounterInts, 0);
     hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, y_tmp, npad);
     hipLaunchKernelGGL((k_trsv<false, T, BS>), dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, r, y_tmp, counters,
-                       nblk, status);
+                       nblk, status, spin_limit);
     // z may be the caller's r: unset it only once the forward solve has read r
     hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, z, npad);
     hipLaunchKernelGGL((k_trsv<true, T, BS>), dim3(nblk / 2), dim3(256), 0, s, L, npad, dinv, y_tmp, z, counters,
-                       nblk, status);
+                       nblk, status, spin_limit);
 }
 
 void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float *dinv,
-                       const double *r, double *y_tmp, double *z, int *counters, int *status, const float *Q)
+                       const double *r, double *y_tmp, double *z, int *counters, int *status, const float *Q,
+                       long spin_limit)
 {
     const int nblk = (int)(npad / 128);
     const float *Qb = Q + (int64_t)nblk * 128 * 128;  // the backward direction's tiles
@@ -583,11 +586,11 @@ void launch_prec_apply(hipStream_t s, const float *L, int64_t npad, const float 
     launch_fill_ints(s, counters, kCounterInts, 0);
     hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, y_tmp, npad);
     hipLaunchKernelGGL(k_trsv1<false>, dim3(nblk), dim3(256), 0, s, L, npad, dinv, Q, r, y_tmp, counters, nblk,
-                       status);
+                       status, spin_limit);
     // z may be the caller's r: unset it only once the forward solve has read r
     hipLaunchKernelGGL(k_unset, dim3(gu), dim3(256), 0, s, z, npad);
     hipLaunchKernelGGL(k_trsv1<true>, dim3(nblk), dim3(256), 0, s, L, npad, dinv, Qb, y_tmp, z, counters, nblk,
-                       status);
+                       status, spin_limit);
 }
 
 size_t near_q_floats(int64_t npad) { return (size_t)npad * 256; }
@@ -600,9 +603,10 @@ void launch_near_q(hipStream_t s, const float *A, int64_t npad, const float *din
 }
 
 void launch_chol64_solve(hipStream_t s, const double *L, int64_t npad, const double *dinv, const double *r,
-                         double *y_tmp, double *z, int *counters, int *status)
+                         double *y_tmp, double *z, int *counters, int *status,
+                        long spin_limit)
 {
-    prec_apply<double, 64>(s, L, npad, dinv, r, y_tmp, z, counters, status);
+    prec_apply<double, 64>(s, L, npad, dinv, r, y_tmp, z, counters, status, spin_limit);
 }
 
 }  // namespace mag

@@ -136,3 +136,34 @@ def test_adjoint_high_dimension(mag, m):
     err = np.abs(Xd.grad.cpu().numpy() - dX_ref).max() / np.abs(dX_ref).max()
     print(f"m={m}: dt err {abs(td.grad.item() - dt_ref) / abs(dt_ref):.2e} dX err {err:.2e}")
     assert err <= 1e-10
+
+
+def test_spin_limit_forces_the_substitution_timeout(mag):
+    # The sync-free triangular solves give up after a bounded number of polls and
+    # report MAG_EINTERNAL.  A limit of one poll forces that path from the host:
+    # every kernel still finishes (a timed-out workgroup carries on with what it
+    # read), the calls fail cleanly, and the context works again at the default.
+    n, t = 3000, 2.0
+    X = W.gaussian(n, 3, seed=5)
+    Xd = dev(X)
+    ctx = mag.Context()
+    try:
+        L, dinv, bd = mag.factor32(Xd, t, ctx=ctx)
+        assert bd == 0
+        r = dev(np.random.default_rng(3).standard_normal(n))
+        z_ref = mag.prec_apply(L, dinv, n, r, ctx=ctx).cpu().numpy()
+        ctx.set_spin_limit(1)
+        for call in (lambda: mag.prec_apply(L, dinv, n, r, ctx=ctx),
+                     lambda: mag.weighting(Xd, t, ctx=ctx),
+                     lambda: mag.weighting(Xd, t, ctx=ctx, solver="fp64_chol")):
+            with pytest.raises(mag.MagError) as e:
+                call()
+            assert e.value.code == -6  # MAG_EINTERNAL
+        ctx.set_spin_limit(0)
+        assert np.array_equal(mag.prec_apply(L, dinv, n, r, ctx=ctx).cpu().numpy(), z_ref)
+        w = mag.weighting(Xd, t, ctx=ctx).w.cpu().numpy()
+        assert np.abs(oracle.residual(X, t, w)).max() <= 1e-12
+        with pytest.raises(mag.MagError):
+            ctx.set_spin_limit(-1)
+    finally:
+        ctx.close()
