@@ -12,8 +12,11 @@
 // and, panels taken in pairs, 4. the trailing update A22 -= L21 L21^T of both
 // panels at once (K = 2 nb, lower tiles only), after a strip update of the
 // second panel's columns by the first.  A deep K in step 4 amortises the load
-// and store of each C tile over more MFMA work.  The inverses of the diagonal
-// 128-blocks are kept (dinv) for the preconditioner's triangular solves.
+// and store of each C tile over more MFMA work; steps 2, 3 and the strip run
+// on 64-row tiles (twice the workgroups of 128-row ones, which keeps more CUs
+// busy in the late panels, where a 128-row tiling leaves most of them idle).
+// The inverses of the diagonal 128-blocks are kept (dinv) for the
+// preconditioner's triangular solves.
 #include "internal.hpp"
 
 #include <algorithm>
