@@ -138,6 +138,21 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
     if (tid == 0) bad = 0;
     __syncthreads();
 
+    // columns c0 .. c0 + 31 of the factored block to A: L on and below the
+    // diagonal, L^T above it (the mirror of an entry of an earlier, final column
+    // or of the diagonal 32-block); threads t = 0 .. nt-1 of the caller
+    auto write_cols = [&](int c0, int t, int nt) {
+        for (int e = t; e < 32 * (NB / 4); e += nt) {
+            const int c = c0 + (e >> 5), r4 = (e & 31) * 4;
+            float4 v;
+            v.x = (r4 + 0 >= c) ? S[c * LDS_LD + r4 + 0] : S[(r4 + 0) * LDS_LD + c];
+            v.y = (r4 + 1 >= c) ? S[c * LDS_LD + r4 + 1] : S[(r4 + 1) * LDS_LD + c];
+            v.z = (r4 + 2 >= c) ? S[c * LDS_LD + r4 + 2] : S[(r4 + 2) * LDS_LD + c];
+            v.w = (r4 + 3 >= c) ? S[c * LDS_LD + r4 + 3] : S[(r4 + 3) * LDS_LD + c];
+            *reinterpret_cast<float4 *>(Ablk + (int64_t)c * ld + r4) = v;
+        }
+    };
+
     for (int J = 0; J < 4; ++J) {
         const int j0 = 32 * J;
         // 1. factor the diagonal 32 x 32 block in wave 0 and invert it in the same
@@ -152,9 +167,14 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
         //    and g_k = -m_k / sqrt(A(c, c)) below.  Column c of L stays in the
         //    lanes that computed it (register r_c) until the sweep ends.
         if (wave != 0) {
-            // the previous step's products that this factor does not need (all but
+            // block column J - 1 of L is final (its panel solve ran in step 2 of
+            // J - 1): out to A now rather than in the closing write-back; then the
+            // previous step's products that this factor does not need (all but
             // the trailing block (J, J), item 0), on waves 1..3 beside the factor
-            if (J > 0) step_products(S, V, J - 1, wave, 3, lane);
+            if (J > 0) {
+                write_cols(32 * (J - 1), tid - 64, 192);
+                step_products(S, V, J - 1, wave, 3, lane);
+            }
         } else {
             const int b = lane & 31, h = lane >> 5;
             v16f accA, accY;
@@ -247,22 +267,18 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
         }
     }
 
-    // write L back (lower triangle including the diagonal) and L^T above it, and the
+    // the last block column of L (the others went out during the steps) and the
     // inverse (zero above the diagonal)
+    write_cols(96, tid, 256);
 #pragma unroll 4
     for (int i = 0; i < 16; ++i) {
         const int e4 = tid + 256 * i;
         const int c = e4 >> 5, r4 = (e4 & 31) * 4;
-        float4 v, w;
-        v.x = (r4 + 0 >= c) ? S[c * LDS_LD + r4 + 0] : S[(r4 + 0) * LDS_LD + c];
-        v.y = (r4 + 1 >= c) ? S[c * LDS_LD + r4 + 1] : S[(r4 + 1) * LDS_LD + c];
-        v.z = (r4 + 2 >= c) ? S[c * LDS_LD + r4 + 2] : S[(r4 + 2) * LDS_LD + c];
-        v.w = (r4 + 3 >= c) ? S[c * LDS_LD + r4 + 3] : S[(r4 + 3) * LDS_LD + c];
+        float4 w;
         w.x = (r4 + 0 >= c) ? V[c * LDS_LD + r4 + 0] : 0.0f;
         w.y = (r4 + 1 >= c) ? V[c * LDS_LD + r4 + 1] : 0.0f;
         w.z = (r4 + 2 >= c) ? V[c * LDS_LD + r4 + 2] : 0.0f;
         w.w = (r4 + 3 >= c) ? V[c * LDS_LD + r4 + 3] : 0.0f;
-        *reinterpret_cast<float4 *>(Ablk + (int64_t)c * ld + r4) = v;
         *reinterpret_cast<float4 *>(Linv + c * NB + r4) = w;
     }
     if (tid == 0 && bad != 0) atomicCAS(&status[kStBreakdown], 0, bad);
