@@ -153,6 +153,20 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
         }
     };
 
+    // rows r0 .. r0 + 31 of the inverse to Linv (column-major, zero above the
+    // diagonal)
+    auto write_inv_rows = [&](int r0, int t, int nt) {
+        for (int e = t; e < NB * 8; e += nt) {
+            const int c = e >> 3, r4 = r0 + (e & 7) * 4;
+            float4 w;
+            w.x = (r4 + 0 >= c) ? V[c * LDS_LD + r4 + 0] : 0.0f;
+            w.y = (r4 + 1 >= c) ? V[c * LDS_LD + r4 + 1] : 0.0f;
+            w.z = (r4 + 2 >= c) ? V[c * LDS_LD + r4 + 2] : 0.0f;
+            w.w = (r4 + 3 >= c) ? V[c * LDS_LD + r4 + 3] : 0.0f;
+            *reinterpret_cast<float4 *>(Linv + c * NB + r4) = w;
+        }
+    };
+
     for (int J = 0; J < 4; ++J) {
         const int j0 = 32 * J;
         // 1. factor the diagonal 32 x 32 block in wave 0 and invert it in the same
@@ -167,12 +181,14 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
         //    and g_k = -m_k / sqrt(A(c, c)) below.  Column c of L stays in the
         //    lanes that computed it (register r_c) until the sweep ends.
         if (wave != 0) {
-            // block column J - 1 of L is final (its panel solve ran in step 2 of
-            // J - 1): out to A now rather than in the closing write-back; then the
-            // previous step's products that this factor does not need (all but
-            // the trailing block (J, J), item 0), on waves 1..3 beside the factor
+            // block column J - 1 of L and block row J - 1 of the inverse are final
+            // (step 2 of J - 1 was their last change): out to A and Linv now rather
+            // than in the closing write-back; then the previous step's products that
+            // this factor does not need (all but the trailing block (J, J), item 0),
+            // on waves 1..3 beside the factor
             if (J > 0) {
                 write_cols(32 * (J - 1), tid - 64, 192);
+                write_inv_rows(32 * (J - 1), tid - 64, 192);
                 step_products(S, V, J - 1, wave, 3, lane);
             }
         } else {
@@ -267,20 +283,10 @@ __device__ __forceinline__ void potrf128_body(float *__restrict__ A, int64_t ld,
         }
     }
 
-    // the last block column of L (the others went out during the steps) and the
-    // inverse (zero above the diagonal)
+    // the last block column of L and block row of the inverse (the others went
+    // out during the steps)
     write_cols(96, tid, 256);
-#pragma unroll 4
-    for (int i = 0; i < 16; ++i) {
-        const int e4 = tid + 256 * i;
-        const int c = e4 >> 5, r4 = (e4 & 31) * 4;
-        float4 w;
-        w.x = (r4 + 0 >= c) ? V[c * LDS_LD + r4 + 0] : 0.0f;
-        w.y = (r4 + 1 >= c) ? V[c * LDS_LD + r4 + 1] : 0.0f;
-        w.z = (r4 + 2 >= c) ? V[c * LDS_LD + r4 + 2] : 0.0f;
-        w.w = (r4 + 3 >= c) ? V[c * LDS_LD + r4 + 3] : 0.0f;
-        *reinterpret_cast<float4 *>(Linv + c * NB + r4) = w;
-    }
+    write_inv_rows(96, tid, 256);
     if (tid == 0 && bad != 0) atomicCAS(&status[kStBreakdown], 0, bad);
 }
 
